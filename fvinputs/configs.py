@@ -1,0 +1,307 @@
+"""Synthetic workloads: materials, geometry and initial primitive fields.
+
+The five workloads follow the inert problems of the paper's validation
+section (plate-impact spallation, expanding ring, expanding shell), built on a
+copper-like solid whose constants are stated below.  Where the workloads leave
+a detail open the reading is the one recorded in the design notes (free
+surface ends for the plate impacts, gas at atmospheric pressure around rings
+and shells, gate pressure -1.5 GPa for plate impacts and 0 otherwise).
+"""
+from dataclasses import dataclass, field
+import numpy as np
+
+from .fields import (uniform_field, gaussian_field, lognormal_field,
+                     inclusion_field)
+
+# Base seed: workload k uses CONFIG_SEEDS[k] for its phi0 field and draws.
+CONFIG_SEEDS = {k: 221004037 + k for k in range(1, 6)}
+ENSEMBLE_MEMBER_SEED0 = 4000
+
+# Copper-like solid: rho0 8930 kg/m^3, bulk sound speed 3940 m/s
+# (K0 = rho0 * 3940^2), shear modulus 45 GPa, yield 90 MPa.  Romenskii
+# exponents and Grueneisen constant from the CuBe row of the paper's
+# Romenskii table; Bonora constants from its CuBe damage row with the
+# critical damage 0.9; hardening exponent from its Johnson-Cook CuBe row.
+COPPER = dict(
+    kind="solid", rho0=8930.0, K0=8930.0 * 3940.0 ** 2, alpha=1.0, G0=45.0e9,
+    beta=3.0, Gamma0=2.0, yield_stress=90.0e6, D_crit=0.9, D0=0.0,
+    eps_th=0.08, eps_c=0.16, bonora_alpha=0.631, n_hard=0.31, p_gate=0.0,
+)
+# Low-density ideal gas, gamma = 1.4 (Grueneisen constant gamma - 1).
+GAS = dict(
+    kind="gas", rho0=1.0, K0=0.0, alpha=1.0, G0=0.0, beta=0.0, Gamma0=0.4,
+    yield_stress=0.0, D_crit=1.0, D0=0.0, eps_th=0.0, eps_c=0.0,
+    bonora_alpha=1.0, n_hard=1.0, p_gate=0.0,
+)
+P_ATM = 1.0e5
+
+
+def vbar_components(dim):
+    """Stored (i, j) components of the unimodular stretch, row-major:
+    1D uniaxial strain keeps Vbar diagonal; 2D plane strain keeps the xy block
+    and the zz entry; 3D stores all nine."""
+    if dim == 1:
+        return [(0, 0), (1, 1), (2, 2)]
+    if dim == 2:
+        return [(0, 0), (0, 1), (1, 0), (1, 1), (2, 2)]
+    return [(i, j) for i in range(3) for j in range(3)]
+
+
+def prim_field_names(dim, mats):
+    n = len(mats)
+    solids = [l for l, m in enumerate(mats) if m["kind"] == "solid"]
+    names = [f"phi{l}" for l in range(n)] + [f"rho{l}" for l in range(n)]
+    for l in solids:
+        names += [f"eps{l}", f"D{l}"]
+    names += ["u", "v", "w"][:dim] + ["p"]
+    names += [f"V{i + 1}{j + 1}" for i, j in vbar_components(dim)]
+    names += ["X", "Y", "Z"][:dim]
+    return names
+
+
+@dataclass
+class Case:
+    name: str
+    dim: int
+    n: tuple            # (nx, ny, nz)
+    lo: tuple           # (x, y, z) lower corner; unused dims span [0, 1]
+    hi: tuple
+    bc: tuple           # ((xlo, xhi), (ylo, yhi), (zlo, zhi)) names
+    mats: list
+    prim: np.ndarray    # (S, nz, ny, nx)
+    phi0: np.ndarray    # (nz, ny, nx)
+    t_end: float
+    cfl: float = 0.6
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def dx(self):
+        return tuple((self.hi[k] - self.lo[k]) / self.n[k] for k in range(3))
+
+    @property
+    def n_cells(self):
+        return int(self.n[0] * self.n[1] * self.n[2])
+
+
+def _centres(n, lo, hi, sub=1):
+    """Cell-centre (sub=1) or sub-sample coordinates per axis."""
+    out = []
+    for k in range(3):
+        d = (hi[k] - lo[k]) / n[k]
+        if sub == 1:
+            out.append(lo[k] + (np.arange(n[k]) + 0.5) * d)
+        else:
+            off = (np.arange(sub) + 0.5) / sub
+            out.append(lo[k] + (np.arange(n[k])[:, None] + off[None, :]) * d)
+    return out
+
+
+def _subsample(dim, n, lo, hi, indicator, velocity, rho_in, rho_out, sub=4):
+    """Volume fraction of the solid region and the mass-weighted velocity of
+    each cell from sub^dim sub-samples.  `indicator(x, y, z)` -> bool array,
+    `velocity(x, y, z)` -> list of d arrays (solid velocity)."""
+    nx, ny, nz = n
+    frac = np.zeros((nz, ny, nx))
+    mom = np.zeros((dim, nz, ny, nx))
+    mass = np.zeros((nz, ny, nx))
+    subs = [sub if k < dim else 1 for k in range(3)]
+    d = [(hi[k] - lo[k]) / n[k] for k in range(3)]
+    cnt = float(np.prod(subs))
+    for sz in range(subs[2]):
+        zc = lo[2] + (np.arange(nz) + (sz + 0.5) / subs[2]) * d[2]
+        for sy in range(subs[1]):
+            yc = lo[1] + (np.arange(ny) + (sy + 0.5) / subs[1]) * d[1]
+            for sx in range(subs[0]):
+                xc = lo[0] + (np.arange(nx) + (sx + 0.5) / subs[0]) * d[0]
+                Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+                ins = indicator(X, Y, Z)
+                frac += ins
+                rho = np.where(ins, rho_in, rho_out)
+                mass += rho
+                vel = velocity(X, Y, Z)
+                for k in range(dim):
+                    mom[k] += np.where(ins, rho * vel[k], 0.0)
+    frac /= cnt
+    u = mom / mass[None]
+    return frac, u
+
+
+def _assemble(dim, mats, frac_solid, u, p, n, lo, hi):
+    """Primitive array (S, nz, ny, nx) from the solid volume fraction, the
+    velocity and a uniform pressure.  Material 0 is the solid; if a second
+    material is present it fills the remainder."""
+    nx, ny, nz = n
+    shp = (nz, ny, nx)
+    nm = len(mats)
+    rows = []
+    if nm == 1:
+        rows.append(frac_solid)
+    else:
+        rows += [frac_solid, 1.0 - frac_solid]
+    rows += [np.full(shp, m["rho0"]) for m in mats]
+    for m in mats:
+        if m["kind"] == "solid":
+            rows += [np.zeros(shp), np.zeros(shp)]
+    rows += [u[k] for k in range(dim)]
+    rows.append(np.full(shp, p))
+    for (i, j) in vbar_components(dim):
+        rows.append(np.full(shp, 1.0 if i == j else 0.0))
+    cx, cy, cz = _centres(n, lo, hi)
+    Z, Y, X = np.meshgrid(cz, cy, cx, indexing="ij")
+    rows += [X, Y, Z][:dim]
+    return np.stack(rows).astype(np.float64)
+
+
+def config_member_draws(n_members=64):
+    """Ensemble draws: grid edge in {256, 384, 512, 768} and ring speed in
+    U(100, 250) m/s per member."""
+    rng = np.random.Generator(np.random.PCG64(CONFIG_SEEDS[4]))
+    sizes = rng.choice(np.array([256, 384, 512, 768]), size=n_members)
+    vels = rng.uniform(100.0, 250.0, size=n_members)
+    return [int(s) for s in sizes], [float(v) for v in vels]
+
+
+def _copper(p_gate):
+    m = dict(COPPER)
+    m["p_gate"] = p_gate
+    return m
+
+
+def _ring(name, nedge, v_out, phi0_seed, t_end, with_phi0=True):
+    lo = (-0.03, -0.03, 0.0)
+    hi = (0.03, 0.03, 1.0)
+    n = (nedge, nedge, 1)
+    r_in, r_out = 0.025, 0.0265
+    mats = [_copper(0.0), dict(GAS)]
+
+    def ind(X, Y, Z):
+        r = np.sqrt(X * X + Y * Y)
+        return (r >= r_in) & (r <= r_out)
+
+    def vel(X, Y, Z):
+        # u = v_out (r / r_out) rhat = v_out / r_out * (x, y)
+        s = v_out / r_out
+        return [s * X, s * Y]
+
+    frac, u = _subsample(2, n, lo, hi, ind, vel, mats[0]["rho0"],
+                         mats[1]["rho0"])
+    prim = _assemble(2, mats, frac, u, P_ATM, n, lo, hi)
+    dxs = (1.0, (hi[1] - lo[1]) / n[1], (hi[0] - lo[0]) / n[0])
+    phi0 = (gaussian_field((1, nedge, nedge), dxs, 0.2e-3, 0.05, phi0_seed)
+            if with_phi0 else np.ones((1, nedge, nedge)))
+    bc = (("transmissive",) * 2, ("transmissive",) * 2, ("transmissive",) * 2)
+    return Case(name, 2, n, lo, hi, bc, mats, prim, phi0, t_end,
+                meta=dict(v_out=v_out))
+
+
+def make_case(config, n=None, member=None, t_end=None):
+    """Build workload `config` (1..5).  `n` overrides the grid edge (a scaled
+    copy of the same geometry); `member` selects an ensemble member of
+    workload 4."""
+    if config == 1:
+        nx = n or 400
+        lo, hi = (0.0, 0.0, 0.0), (0.01, 1.0, 1.0)
+        mats = [_copper(-1.5e9)]
+        grid = (nx, 1, 1)
+
+        def ind(X, Y, Z):
+            return np.ones_like(X, dtype=bool)
+
+        def vel(X, Y, Z):
+            return [np.where(X < 0.002, 200.0, 0.0)]
+
+        frac, u = _subsample(1, grid, lo, hi, ind, vel, mats[0]["rho0"], 1.0)
+        prim = _assemble(1, mats, frac, u, P_ATM, grid, lo, hi)
+        phi0 = uniform_field((1, 1, nx), 0.05, CONFIG_SEEDS[1])
+        bc = (("free", "free"), ("transmissive",) * 2, ("transmissive",) * 2)
+        return Case("spall1d", 1, grid, lo, hi, bc, mats, prim, phi0,
+                    t_end if t_end is not None else 2.0e-6)
+    if config == 2:
+        c = _ring("ring2d", n or 1024, 150.0, CONFIG_SEEDS[2],
+                  t_end if t_end is not None else 40.0e-6)
+        return c
+    if config == 3:
+        ne = n or 256
+        lo, hi = (-0.02, -0.02, -0.02), (0.02, 0.02, 0.02)
+        grid = (ne, ne, ne)
+        mats = [_copper(0.0), dict(GAS)]
+
+        def ind(X, Y, Z):
+            r = np.sqrt(X * X + Y * Y)
+            return (r >= 0.015) & (r <= 0.016) & (np.abs(Z) <= 0.015)
+
+        def vel(X, Y, Z):
+            r = np.sqrt(X * X + Y * Y)
+            r = np.where(r > 0, r, 1.0)
+            return [200.0 * X / r, 200.0 * Y / r, np.zeros_like(X)]
+
+        frac, u = _subsample(3, grid, lo, hi, ind, vel, mats[0]["rho0"],
+                             mats[1]["rho0"])
+        prim = _assemble(3, mats, frac, u, P_ATM, grid, lo, hi)
+        d = (hi[0] - lo[0]) / ne
+        phi0 = lognormal_field((ne, ne, ne), (d, d, d), 0.3e-3, 0.05,
+                               CONFIG_SEEDS[3])
+        bc = (("transmissive",) * 2,) * 3
+        return Case("shell3d", 3, grid, lo, hi, bc, mats, prim, phi0,
+                    t_end if t_end is not None else 18.0e-6)
+    if config == 4:
+        sizes, vels = config_member_draws()
+        m = 0 if member is None else member
+        ne = n or sizes[m]
+        c = _ring(f"ensemble_m{m}", ne, vels[m], ENSEMBLE_MEMBER_SEED0 + m,
+                  t_end if t_end is not None else 40.0e-6)
+        c.meta["member"] = m
+        return c
+    if config == 5:
+        ne = n or 512
+        lo, hi = (0.0, 0.0, 0.0), (0.02, 0.02, 0.02)
+        grid = (ne, ne, ne)
+        mats = [_copper(-1.5e9)]
+
+        def ind(X, Y, Z):
+            return np.ones_like(X, dtype=bool)
+
+        def vel(X, Y, Z):
+            return [np.where(X < 0.004, 400.0, 0.0)]
+
+        # The plate is uniform in y and z: sub-sample the x profile only.
+        frac1, u1 = _subsample(1, (ne, 1, 1), lo, (hi[0], 1.0, 1.0), ind, vel,
+                               mats[0]["rho0"], 1.0)
+        frac = np.broadcast_to(frac1, (ne, ne, ne))
+        u = np.zeros((3, ne, ne, ne))
+        u[0] = u1[0]
+        prim = _assemble(3, mats, frac, u, P_ATM, grid, lo, hi)
+        phi0 = inclusion_field(grid, lo, hi, (0.004, 0.0, 0.0),
+                               (0.02, 0.02, 0.02), 1000, 0.1e-3, 0.3e-3, 0.7,
+                               CONFIG_SEEDS[5])
+        bc = (("free", "free"), ("transmissive",) * 2, ("transmissive",) * 2)
+        return Case("impact3d", 3, grid, lo, hi, bc, mats, prim, phi0,
+                    t_end if t_end is not None else 3.0e-6)
+    raise ValueError(f"unknown workload {config}")
+
+
+def uniform_case(dim, n, mats, phi, rho, u, p, bc="periodic", vbar=None,
+                 phi0=1.0, lo=None, hi=None, t_end=1.0):
+    """A spatially uniform primitive state (used for invariance checks)."""
+    nx, ny, nz = n
+    lo = lo or (0.0, 0.0, 0.0)
+    hi = hi or tuple(1e-3 * n[k] if k < dim else 1.0 for k in range(3))
+    shp = (nz, ny, nx)
+    solids = [l for l, m in enumerate(mats) if m["kind"] == "solid"]
+    rows = [np.full(shp, v) for v in phi] + [np.full(shp, v) for v in rho]
+    for _ in solids:
+        rows += [np.zeros(shp), np.zeros(shp)]
+    rows += [np.full(shp, u[k]) for k in range(dim)]
+    rows.append(np.full(shp, p))
+    comps = vbar_components(dim)
+    for (i, j) in comps:
+        val = (1.0 if i == j else 0.0) if vbar is None else vbar[i][j]
+        rows.append(np.full(shp, val))
+    cx, cy, cz = _centres(n, lo, hi)
+    Z, Y, X = np.meshgrid(cz, cy, cx, indexing="ij")
+    rows += [X, Y, Z][:dim]
+    prim = np.stack(rows).astype(np.float64)
+    bcs = tuple((bc, bc) if k < dim else ("transmissive", "transmissive")
+                for k in range(3))
+    return Case("uniform", dim, tuple(n), lo, hi, bcs, mats, prim,
+                np.full(shp, float(phi0)), t_end)

@@ -1,0 +1,177 @@
+"""Mixture closures and conserved <-> primitive conversion -- oracle, FP64.
+
+The mixture rules are deferred by the paper to earlier work (Section 2.3,
+last paragraph); the reading used here is the Allaire-type closure under the
+paper's mechanical and thermal equilibrium assumption (Section 2.1):
+
+  * pressure: rho e = sum_l phi_l rho_l e_l(rho_l, p) solved for the common
+    p with each e_l in Mie-Grueneisen form, i.e.
+      p = [rho e - sum phi_l rho_l e_ref,l + sum phi_l p_ref,l / Gamma_l]
+          / sum (phi_l / Gamma_l)
+  * stress: the void carries none, so the mixture stress is the
+    volume-weighted material stress
+      sigma = -(1 - nu) p I + 2 G_mix dev(H),  G_mix = sum phi_l G_l
+    (this makes the mixture work rate equal sum phi_l p_l div u, the
+    energy-consistent choice; with no void it is -p I + 2 G dev H)
+  * sound speed: the frozen (Allaire) mixture bulk speed scaled by (1 - nu),
+    plus the shear contribution, c^2 = c_b^2 + (4/3) G_mix / rho.
+Parity of the mixture rule itself is unpinned against the paper (it is not
+printed there); the single-material limit is pinned.
+"""
+import numpy as np
+
+from .closures import ref_terms, gruneisen
+from .kinematics import full_vbar, hencky, J2_of
+
+C_MIN2 = 1.0e-6       # floor on c^2 [m^2/s^2]
+
+
+class Options:
+    def __init__(self, phi_floor=1.0e-8, cfl=0.6, weno_eps=1.0e-6):
+        self.phi_floor = phi_floor
+        self.cfl = cfl
+        self.weno_eps = weno_eps
+
+
+def material_terms(rho_l, D_l, J2, mats):
+    """Per-material (rho e_ref, p_ref, rho dp_ref/drho, G) lists."""
+    out = []
+    for l, m in enumerate(mats):
+        D = D_l[l] if l in D_l else np.zeros_like(J2)
+        out.append(ref_terms(rho_l[l], J2, D, m))
+    return out
+
+
+def pressure_from_energy(phi, terms, rho_e, mats):
+    xi = sum(phi[l] / gruneisen(m) for l, m in enumerate(mats))
+    num = rho_e.copy()
+    for l, m in enumerate(mats):
+        rho_eref, pref, _, _ = terms[l]
+        num = num - phi[l] * rho_eref + phi[l] * pref / gruneisen(m)
+    return num / xi
+
+
+def energy_from_pressure(phi, terms, p, mats):
+    xi = sum(phi[l] / gruneisen(m) for l, m in enumerate(mats))
+    rho_e = xi * p
+    for l, m in enumerate(mats):
+        rho_eref, pref, _, _ = terms[l]
+        rho_e = rho_e + phi[l] * rho_eref - phi[l] * pref / gruneisen(m)
+    return rho_e
+
+
+def solid_fraction(phi):
+    """1 - nu with the void fraction nu = 1 - sum phi clamped to [0, 1]."""
+    s = np.sum(phi, axis=0)
+    return np.clip(s, 0.0, 1.0)
+
+
+def sound_speed(phi, rho_l, terms, p, rho, mats):
+    """Longitudinal mixture sound speed (see module docstring)."""
+    xi = sum(phi[l] / gruneisen(m) for l, m in enumerate(mats))
+    acc = np.zeros_like(p)
+    Gmix = np.zeros_like(p)
+    for l, m in enumerate(mats):
+        _, pref, rho_dpref, G = terms[l]
+        g = gruneisen(m)
+        acc = acc + phi[l] / g * (rho_dpref + (g + 1.0) * (p - pref))
+        Gmix = Gmix + phi[l] * G
+    # acc = sum phi_l xi_l rho_l c_l^2 (with rho_l c_l^2 = rho_l p_ref' +
+    # (Gamma_l + 1)(p - p_ref,l)); bulk c^2 = (1-nu) acc / (xi rho)
+    cb2 = solid_fraction(phi) * acc / (xi * rho)
+    c2 = np.maximum(cb2, 0.0) + (4.0 / 3.0) * Gmix / rho
+    return np.sqrt(np.maximum(c2, C_MIN2)), Gmix
+
+
+def stress(phi, p, Gmix, H):
+    s = 2.0 * Gmix[None, None] * H
+    f = solid_fraction(phi)
+    for i in range(3):
+        s[i, i] = s[i, i] - f * p
+    return s
+
+
+def prim_to_cons(W, layout, opts):
+    """Conserved state from the generator's primitive array (same field
+    order, rho_l in place of phi_l rho_l, eps/D in place of the history
+    densities, velocity, pressure in place of energy).  Volume fractions are
+    clamped to [phi_floor, 1]."""
+    L = layout
+    dim, mats = L.dim, L.mats
+    shape = W.shape[1:]
+    phi = np.clip(W[L.phi], opts.phi_floor, 1.0)
+    rho_l = W[L.mass]
+    D_l = {l: W[L.dmg[l]] for l in L.solids}
+    V = full_vbar(W[L.vbar], L.vcomps, shape)
+    H, _, _ = hencky(V)
+    J2 = J2_of(H)
+    terms = material_terms(rho_l, D_l, J2, mats)
+    p = W[L.energy]                       # pressure sits in the energy slot
+    rho_e = energy_from_pressure(phi, terms, p, mats)
+    rho = np.sum(phi * rho_l, axis=0)
+    u = W[L.mom]
+    U = np.zeros_like(W)
+    U[L.phi] = phi
+    U[L.mass] = phi * rho_l
+    for l in L.solids:
+        U[L.eps[l]] = phi[l] * rho_l[l] * W[L.eps[l]]
+        U[L.dmg[l]] = phi[l] * rho_l[l] * W[L.dmg[l]]
+    U[L.mom] = rho[None] * u
+    U[L.energy] = rho_e + 0.5 * rho * np.sum(u * u, axis=0)
+    U[L.vbar] = W[L.vbar]
+    U[L.X] = W[L.X]
+    return U
+
+
+class Prim:
+    """Cell primitives and derived quantities."""
+    pass
+
+
+def cons_to_prim(U, layout):
+    """Primitive and derived cell quantities from the conserved state."""
+    L = layout
+    dim, mats = L.dim, L.mats
+    shape = U.shape[1:]
+    P = Prim()
+    phi = U[L.phi]
+    mass = np.maximum(U[L.mass], 0.0)
+    rho_l = mass / phi
+    rho = np.sum(mass, axis=0)
+    P.phi, P.rho_l, P.rho = phi, rho_l, rho
+    P.eps, P.D = {}, {}
+    for l in L.solids:
+        ml = U[L.mass[l]]
+        pos = ml > 0
+        safe = np.where(pos, ml, 1.0)
+        P.eps[l] = np.where(pos, U[L.eps[l]] / safe, 0.0)
+        P.D[l] = np.where(pos, U[L.dmg[l]] / safe, 0.0)
+    u = np.zeros((3,) + shape)
+    for k in range(dim):
+        u[k] = U[L.mom[k]] / rho
+    P.u = u
+    rho_e = U[L.energy] - 0.5 * rho * np.sum(u * u, axis=0)
+    V = full_vbar(U[L.vbar], L.vcomps, shape)
+    H, _, _ = hencky(V)
+    J2 = J2_of(H)
+    terms = material_terms(rho_l, P.D, J2, mats)
+    p = pressure_from_energy(phi, terms, rho_e, mats)
+    c, Gmix = sound_speed(phi, rho_l, terms, p, rho, mats)
+    P.V, P.H, P.J2, P.p, P.c, P.Gmix = V, H, J2, p, c, Gmix
+    P.sigma = stress(phi, p, Gmix, H)
+    P.X = U[L.X]
+    P.rho_e = rho_e
+    return P
+
+
+def face_state(phi, rho_l, eps, D, u, p, H, mats):
+    """Conserved-side quantities of a reconstructed face state: mixture
+    density, total energy density, stress and sound speed."""
+    J2 = J2_of(H)
+    terms = material_terms(rho_l, D, J2, mats)
+    rho = np.sum(phi * rho_l, axis=0)
+    rho_e = energy_from_pressure(phi, terms, p, mats)
+    rhoE = rho_e + 0.5 * rho * np.sum(u * u, axis=0)
+    c, Gmix = sound_speed(phi, rho_l, terms, p, rho, mats)
+    sig = stress(phi, p, Gmix, H)
+    return rho, rhoE, sig, c

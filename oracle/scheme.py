@@ -1,0 +1,418 @@
+"""Hyperbolic update -- oracle, FP64, vectorised over cells and faces.
+
+The base finite-volume scheme is deferred by the paper to earlier work
+(Section 3, first paragraph).  Readings (each listed in the design notes):
+
+  * reconstruction: piecewise-linear MUSCL of the primitives
+    (phi_l, rho_l, eps_p, D, u, p, dev H, Vbar) with the van Leer limiter,
+    slope 2ab/(a+b) if ab > 0 else 0; two ghost layers.  dev H is taken at
+    cell centres and reconstructed, its trace removed again at the face.
+  * Lagrangian coordinates: third-order upwind WENO (Section 3.2.1) with
+    Jiang-Shu weights, smoothness floor eps_w = weno_eps * L^2 with L
+    the domain extent along the sweep (the paper gives no value).
+  * flux: HLLC with Davis wave speeds for the conserved equations
+    (phasic mass and history, momentum, energy, Section 2.1), the Godunov face
+    velocity for the non-conservative terms and upwinded face values of
+    phi_l, X and Vbar.
+  * void-opening modifier (Section 3.1): a face opens when either
+    neighbouring cell is critically damaged (D >= D_crit) and the sum of the
+    two cell-centre normal stresses is tensile.  An opened face carries no
+    conserved flux and no volume-fraction flux; each side sees its own
+    one-sided free-surface velocity u* = u_n -/+ sigma_nn/(rho c) and its own
+    cell-centre X and Vbar, so the opening leaves X and Vbar unchanged.
+  * free-surface boundaries behave like an opened face towards void; the
+    material leaves through it when u* points outward.
+  * time integration: SSP-RK3 (Shu-Osher) for all transported fields,
+    unsplit (the X update of Section 3.2.1 runs concurrently, with the same
+    stages).  Volume fractions are clamped to [phi_floor, 1] after each stage.
+Parity of the flux scheme is unpinned against the paper beyond the invariants
+and exact solutions checked by the tests (uniform states, conservation,
+linear X transport, mirror symmetry, elastic wave speeds, convergence order).
+"""
+import numpy as np
+
+from .layout import hencky_comps
+from .mixture import cons_to_prim, face_state
+
+AX = {0: -1, 1: -2, 2: -3}          # x, y, z -> axis from the end
+
+
+class Geometry:
+    def __init__(self, dim, n, lo, hi, bc):
+        self.dim = dim
+        self.n = tuple(n)
+        self.lo = tuple(lo)
+        self.hi = tuple(hi)
+        self.bc = tuple(tuple(b) for b in bc)
+        self.dx = tuple((hi[k] - lo[k]) / n[k] for k in range(3))
+        self.gw = [2 if k < dim else 0 for k in range(3)]
+        for k in range(dim):
+            lo_b, hi_b = self.bc[k]
+            if (lo_b == "periodic") != (hi_b == "periodic"):
+                raise ValueError("periodic boundaries must be paired")
+            for b in (lo_b, hi_b):
+                if b not in ("transmissive", "free", "periodic"):
+                    raise ValueError(f"unsupported boundary {b}")
+
+
+def pad(U, geom):
+    """Two ghost layers per active direction: zero-gradient copies for
+    transmissive and free-surface sides, wrap-around for periodic ones."""
+    out = U
+    for k in range(geom.dim):
+        ax = out.ndim + AX[k]
+        pw = [(0, 0)] * out.ndim
+        pw[ax] = (2, 2)
+        mode = "wrap" if geom.bc[k][0] == "periodic" else "edge"
+        out = np.pad(out, pw, mode=mode)
+    return out
+
+
+def _sweep_view(arr, a, geom):
+    """Crop the transverse active axes to the interior and move the sweep
+    axis `a` last."""
+    sl = [slice(None)] * arr.ndim
+    for k in range(3):
+        if k != a and geom.gw[k] > 0:
+            sl[arr.ndim + AX[k]] = slice(geom.gw[k], -geom.gw[k])
+    v = arr[tuple(sl)]
+    return np.moveaxis(v, arr.ndim + AX[a], -1)
+
+
+def _unsweep(arr, a):
+    return np.moveaxis(arr, -1, arr.ndim + AX[a])
+
+
+def van_leer(dm, dp):
+    """van Leer limited slope: 2ab/(a+b) where ab > 0, else 0."""
+    prod = dm * dp
+    den = np.where(prod > 0, dm + dp, 1.0)
+    return np.where(prod > 0, 2.0 * prod / den, 0.0)
+
+
+def weno3_faces(q, eps):
+    """Third-order WENO face values from the left and from the right at faces
+    f = 0..n of a padded line q[..., 0..n+3] (cells f+1 | f+2 meet at f)."""
+    qm, q0, q1, q2 = q[..., :-3], q[..., 1:-2], q[..., 2:-1], q[..., 3:]
+    # from the left (upwind cell f+1 = q0)
+    p0 = -0.5 * qm + 1.5 * q0
+    p1 = 0.5 * q0 + 0.5 * q1
+    b0 = (q0 - qm) ** 2
+    b1 = (q1 - q0) ** 2
+    a0 = (1.0 / 3.0) / (eps + b0) ** 2
+    a1 = (2.0 / 3.0) / (eps + b1) ** 2
+    left = (a0 * p0 + a1 * p1) / (a0 + a1)
+    # from the right (upwind cell f+2 = q1), mirror image
+    r0 = -0.5 * q2 + 1.5 * q1
+    r1 = 0.5 * q1 + 0.5 * q0
+    c0 = (q1 - q2) ** 2
+    c1 = (q0 - q1) ** 2
+    e0 = (1.0 / 3.0) / (eps + c0) ** 2
+    e1 = (2.0 / 3.0) / (eps + c1) ** 2
+    right = (e0 * r0 + e1 * r1) / (e0 + e1)
+    return left, right
+
+
+def _pick(sel_pos, sel_neg, vL, vR):
+    """Upwind choice: vL where sel_pos, vR where sel_neg, mean otherwise."""
+    return np.where(sel_pos, vL, np.where(sel_neg, vR, 0.5 * (vL + vR)))
+
+
+def _rec_rows(P, layout):
+    """Cell-centre primitive rows that are reconstructed, with names."""
+    L = layout
+    rows, names = [], []
+    for l in range(L.nm):
+        rows.append(P.phi[l]); names.append(("phi", l))
+    for l in range(L.nm):
+        rows.append(P.rho_l[l]); names.append(("rho", l))
+    for l in L.solids:
+        rows.append(P.eps[l]); names.append(("eps", l))
+        rows.append(P.D[l]); names.append(("D", l))
+    for k in range(L.dim):
+        rows.append(P.u[k]); names.append(("u", k))
+    rows.append(P.p); names.append(("p", 0))
+    for (i, j) in hencky_comps(L.dim):
+        rows.append(P.H[i, j]); names.append(("H", (i, j)))
+    for k, (i, j) in enumerate(L.vcomps):
+        rows.append(P.V[i, j]); names.append(("V", (i, j)))
+    return np.stack(rows), names
+
+
+def _unpack(W, names, layout, shape):
+    L = layout
+    phi = np.zeros((L.nm,) + shape)
+    rho = np.zeros((L.nm,) + shape)
+    eps, D = {}, {}
+    u = np.zeros((3,) + shape)
+    H = np.zeros((3, 3) + shape)
+    V = np.zeros((3, 3) + shape)
+    p = None
+    for r, (kind, key) in enumerate(names):
+        if kind == "phi":
+            phi[key] = W[r]
+        elif kind == "rho":
+            rho[key] = W[r]
+        elif kind == "eps":
+            eps[key] = W[r]
+        elif kind == "D":
+            D[key] = W[r]
+        elif kind == "u":
+            u[key] = W[r]
+        elif kind == "p":
+            p = W[r]
+        elif kind == "H":
+            i, j = key
+            H[i, j] = W[r]
+            H[j, i] = W[r]
+        elif kind == "V":
+            i, j = key
+            V[i, j] = W[r]
+    tr = (H[0, 0] + H[1, 1] + H[2, 2]) / 3.0
+    for i in range(3):
+        H[i, i] = H[i, i] - tr
+    return phi, rho, eps, D, u, p, H, V
+
+
+def _face_conserved(phi, rho_l, eps, D, u, rho, rhoE, layout):
+    L = layout
+    rows = [phi[l] * rho_l[l] for l in range(L.nm)]
+    for l in L.solids:
+        rows.append(phi[l] * rho_l[l] * eps[l])
+        rows.append(phi[l] * rho_l[l] * D[l])
+    for k in range(L.dim):
+        rows.append(rho * u[k])
+    rows.append(rhoE)
+    return np.stack(rows)
+
+
+def _phys_flux(Uc, un, u, t, layout):
+    """Physical flux U u_n - (0, 0, sigma n, u . sigma n) (Section 2.1)."""
+    L = layout
+    F = Uc * un[None]
+    base = L.nm + 2 * len(L.solids)
+    for k in range(L.dim):
+        F[base + k] = F[base + k] - t[k]
+    F[-1] = F[-1] - np.sum(u * t, axis=0)
+    return F
+
+
+def hllc(sL, sR, a, layout):
+    """HLLC flux for the conserved equations and the Godunov face velocity.
+    s* = dict(rho, u (3,..), t (3,..) = sigma[:, a], rhoE, c, Uc)."""
+    L = layout
+    unL, unR = sL["u"][a], sR["u"][a]
+    tnL, tnR = sL["t"][a], sR["t"][a]
+    rL, rR = sL["rho"], sR["rho"]
+    SL = np.minimum(unL - sL["c"], unR - sR["c"])
+    SR = np.maximum(unL + sL["c"], unR + sR["c"])
+    # grouped so that a mirrored pair of states gives exactly -S*
+    num = (tnL - tnR) + (rL * unL * (SL - unL) - rR * unR * (SR - unR))
+    den = rL * (SL - unL) - rR * (SR - unR)
+    Ss = num / den
+    FL = _phys_flux(sL["Uc"], unL, sL["u"], sL["t"], L)
+    FR = _phys_flux(sR["Uc"], unR, sR["u"], sR["t"], L)
+
+    def star(s, S, un, tn):
+        chi = (S - un) / (S - Ss)
+        Us = s["Uc"] * chi[None]
+        base = L.nm + 2 * len(L.solids)
+        for k in range(L.dim):
+            Us[base + k] = chi * s["rho"] * (s["u"][k] + (Ss - un if k == a
+                                                         else 0.0))
+        Us[-1] = chi * (s["rhoE"] + (Ss - un) * (s["rho"] * Ss
+                                                 - tn / (S - un)))
+        return Us
+
+    FsL = FL + SL[None] * (star(sL, SL, unL, tnL) - sL["Uc"])
+    FsR = FR + SR[None] * (star(sR, SR, unR, tnR) - sR["Uc"])
+    Fstar = np.where(Ss[None] > 0, FsL,
+                     np.where(Ss[None] < 0, FsR, 0.5 * (FsL + FsR)))
+    F = np.where(SL[None] >= 0, FL, np.where(SR[None] <= 0, FR, Fstar))
+    uface = np.where(SL > 0, unL, np.where(SR < 0, unR, Ss))
+    return F, uface, Ss
+
+
+def _side(W, names, layout, shape, mats):
+    phi, rho_l, eps, D, u, p, H, V = _unpack(W, names, layout, shape)
+    rho, rhoE, sig, c = face_state(phi, rho_l, eps, D, u, p, H, mats)
+    Uc = _face_conserved(phi, rho_l, eps, D, u, rho, rhoE, layout)
+    return dict(phi=phi, rho_l=rho_l, u=u, p=p, H=H, V=V, rho=rho,
+                rhoE=rhoE, sig=sig, c=c, Uc=Uc)
+
+
+def _vflux(V, uvec, a, comps):
+    """Vbar flux along direction a: V_ij u_a - V_aj u_i (Section 2.1)."""
+    return np.stack([V[i, j] * uvec[a] - V[a, j] * uvec[i] for (i, j) in comps])
+
+
+def rhs(U, geom, layout, opts):
+    """L(U) of the semi-discrete system and the outward boundary fluxes.
+
+    Returns (dU (S, nz, ny, nx), bflux) where bflux[(k, side)] is the
+    outward conserved-flux array (n_flux, transverse...) on boundary side
+    `side` of direction k (absent for periodic sides)."""
+    L = layout
+    mats = L.mats
+    dim = L.dim
+    Up = pad(U, geom)
+    P = cons_to_prim(Up, L)
+    R, names = _rec_rows(P, L)
+    dU = np.zeros_like(U)
+    bflux = {}
+    crit = np.zeros(P.p.shape, dtype=bool)
+    for l in L.solids:
+        crit |= P.D[l] >= mats[l]["D_crit"]
+    for a in range(dim):
+        dxa = geom.dx[a]
+        n = geom.n[a]
+        Rs = _sweep_view(R, a, geom)                 # (nR, T.., n+4)
+        s = van_leer(Rs[..., 1:-1] - Rs[..., :-2], Rs[..., 2:] - Rs[..., 1:-1])
+        # s[..., m] is the slope at padded cell m+1, m = 0..n+1
+        WL = Rs[..., 1:-2] + 0.5 * s[..., :-1]        # cells f+1, f = 0..n
+        WR = Rs[..., 2:-1] - 0.5 * s[..., 1:]         # cells f+2
+        fshape = WL.shape[1:]
+        sL = _side(WL, names, L, fshape, mats)
+        sR = _side(WR, names, L, fshape, mats)
+        for sd in (sL, sR):
+            sd["t"] = sd["sig"][:, a]
+        F, uface, Ss = hllc(sL, sR, a, L)
+        # tangential face velocity upwinded by the contact speed
+        uvec = _pick(Ss > 0, Ss < 0, sL["u"], sR["u"])
+        uvec[a] = uface
+        up, un_ = uface > 0, uface < 0
+        phi_f = _pick(up, un_, sL["phi"], sR["phi"])
+        V_f = _pick(up, un_, sL["V"], sR["V"])
+        Xs = _sweep_view(P.X, a, geom)
+        ext = geom.hi[a] - geom.lo[a]
+        XfL, XfR = weno3_faces(Xs, opts.weno_eps * ext * ext)
+        X_f = _pick(up, un_, XfL, XfR)
+        # per-side (as seen from the left / right cell) geometric fluxes
+        velL = uface.copy()
+        velR = uface.copy()
+        phiL = phi_f * uface[None]
+        phiR = phiL.copy()
+        XL = X_f * uface[None]
+        XR = XL.copy()
+        VfL = _vflux(V_f, uvec, a, L.vcomps)
+        VfR = VfL.copy()
+        rowL = V_f[a].copy()
+        rowR = rowL.copy()
+        # centre values of the two neighbours of each face
+        cen = {}
+        for key, arr in (("V", P.V), ("X", P.X), ("u", P.u),
+                         ("sig", P.sigma[a, a]), ("crit", crit)):
+            v = _sweep_view(arr, a, geom)
+            cen[key] = (v[..., 1:-2], v[..., 2:-1])
+        ustarL = sL["u"][a] - sL["t"][a] / (sL["rho"] * sL["c"])
+        ustarR = sR["u"][a] + sR["t"][a] / (sR["rho"] * sR["c"])
+
+        def closed_side(K, ustar, mask):
+            """Overwrite side K's geometric fluxes with its own centre values
+            and one-sided velocity where `mask`."""
+            Vc, Xc, uc = cen["V"][K], cen["X"][K], cen["u"][K].copy()
+            uc[a] = ustar
+            vf = _vflux(Vc, uc, a, L.vcomps)
+            xf = Xc * ustar[None]
+            m = mask
+            if K == 0:
+                velL[m] = ustar[m]
+                phiL[:, m] = 0.0
+                XL[:, m] = xf[:, m]
+                VfL[:, m] = vf[:, m]
+                rowL[:, m] = Vc[a][:, m]
+            else:
+                velR[m] = ustar[m]
+                phiR[:, m] = 0.0
+                XR[:, m] = xf[:, m]
+                VfR[:, m] = vf[:, m]
+                rowR[:, m] = Vc[a][:, m]
+
+        opened = ((cen["crit"][0] | cen["crit"][1])
+                  & (cen["sig"][0] + cen["sig"][1] > 0))
+        # boundary faces are handled below, never by the damage predicate
+        if geom.bc[a][0] != "periodic":
+            opened[..., 0] = False
+            opened[..., -1] = False
+        F[:, opened] = 0.0
+        closed_side(0, ustarL, opened)
+        closed_side(1, ustarR, opened)
+        # free-surface boundaries
+        for side in (0, 1):
+            if geom.bc[a][side] != "free":
+                continue
+            fi = 0 if side == 0 else n
+            K = 1 if side == 0 else 0             # interior side
+            sK = sR if K == 1 else sL
+            ust = (ustarR if K == 1 else ustarL)[..., fi]
+            outward = ust < 0 if side == 0 else ust > 0
+            m = np.zeros(opened.shape, dtype=bool)
+            # inflow of void: closed face
+            m[..., fi] = ~outward
+            F[:, m] = 0.0
+            closed_side(K, ustarR if K == 1 else ustarL, m)
+            # outflow of material at the free-surface velocity, no traction
+            mo = np.zeros(opened.shape, dtype=bool)
+            mo[..., fi] = outward
+            us = ustarR if K == 1 else ustarL
+            Fo = sK["Uc"] * us[None]
+            F[:, mo] = Fo[:, mo]
+            ufo = sK["u"].copy()
+            ufo[a] = us
+            XK = XfR if K == 1 else XfL
+            vfo = _vflux(sK["V"], ufo, a, L.vcomps)
+            if K == 0:
+                velL[mo] = us[mo]
+                phiL[:, mo] = (sK["phi"] * us[None])[:, mo]
+                XL[:, mo] = (XK * us[None])[:, mo]
+                VfL[:, mo] = vfo[:, mo]
+                rowL[:, mo] = sK["V"][a][:, mo]
+            else:
+                velR[mo] = us[mo]
+                phiR[:, mo] = (sK["phi"] * us[None])[:, mo]
+                XR[:, mo] = (XK * us[None])[:, mo]
+                VfR[:, mo] = vfo[:, mo]
+                rowR[:, mo] = sK["V"][a][:, mo]
+        # outward boundary fluxes for the conservation totals
+        for side in (0, 1):
+            if geom.bc[a][side] == "periodic":
+                continue
+            bflux[(a, side)] = (-F[..., 0] if side == 0 else F[..., n]).copy()
+        # cell updates (cells i = 0..n-1 between faces i and i+1)
+        inv = 1.0 / dxa
+        div = (velL[..., 1:] - velR[..., :-1]) * inv
+        contrib = np.zeros((L.S,) + div.shape)
+        for r, row in enumerate(L.flux_rows):
+            contrib[row] = -(F[r][..., 1:] - F[r][..., :-1]) * inv
+        Pc = {}
+        for key, arr in (("phi", P.phi), ("X", P.X), ("V", P.V), ("u", P.u)):
+            v = _sweep_view(arr, a, geom)
+            Pc[key] = v[..., 2:-2]
+        for l in range(L.nm):
+            contrib[L.phi[l]] = (-(phiL[l][..., 1:] - phiR[l][..., :-1]) * inv
+                                 + Pc["phi"][l] * div)
+        for k in range(dim):
+            contrib[L.X[k]] = (-(XL[k][..., 1:] - XR[k][..., :-1]) * inv
+                               + Pc["X"][k] * div)
+        for q, (i, j) in enumerate(L.vcomps):
+            beta_j = (rowL[j][..., 1:] - rowR[j][..., :-1]) * inv
+            contrib[L.vbar[q]] = (-(VfL[q][..., 1:] - VfR[q][..., :-1]) * inv
+                                  + (2.0 / 3.0) * Pc["V"][i, j] * div
+                                  - Pc["u"][i] * beta_j)
+        dU += _unsweep(contrib, a)
+    return dU, bflux
+
+
+def clamp_phi(U, layout, opts):
+    U[layout.phi] = np.clip(U[layout.phi], opts.phi_floor, 1.0)
+    return U
+
+
+def dt_inverse(U, geom, layout):
+    """Largest sum over directions of (|u_d| + c) / dx_d (the CFL
+    reduction); the time step is CFL / dt_inverse."""
+    P = cons_to_prim(U, layout)
+    s = np.zeros_like(P.p)
+    for k in range(layout.dim):
+        s = s + (np.abs(P.u[k]) + P.c) / geom.dx[k]
+    return float(np.max(s))

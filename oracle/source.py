@@ -1,0 +1,137 @@
+"""Per-cell source step -- oracle, FP64.
+
+Applied once per time step after the three SSP-RK3 stages (Lie splitting;
+the paper is silent on the splitting).  Readings:
+
+  * perturbation (Section 2.4, 3.2.2): phi = phi0(X) by multilinear
+    interpolation of the cell-centred initial field at the cell's Lagrangian
+    coordinates, X clamped to the span of the initial cell centres.
+  * plasticity (Section 2.1 plastic source, deferred to earlier work; the
+    perturbed yield of Section 2.4): instantaneous radial return of the
+    deviatoric Hencky strain to the perturbed yield surface.  The mixture
+    yield is sum phi_l (1-D_l) phi sigma_Y,l and the mixture modulus
+    sum phi_l (1-D_l) G~_l, so J_max = Y_mix / (sqrt(6) G_mix); for one solid
+    this is phi sigma_Y / (sqrt(6) G~), the effective-stress form.  The yield
+    is constant (sigma_Y) and drops to zero once D >= D_crit (Section 3.1,
+    second healing remark).  Delta eps_p = sqrt(2/3) (J - J_max).
+  * damage (Section 2.2 Bonora rate with the Pirondi-Bonora gate, Section 3.1
+    RK4): gate frozen at the start of the step (p < p_gate, eps_p^n above the
+    triaxiality-dependent threshold, Delta eps_p > 0, D < D_crit); triaxiality
+    from the hydrostatic pressure and the nominal equivalent stress at yield
+    (1-D) phi sigma_Y, frozen over the step; classical RK4 in eps_p from
+    eps_p^n to eps_p^n + Delta eps_p (eps_p linear in time over the step),
+    every stage argument and the result clamped to [0, D_crit].
+  * Vbar is rebuilt as the symmetric unimodular stretch Q exp(h) Q^T.
+  * Total energy is unchanged, so the dissipated elastic energy becomes heat.
+"""
+import numpy as np
+
+from .closures import (solid_shear_modulus, triaxiality, eps_threshold,
+                       bonora_dD_deps)
+from .kinematics import hencky, stretch_from_log
+from .mixture import cons_to_prim
+
+
+def phi0_at(X, phi0, geom):
+    """Multilinear interpolation of phi0 (nz, ny, nx) at coordinates
+    X (d, ...) (Section 3.2.2: the initial field is interpolated at the
+    evolved Lagrangian coordinates).  Written as nested linear
+    interpolations a + t (b - a), x first, so a constant field is returned
+    exactly."""
+    dim = geom.dim
+    base, wts = [], []
+    for k in range(dim):
+        nk = geom.n[k]
+        s = (X[k] - (geom.lo[k] + 0.5 * geom.dx[k])) / geom.dx[k]
+        s = np.clip(s, 0.0, nk - 1.0)
+        i0 = np.minimum(np.floor(s), max(nk - 2, 0)).astype(np.int64)
+        base.append(i0)
+        wts.append(s - i0)
+
+    def corner(bits):
+        idx = [np.zeros(X.shape[1:], dtype=np.int64) for _ in range(3)]
+        for k in range(dim):
+            idx[k] = np.minimum(base[k] + bits[k], geom.n[k] - 1)
+        return phi0[idx[2], idx[1], idx[0]]
+
+    def lerp(a, b, t):
+        return a + t * (b - a)
+
+    if dim == 1:
+        return lerp(corner((0,)), corner((1,)), wts[0])
+    if dim == 2:
+        f0 = lerp(corner((0, 0)), corner((1, 0)), wts[0])
+        f1 = lerp(corner((0, 1)), corner((1, 1)), wts[0])
+        return lerp(f0, f1, wts[1])
+    g = []
+    for bz in (0, 1):
+        f0 = lerp(corner((0, 0, bz)), corner((1, 0, bz)), wts[0])
+        f1 = lerp(corner((0, 1, bz)), corner((1, 1, bz)), wts[0])
+        g.append(lerp(f0, f1, wts[1]))
+    return lerp(g[0], g[1], wts[2])
+
+
+def damage_rk4(D, eps0, deps, R, m):
+    """Classical RK4 for dD/d(eps_p) from eps0 over deps, clamped."""
+    Dc = m["D_crit"]
+
+    def f(Dv, e):
+        return bonora_dD_deps(Dv, e, R, m)
+
+    def cl(v):
+        return np.clip(v, 0.0, Dc)
+
+    h = deps
+    k1 = f(D, eps0)
+    k2 = f(cl(D + 0.5 * h * k1), eps0 + 0.5 * h)
+    k3 = f(cl(D + 0.5 * h * k2), eps0 + 0.5 * h)
+    k4 = f(cl(D + h * k3), eps0 + h)
+    return cl(D + h / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4))
+
+
+def source_step(U, phi0, geom, layout, opts):
+    """Plastic return, damage and Vbar re-symmetrisation on U (in place)."""
+    L = layout
+    mats = L.mats
+    P = cons_to_prim(U, L)
+    pert = phi0_at(P.X, phi0, geom)
+    _, h, Q = hencky(P.V)
+    J = np.sqrt(np.sum(h * h, axis=0))
+    Ymix = np.zeros_like(J)
+    Gmix = np.zeros_like(J)
+    for l in L.solids:
+        m = mats[l]
+        w = 1.0 - P.D[l]
+        Gt = solid_shear_modulus(P.rho_l[l], m)
+        Gmix = Gmix + P.phi[l] * w * Gt
+        sy = np.where(P.D[l] < m["D_crit"], pert * m["yield_stress"], 0.0)
+        Ymix = Ymix + P.phi[l] * w * sy
+    pos = Gmix > 0
+    Jmax = np.where(pos, Ymix / (np.sqrt(6.0) * np.where(pos, Gmix, 1.0)),
+                    0.0)
+    yielding = J > Jmax
+    scale = np.where(yielding, Jmax / np.where(yielding, J, 1.0), 1.0)
+    deps = np.where(yielding, np.sqrt(2.0 / 3.0) * (J - Jmax), 0.0)
+    Vn = stretch_from_log(h * scale[None], Q)
+    for q, (i, j) in enumerate(L.vcomps):
+        U[L.vbar[q]] = Vn[i, j]
+    for l in L.solids:
+        m = mats[l]
+        mass = U[L.mass[l]]
+        eps_n = P.eps[l]
+        D_n = P.D[l]
+        sig_eq = (1.0 - D_n) * pert * m["yield_stress"]
+        gate = (P.p < m["p_gate"]) & (deps > 0) & (D_n < m["D_crit"])
+        ok = sig_eq > 0
+        R = triaxiality(P.p, np.where(ok, sig_eq, 1.0), P.rho_l[l], m)
+        R = np.where(ok, R, 1.0)
+        thr = eps_threshold(R, m)
+        gate = gate & ((eps_n > thr) | ~ok)
+        Dnew = D_n.copy()
+        g1 = gate & ok
+        if np.any(g1):
+            Dnew[g1] = damage_rk4(D_n[g1], eps_n[g1], deps[g1], R[g1], m)
+        Dnew[gate & ~ok] = m["D_crit"]
+        U[L.eps[l]] = mass * (eps_n + deps)
+        U[L.dmg[l]] = mass * Dnew
+    return U
