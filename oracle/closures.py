@@ -55,6 +55,19 @@ def ref_terms(rho, J2, D, m):
     return rho_eref, pref, rho_dpref, w * Gt
 
 
+# A damage value within this relative distance of D_crit counts as critical:
+# damage is clamped at D_crit and then advected as the ratio
+# (phi rho D)/(phi rho), which returns D_crit only up to rounding; the
+# critical test of Section 3.1 (D >= D_crit) is read as holding for it.
+CRIT_REL_TOL = 1.0e-9
+
+
+def is_critical(D, m):
+    """Critical damage test of Section 3.1, D >= D_crit, up to the rounding
+    of the advected ratio (see CRIT_REL_TOL)."""
+    return D >= m["D_crit"] * (1.0 - CRIT_REL_TOL)
+
+
 def gruneisen(m):
     return m["Gamma0"]
 

@@ -32,9 +32,19 @@ linear X transport, mirror symmetry, elastic wave speeds, convergence order).
 import numpy as np
 
 from .layout import hencky_comps
+from .closures import is_critical
 from .mixture import cons_to_prim, face_state
 
 AX = {0: -1, 1: -2, 2: -3}          # x, y, z -> axis from the end
+
+# Contact and face speeds below this fraction of the largest signal speed
+# count as stationary: every upwind choice made on their sign takes the mean
+# of the two sides.  Without shear waves in the approximate solver the star
+# fluxes of the two sides differ by the jump in tangential traction when the
+# contact speed passes zero, and the face stretch differs when the face speed
+# does, so the choice must not hinge on the sign of a rounding residue (as on
+# a symmetry plane).
+TIE_REL = 1.0e-12
 
 
 class Geometry:
@@ -226,11 +236,12 @@ def hllc(sL, sR, a, layout):
 
     FsL = FL + SL[None] * (star(sL, SL, unL, tnL) - sL["Uc"])
     FsR = FR + SR[None] * (star(sR, SR, unR, tnR) - sR["Uc"])
-    Fstar = np.where(Ss[None] > 0, FsL,
-                     np.where(Ss[None] < 0, FsR, 0.5 * (FsL + FsR)))
+    tie = TIE_REL * np.maximum(np.abs(SL), np.abs(SR))
+    Fstar = np.where(Ss[None] > tie, FsL,
+                     np.where(Ss[None] < -tie, FsR, 0.5 * (FsL + FsR)))
     F = np.where(SL[None] >= 0, FL, np.where(SR[None] <= 0, FR, Fstar))
     uface = np.where(SL > 0, unL, np.where(SR < 0, unR, Ss))
-    return F, uface, Ss
+    return F, uface, Ss, tie
 
 
 def _side(W, names, layout, shape, mats):
@@ -262,7 +273,7 @@ def rhs(U, geom, layout, opts):
     bflux = {}
     crit = np.zeros(P.p.shape, dtype=bool)
     for l in L.solids:
-        crit |= P.D[l] >= mats[l]["D_crit"]
+        crit |= is_critical(P.D[l], mats[l])
     for a in range(dim):
         dxa = geom.dx[a]
         n = geom.n[a]
@@ -276,11 +287,11 @@ def rhs(U, geom, layout, opts):
         sR = _side(WR, names, L, fshape, mats)
         for sd in (sL, sR):
             sd["t"] = sd["sig"][:, a]
-        F, uface, Ss = hllc(sL, sR, a, L)
+        F, uface, Ss, tie = hllc(sL, sR, a, L)
         # tangential face velocity upwinded by the contact speed
-        uvec = _pick(Ss > 0, Ss < 0, sL["u"], sR["u"])
+        uvec = _pick(Ss > tie, Ss < -tie, sL["u"], sR["u"])
         uvec[a] = uface
-        up, un_ = uface > 0, uface < 0
+        up, un_ = uface > tie, uface < -tie
         phi_f = _pick(up, un_, sL["phi"], sR["phi"])
         V_f = _pick(up, un_, sL["V"], sR["V"])
         Xs = _sweep_view(P.X, a, geom)

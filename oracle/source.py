@@ -27,7 +27,7 @@ the paper is silent on the splitting).  Readings:
 import numpy as np
 
 from .closures import (solid_shear_modulus, triaxiality, eps_threshold,
-                       bonora_dD_deps)
+                       bonora_dD_deps, is_critical)
 from .kinematics import hencky, stretch_from_log
 from .mixture import cons_to_prim
 
@@ -104,7 +104,7 @@ def source_step(U, phi0, geom, layout, opts):
         w = 1.0 - P.D[l]
         Gt = solid_shear_modulus(P.rho_l[l], m)
         Gmix = Gmix + P.phi[l] * w * Gt
-        sy = np.where(P.D[l] < m["D_crit"], pert * m["yield_stress"], 0.0)
+        sy = np.where(~is_critical(P.D[l], m), pert * m["yield_stress"], 0.0)
         Ymix = Ymix + P.phi[l] * w * sy
     pos = Gmix > 0
     Jmax = np.where(pos, Ymix / (np.sqrt(6.0) * np.where(pos, Gmix, 1.0)),
@@ -121,7 +121,7 @@ def source_step(U, phi0, geom, layout, opts):
         eps_n = P.eps[l]
         D_n = P.D[l]
         sig_eq = (1.0 - D_n) * pert * m["yield_stress"]
-        gate = (P.p < m["p_gate"]) & (deps > 0) & (D_n < m["D_crit"])
+        gate = (P.p < m["p_gate"]) & (deps > 0) & ~is_critical(D_n, m)
         ok = sig_eq > 0
         R = triaxiality(P.p, np.where(ok, sig_eq, 1.0), P.rho_l[l], m)
         R = np.where(ok, R, 1.0)

@@ -181,7 +181,7 @@ def test_flux_consistency():
     for a in range(2):
         for sd in (sL, sR):
             sd["t"] = sd["sig"][:, a]
-        Fh, uf, Ss = Sch.hllc(sL, sR, a, L)
+        Fh, uf, Ss, _ = Sch.hllc(sL, sR, a, L)
         Fp = Sch._phys_flux(sL["Uc"], sL["u"][a], sL["u"], sL["t"], L)
         assert np.allclose(Fh, Fp, rtol=1e-12, atol=1e-6)
         assert np.allclose(uf, sL["u"][a], rtol=1e-12, atol=1e-12)
