@@ -1,0 +1,168 @@
+"""Throughput of the fracture hot path on one MI355X.
+
+One step = one full time step of the whole hot path over the 1024^2
+expanding-ring workload: three SSP-RK3 stage launches (reconstruction, HLLC
+with the void-opening modifier, conservative update) with the source step
+(plastic return, damage, phi0 gather) and the CFL reduction fused into the
+third.  Inputs are resident in HBM when the timed region starts.
+
+Prints one JSON line: cell-updates/s, the roofline of the dominant (stage)
+kernel and the CPU oracle timed on a bounded window of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2210_04037_amd", "csrc", f)
+                  for f in ("fv_core.hpp", "fv_stage.hpp", "fv_api.hip")]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(precision):
+    """HBM bytes per stage launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    key = f"bytes_per_launch_{precision}"
+    return float(vals[key]) if key in vals else None
+
+
+def cpu_baseline(case, seconds=15.0):
+    """The oracle on a bounded window of the same workload: a 96 x 96
+    window through the ring, stepped until ~`seconds` of CPU time."""
+    from threadpoolctl import threadpool_limits
+    import fvinputs as F
+    from oracle import Solver
+    nx = case.n[0]
+    w = 96
+    x0 = int(nx * (0.5 + 0.4292 * 0.7071)) - w // 2     # on the ring, 45 deg
+    y0 = x0
+    dx, dy = case.dx[0], case.dx[1]
+    sub = F.Case(case.name + "_window", 2, (w, w, 1),
+                 (case.lo[0] + x0 * dx, case.lo[1] + y0 * dy, case.lo[2]),
+                 (case.lo[0] + (x0 + w) * dx, case.lo[1] + (y0 + w) * dy,
+                  case.hi[2]), case.bc, case.mats,
+                 case.prim[:, :, y0:y0 + w, x0:x0 + w].copy(),
+                 case.phi0[:, y0:y0 + w, x0:x0 + w].copy(), case.t_end)
+    with threadpool_limits(limits=1):
+        s = Solver(sub)
+        t0 = time.process_time()
+        w0 = time.perf_counter()
+        steps = 0
+        while time.process_time() - t0 < seconds and steps < 200:
+            s.step()
+            steps += 1
+        wall = time.perf_counter() - w0
+    return {"value": w * w * steps / wall, "unit": "cell-updates/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{w}x{w} window of the 1024^2 ring workload through "
+                      f"the annulus, {steps} steps, single thread"}
+
+
+def run_gpu(case, precision, steps, warmup):
+    import torch
+    from paper_2210_04037_amd.solver import GpuSolver
+    g = GpuSolver(case, precision=precision, device="cuda:0")
+    g.step(warmup)
+    torch.cuda.synchronize()
+    s = g.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    g.step(steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    t = g.time()[0]
+    g.cfl_dt()          # raises if the device flagged a non-physical state
+    S = g.S
+    elem = 8 if precision == "fp64" else 4
+    g.close()
+    return ms, S, elem, t
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is "
+              "not supported (the multi-GPU sharding is a design note only)",
+              file=sys.stderr)
+        sys.exit(2)
+    import fvinputs as F
+    case = F.make_case(2, n=args.n)
+    ncell = case.n_cells
+    ms, S, elem, t_sim = run_gpu(case, args.precision, args.steps, args.warmup)
+    cu_s = ncell * args.steps / (ms * 1e-3)
+    launches = 3 * args.steps
+    avg_launch_s = ms * 1e-3 / launches
+    # algorithmic bytes per cell-update: SSP-RK3 moves 2S + 3S + 3S fields
+    # plus one phi0 read; per launch that is a third of it
+    bytes_per_launch = (8 * S + 1) * elem * ncell / 3.0
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    traffic = measured_traffic(args.precision)
+    out = {
+        "metric": "cell-updates/s",
+        "value": cu_s,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"2D expanding ring {args.n}x{args.n} over a 60 mm "
+                         "square: copper-like annulus 25-26.5 mm in gas, "
+                         "150 m/s r/R, Gaussian phi0 (0.2 mm, 5%)"),
+            "cells": ncell, "state_fields": S, "precision": args.precision,
+            "simulated_time_s": t_sim,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "stage_kernel (3 launches per step)",
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "avg_launch_ms": avg_launch_s * 1e3,
+        },
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

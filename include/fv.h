@@ -1,0 +1,189 @@
+/*
+ * fv.h -- C ABI of the fracture hot path (libfv.so, gfx950).
+ *
+ * The library advances the multi-material elastoplastic diffuse-interface
+ * system of arXiv 2210.04037 (Wallis, Barton, Nikiforakis): the evolution
+ * equations of Section 2.1 with the Romenskii closures of Section 2.3, Bonora
+ * damage (Section 2.2), the void-opening fracture modifier (Section 3.1) and
+ * the Lagrangian-coordinate perturbation field (Sections 2.4 and 3.2).
+ *
+ * Conventions shared by every entry point
+ *   - Return value: FV_OK (0) or a negative status below.  No C++ exception
+ *     crosses the ABI.  The text of the last error is in fv_last_error().
+ *   - Device pointers are HIP device addresses owned by the caller (PyTorch
+ *     tensors in the Python binding).  The library never allocates device
+ *     memory: it keeps non-owning pointers into the caller's state, phi0 and
+ *     workspace buffers, so a context must be destroyed before they are freed.
+ *   - Host pointers are borrowed for the duration of the call only.
+ *   - A context runs on one HIP stream (the one given to fv_init).  Calls
+ *     marked "async" only enqueue work; errors found on the device (the
+ *     non-physical-state flag) surface at the next syncing call.  A context
+ *     is not thread-safe.
+ *
+ * State layout (one buffer per instance, structure of arrays, x fastest):
+ *   state[f * ncell + (z * ny + y) * nx + x] for field f in the order of the
+ *   evolution equations of Section 2.1:
+ *     [phi_l] * N, [phi_l rho_l] * N, [phi_s rho_s eps_p, phi_s rho_s D] per
+ *     solid, [rho u_i] * dim, rho E, Vbar components, [X_i] * dim
+ *   Vbar components: 1D (11, 22, 33); 2D (11, 12, 21, 22, 33); 3D all nine,
+ *   row-major.  The void fraction is 1 - sum phi_l (not stored).  Element
+ *   type: double for FV_FP64, float for FV_FP32_BULK.  Materials: solids
+ *   first (at most one), then at most one gas; N <= 2.
+ */
+#ifndef FV_H
+#define FV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define FV_OK 0
+#define FV_EINVAL -1     /* invalid argument (message in fv_last_error) */
+#define FV_ENOMEM -2     /* workspace too small */
+#define FV_EDEVICE -3    /* HIP runtime error */
+#define FV_ENONPHYS -4   /* device flag: NaN/Inf or non-positive density */
+#define FV_ESTATE -5     /* call order violated */
+
+/* boundary kinds, per side of each direction */
+#define FV_BC_TRANSMISSIVE 0  /* zero-gradient ghost cells */
+#define FV_BC_FREE 1          /* free surface: void outside (Section 3.1) */
+#define FV_BC_PERIODIC 2      /* both sides of the direction */
+
+/* material kinds */
+#define FV_MAT_SOLID 0   /* Romenskii EOS + shear modulus, Bonora damage */
+#define FV_MAT_GAS 1     /* ideal gas, Grueneisen constant gamma - 1 */
+
+/* precision policies */
+#define FV_FP64 0        /* state and arithmetic in double */
+#define FV_FP32_BULK 1   /* float state; double islands (see fv_options) */
+
+typedef struct fv_ctx fv_ctx;
+
+/* Uniform grid of one instance.  dim in {1, 2}; n[k] cells on [lo[k],hi[k]]
+ * for k < dim (unused directions: n = 1, and their extent sets the cell
+ * volume).  bc[k][0] / bc[k][1] are the lower / upper sides. */
+typedef struct {
+  int32_t dim;
+  int32_t n[3];
+  double lo[3];
+  double hi[3];
+  int32_t bc[3][2];
+} fv_grid;
+
+/* Material constants, SI units (Sections 2.2, 2.3; Appendix A tables).
+ * Solid: rho0, K0 (bulk modulus), alpha (Romenskii exponent), G0, beta
+ * (shear-modulus exponent, G = G0 (rho/rho0)^(beta+1)), Gamma0, yield (the
+ * constant yield stress the perturbation field scales), D_crit, D0, eps_th,
+ * eps_c, bonora_alpha, n_hard (hardening exponent of the threshold strain),
+ * p_gate (damage accrues only for p < p_gate).  Gas: Gamma0 = gamma - 1; the
+ * other fields are ignored. */
+typedef struct {
+  int32_t kind;
+  double rho0, K0, alpha, G0, beta, Gamma0;
+  double yield, D_crit, D0, eps_th, eps_c, bonora_alpha, n_hard, p_gate;
+} fv_material;
+
+/* Run options.  cfl: Courant number of the CFL reduction.  phi_floor:
+ * volume fractions are clamped to [phi_floor, 1] (absent materials).
+ * weno_eps: WENO3 smoothness floor relative to the squared domain extent.
+ * phi_fp64_cut: FP32-bulk only, cells with a volume fraction below it invert
+ * the mixture EOS in double.  tile: 0 selects the default tile. */
+typedef struct {
+  int32_t precision;
+  double cfl;
+  double phi_floor;
+  double weno_eps;
+  double phi_fp64_cut;
+  int32_t tile[3];
+  int32_t reserved;
+} fv_options;
+
+/* Number of state fields S for a dimension and material list (the first
+ * dimension of every state buffer).  Returns 0 for an invalid list. */
+int32_t fv_state_fields(int32_t dim, int32_t n_mat, const fv_material* mats);
+
+/* Bytes of device workspace fv_init needs for these instances (two stage
+ * copies of every state, boundary-flux accumulators, dt state, instance
+ * tables, reduction bins).  Returns 0 for invalid arguments. */
+size_t fv_workspace_bytes(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
+                          const fv_material* mats, const fv_options* opt);
+
+/* Create a context for n_inst instances sharing dimension, materials and
+ * options (the ensemble of seeded realisations advances in one launch).
+ * state[i]: device pointer to instance i's state (S * ncell elements,
+ * caller-owned, in/out).  phi0[i]: device pointer to the initial perturbation
+ * field of instance i on its initial mesh (ncell elements of the state's
+ * element type, read-only, Section 2.4).  workspace: device buffer of at
+ * least fv_workspace_bytes.  stream: hipStream_t (NULL = default stream).
+ * The states are not read here: load them with fv_load_primitive or write
+ * conserved values and call fv_reset.  Errors: FV_EINVAL, FV_ENOMEM,
+ * FV_EDEVICE. */
+int32_t fv_init(fv_ctx** out, int32_t n_inst, const fv_grid* grids,
+                int32_t n_mat, const fv_material* mats, const fv_options* opt,
+                void* const* state, const void* const* phi0, void* workspace,
+                size_t workspace_bytes, void* stream);
+
+/* Convert a primitive field to instance inst's conserved state (async).
+ * prim: device pointer, S * ncell doubles in the state's field order with
+ * rho_l in place of phi_l rho_l, (eps_p, D) in place of the history
+ * densities, the velocity in place of the momentum and the pressure in place
+ * of the total energy.  Volume fractions are clamped to [phi_floor, 1].
+ * Also resets the instance's time, boundary accumulators and flag and
+ * computes its first CFL time step. */
+int32_t fv_load_primitive(fv_ctx* ctx, int32_t inst, const void* prim);
+
+/* Reset time, accumulators and flag of every instance and recompute the CFL
+ * time step from the current states (after the caller wrote conserved
+ * states directly).  Async. */
+int32_t fv_reset(fv_ctx* ctx);
+
+/* The primitive field of instance inst (same layout as fv_load_primitive's
+ * input) into prim (device, S * ncell doubles).  Async. */
+int32_t fv_primitive(fv_ctx* ctx, int32_t inst, void* prim);
+
+/* Time step of every instance from the CFL reduction of its current state
+ * (Courant number times the inverse of the largest sum over directions of
+ * (|u_d| + c) / dx_d), clamped to its end time.  dt_host: [n_inst] out.
+ * Synchronises the stream; returns FV_ENONPHYS if the device flag is set. */
+int32_t fv_cfl_dt(fv_ctx* ctx, double* dt_host);
+
+/* Advance every instance by n_steps time steps (async, no host sync).  Each
+ * step: three SSP-RK3 stages of the hyperbolic update (MUSCL/van Leer
+ * primitives, WENO3 Lagrangian coordinates, HLLC flux with the void-opening
+ * modifier of Section 3.1), then the source step (radial return to the
+ * perturbed yield of Section 2.4, Bonora damage integrated by RK4 as in
+ * Section 3.1, phi0 interpolated at the Lagrangian coordinates as in
+ * Section 3.2.2) and the CFL reduction for the next step.  dt_host: NULL to
+ * use the device CFL step, else [n_inst] fixed steps.  t_end: NULL to keep
+ * the current end times, else [n_inst]; an instance at its end time does no
+ * work. */
+int32_t fv_step(fv_ctx* ctx, const double* dt_host, int32_t n_steps,
+                const double* t_end);
+
+/* Simulated time of every instance, t_host [n_inst] out.  Synchronises. */
+int32_t fv_time(fv_ctx* ctx, double* t_host);
+
+/* Conservation totals.  out: [n_inst][2 * (N + dim + 1)] doubles: the
+ * interior totals of phi_l rho_l (N), rho u_i (dim) and rho E over the cells
+ * times the cell volume, then the cumulative outward flux of the same
+ * quantities through the domain boundary.  Each sum is exact before its one
+ * final rounding (an integer superaccumulator), so it equals the correctly
+ * rounded sum of the same values.  Synchronises; FV_ENONPHYS if flagged. */
+int32_t fv_totals(fv_ctx* ctx, double* out);
+
+/* Text of the last error of ctx (or of the last failed fv_init when ctx is
+ * NULL).  Valid until the next call on ctx. */
+const char* fv_last_error(const fv_ctx* ctx);
+
+/* Destroy a context (synchronises its stream first).  NULL is allowed. */
+void fv_destroy(fv_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FV_H */

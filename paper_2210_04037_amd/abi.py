@@ -1,0 +1,125 @@
+"""ctypes binding of include/fv.h: the C structs, status codes and the
+library loader.  Argument marshalling only; every step of the method runs in
+the HIP kernels of libfv.so."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfv.so")
+
+FV_OK, FV_EINVAL, FV_ENOMEM, FV_EDEVICE, FV_ENONPHYS, FV_ESTATE = 0, -1, -2, -3, -4, -5
+FV_BC = {"transmissive": 0, "free": 1, "periodic": 2}
+FV_MAT = {"solid": 0, "gas": 1}
+FV_FP64, FV_FP32_BULK = 0, 1
+PRECISIONS = {"fp64": FV_FP64, "fp32": FV_FP32_BULK}
+
+EXPORTS = ["fv_state_fields", "fv_workspace_bytes", "fv_init",
+           "fv_load_primitive", "fv_reset", "fv_primitive", "fv_cfl_dt",
+           "fv_step", "fv_time", "fv_totals", "fv_last_error", "fv_destroy"]
+
+
+class FvGrid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("bc", (ctypes.c_int32 * 2) * 3)]
+
+
+class FvMaterial(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32)] + [
+        (n, ctypes.c_double) for n in (
+            "rho0", "K0", "alpha", "G0", "beta", "Gamma0", "yield_", "D_crit",
+            "D0", "eps_th", "eps_c", "bonora_alpha", "n_hard", "p_gate")]
+
+
+class FvOptions(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("cfl", ctypes.c_double),
+                ("phi_floor", ctypes.c_double), ("weno_eps", ctypes.c_double),
+                ("phi_fp64_cut", ctypes.c_double),
+                ("tile", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32)]
+
+
+class FvError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libfv status {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libfv.so; raises if it has not been built (there is no
+    fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is missing: build it with "
+            "`python -m paper_2210_04037_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    P = ctypes.POINTER
+    lib.fv_state_fields.argtypes = [i32, i32, P(FvMaterial)]
+    lib.fv_state_fields.restype = i32
+    lib.fv_workspace_bytes.argtypes = [i32, P(FvGrid), i32, P(FvMaterial), P(FvOptions)]
+    lib.fv_workspace_bytes.restype = ctypes.c_size_t
+    lib.fv_init.argtypes = [P(vp), i32, P(FvGrid), i32, P(FvMaterial), P(FvOptions),
+                            P(vp), P(vp), vp, ctypes.c_size_t, vp]
+    lib.fv_init.restype = i32
+    lib.fv_load_primitive.argtypes = [vp, i32, vp]
+    lib.fv_load_primitive.restype = i32
+    lib.fv_reset.argtypes = [vp]
+    lib.fv_reset.restype = i32
+    lib.fv_primitive.argtypes = [vp, i32, vp]
+    lib.fv_primitive.restype = i32
+    lib.fv_cfl_dt.argtypes = [vp, P(dbl)]
+    lib.fv_cfl_dt.restype = i32
+    lib.fv_step.argtypes = [vp, P(dbl), i32, P(dbl)]
+    lib.fv_step.restype = i32
+    lib.fv_time.argtypes = [vp, P(dbl)]
+    lib.fv_time.restype = i32
+    lib.fv_totals.argtypes = [vp, P(dbl)]
+    lib.fv_totals.restype = i32
+    lib.fv_last_error.argtypes = [vp]
+    lib.fv_last_error.restype = ctypes.c_char_p
+    lib.fv_destroy.argtypes = [vp]
+    lib.fv_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def grid_struct(case):
+    g = FvGrid()
+    g.dim = case.dim
+    for k in range(3):
+        g.n[k] = int(case.n[k])
+        g.lo[k] = float(case.lo[k])
+        g.hi[k] = float(case.hi[k])
+        for s in range(2):
+            g.bc[k][s] = FV_BC[case.bc[k][s]]
+    return g
+
+
+def material_array(mats):
+    arr = (FvMaterial * len(mats))()
+    for l, m in enumerate(mats):
+        a = arr[l]
+        a.kind = FV_MAT[m["kind"]]
+        for key in ("rho0", "K0", "alpha", "G0", "beta", "Gamma0", "D_crit",
+                    "D0", "eps_th", "eps_c", "bonora_alpha", "n_hard",
+                    "p_gate"):
+            setattr(a, key, float(m[key]))
+        a.yield_ = float(m["yield_stress"])
+    return arr
+
+
+def options_struct(precision="fp64", cfl=0.6, phi_floor=1e-8, weno_eps=1e-6,
+                   phi_fp64_cut=1e-6):
+    o = FvOptions()
+    o.precision = PRECISIONS[precision]
+    o.cfl = cfl
+    o.phi_floor = phi_floor
+    o.weno_eps = weno_eps
+    o.phi_fp64_cut = phi_fp64_cut
+    return o

@@ -1,0 +1,833 @@
+// libfv: kernels and the C ABI declared in include/fv.h.
+//
+// One HIP translation unit.  Templates are instantiated for the supported
+// (dimension, materials, precision) combinations; fv_init picks one set of
+// launchers and every later call goes through it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fv_stage.hpp"
+#include "../../include/fv.h"
+
+using namespace fv;
+
+namespace {
+
+constexpr int NBINS = 70;  // 32-bit bins covering every finite double
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block maximum of a non-negative value, then an integer atomicMax on its
+// bit pattern (order-preserving for non-negative doubles), so the result is
+// independent of the order in which blocks finish.
+template <int NT>
+__device__ void block_max_to(double v, double* scratch, double* target) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  constexpr int NWV = (NT + 63) / 64;
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = scratch[0];
+    for (int w = 1; w < NWV; ++w) m = fmax(m, scratch[w]);
+    if (m > 0.0)
+      atomicMax(reinterpret_cast<unsigned long long*>(target),
+                (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// Exact sum into 32-bit bins of the integer value * 2^1074.
+__device__ __forceinline__ void bin_add(unsigned long long* bins, double v) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  const int ex = (int)((bits >> 52) & 0x7FF);
+  if (ex == 0x7FF) return;              // non-finite values are flagged elsewhere
+  unsigned long long m = bits & ((1ull << 52) - 1);
+  int shift;
+  if (ex == 0) {
+    shift = 0;                          // subnormal: m * 2^-1074
+  } else {
+    m |= 1ull << 52;
+    shift = ex - 1;                     // m * 2^(ex - 1075) = m * 2^(shift - 1074)
+  }
+  if (m == 0) return;
+  const int k0 = shift >> 5, off = shift & 31;
+  const unsigned long long mlo = m & 0xFFFFFFFFull, mhi = m >> 32;
+  const unsigned long long t0 = mlo << off, t1 = mhi << off;
+  const unsigned long long c0 = t0 & 0xFFFFFFFFull;
+  const unsigned long long c1 = (t0 >> 32) + (t1 & 0xFFFFFFFFull);
+  const unsigned long long c2 = t1 >> 32;
+  const bool neg = (bits >> 63) != 0;
+  // two's complement wrap-around makes unsigned adds of negated chunks exact
+  atomicAdd(&bins[k0], neg ? (0ull - c0) : c0);
+  atomicAdd(&bins[k0 + 1], neg ? (0ull - c1) : c1);
+  if (c2) atomicAdd(&bins[k0 + 2], neg ? (0ull - c2) : c2);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) exact_sum_kernel(const T* data, int64_t n,
+                                                        int64_t stride,
+                                                        unsigned long long* out) {
+  __shared__ unsigned long long bins[NBINS];
+  for (int k = threadIdx.x; k < NBINS; k += blockDim.x) bins[k] = 0;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    bin_add(bins, (double)data[i * stride]);
+  __syncthreads();
+  for (int k = threadIdx.x; k < NBINS; k += blockDim.x)
+    if (bins[k]) atomicAdd(&out[k], bins[k]);
+}
+
+// Correctly rounded (ties to even) value of sum_k bins[k] 2^(32k) 2^-1074.
+double bins_to_double(const unsigned long long* ub) {
+  long long bins[NBINS];
+  for (int k = 0; k < NBINS; ++k) bins[k] = (long long)ub[k];
+  uint32_t limb[NBINS + 2];
+  long long carry = 0;
+  for (int k = 0; k < NBINS; ++k) {
+    // exact: |bins[k]| < 2^62 and |carry| < 2^31
+    const __int128 v = (__int128)bins[k] + carry;
+    limb[k] = (uint32_t)(v & 0xFFFFFFFF);
+    carry = (long long)(v >> 32);
+  }
+  limb[NBINS] = (uint32_t)(carry & 0xFFFFFFFF);
+  limb[NBINS + 1] = (uint32_t)((carry >> 32) & 0xFFFFFFFF);
+  const int NL = NBINS + 2;
+  bool neg = (limb[NL - 1] >> 31) != 0;
+  if (neg) {  // magnitude of the two's complement number
+    unsigned long long c = 1;
+    for (int k = 0; k < NL; ++k) {
+      const unsigned long long v = (unsigned long long)(uint32_t)~limb[k] + c;
+      limb[k] = (uint32_t)v;
+      c = v >> 32;
+    }
+  }
+  int top = -1;
+  for (int k = NL - 1; k >= 0 && top < 0; --k)
+    if (limb[k]) top = k * 32 + (31 - __builtin_clz(limb[k]));
+  if (top < 0) return 0.0;
+  auto bit = [&](int i) -> int { return i < 0 ? 0 : (limb[i >> 5] >> (i & 31)) & 1; };
+  // 53 significant bits [top-52, top]
+  const int lo = top - 52;
+  unsigned long long mant = 0;
+  for (int i = top; i >= std::max(lo, 0); --i) mant = (mant << 1) | bit(i);
+  int e2 = 0;  // value = mant * 2^(e2 - 1074)
+  if (lo > 0) {
+    e2 = lo;
+    const int rb = bit(lo - 1);
+    bool sticky = false;
+    for (int i = lo - 2; i >= 0 && !sticky; --i) sticky = bit(i) != 0;
+    if (rb && (sticky || (mant & 1))) {
+      mant += 1;
+      if (mant >> 53) { mant >>= 1; e2 += 1; }
+    }
+  } else {
+    mant = 0;
+    for (int i = top; i >= 0; --i) mant = (mant << 1) | bit(i);
+  }
+  const double r = std::ldexp((double)mant, e2 - 1074);
+  return neg ? -r : r;
+}
+
+// ---------------------------------------------------------------------------
+// stage kernel
+// ---------------------------------------------------------------------------
+template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY)
+stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int parity) {
+  using St = Stage<DIM, NM, NS, T, C, TX, TY>;
+  using TL = typename St::TL;
+  constexpr int NT = TX * TY;
+  extern __shared__ double smem_d[];
+  C* sm = reinterpret_cast<C*>(smem_d);
+  C* fb = sm + (size_t)St::NW * TL::NCELL;
+  const int b = blockIdx.x;
+  const int ii = block_inst[b];
+  const Inst& I = insts[ii];
+  double* dts = I.dts;
+  const int q = parity & 1;
+  const double t = dts[DTS_T + q];
+  const double dtinv = dts[DTS_DTINV + q];
+  double dt = dts[DTS_DTFIX] > 0.0 ? dts[DTS_DTFIX] : P.cfl / dtinv;
+  dt = fmin(dt, dts[DTS_TEND] - t);
+  const int lb = b - I.block_begin;
+  const int tid = threadIdx.x;
+  if (!(dt > 0.0)) {
+    if (stage == 1 && lb == 0 && tid == 0) {
+      dts[DTS_T + 1 - q] = t;
+      dts[DTS_DTINV + 1 - q] = dtinv;
+    }
+    return;
+  }
+  if (stage == 1 && lb == 0 && tid == 0) {
+    dts[DTS_T + 1 - q] = t + dt;
+    dts[DTS_DTINV + 1 - q] = 0.0;
+  }
+  typename St::Ctx cx;
+  cx.I = &I;
+  cx.P = P;
+  cx.stage = stage;
+  cx.parity = q;
+  cx.bx = lb % I.tiles[0];
+  cx.by = lb / I.tiles[0];
+  cx.dt = (C)dt;
+  const T* U = (const T*)I.U;
+  cx.base = U;
+  cx.src = stage == 1 ? U : (stage == 2 ? (const T*)I.U1 : (const T*)I.U2);
+  cx.out = stage == 1 ? (T*)I.U1 : (stage == 2 ? (T*)I.U2 : (T*)I.U);
+
+  for (int tc = tid; tc < TL::NCELL; tc += NT) St::load_cell(cx, sm, tc);
+  __syncthreads();
+
+  C acc[St::S];
+#pragma unroll
+  for (int f = 0; f < St::S; ++f) acc[f] = 0;
+  int tx, ty;
+  int64_t g = 0;
+  const bool own = St::own_cell(cx, tid, tx, ty, g);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const int nit = St::face_items(a);
+    for (int it = tid; it < nit; it += NT) {
+      int cm, c0, c1, c2, gf, fs, bs;
+      if (St::face_item(cx, a, it, cm, c0, c1, c2, gf, fs, bs))
+        St::compute_face(cx, sm, a, cm, c0, c1, c2, gf, fs, bs, fb);
+    }
+    __syncthreads();
+    if (own) St::gather(cx, sm, fb, a, tx, ty, acc);
+    __syncthreads();
+  }
+  double cflv = 0.0;
+  if (own) {
+    bool bad = false;
+    cflv = St::finish_cell(cx, g, acc, &bad);
+    if (bad) atomicOr(reinterpret_cast<unsigned int*>(&dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);
+  }
+  if (stage == 3) block_max_to<NT>(cflv, reinterpret_cast<double*>(smem_d), &dts[DTS_DTINV + 1 - q]);
+}
+
+// ---------------------------------------------------------------------------
+// primitive <-> conserved, CFL
+// ---------------------------------------------------------------------------
+template <int DIM, int NM, int NS, class T>
+__global__ void __launch_bounds__(256) prim_to_cons_kernel(const Inst* insts, int ii, Params P,
+                                                           const double* prim) {
+  using L = Lay<DIM, NM, NS>;
+  const Inst& I = insts[ii];
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= I.ncell) return;
+  double W[L::S], U[L::S];
+  for (int f = 0; f < L::S; ++f) W[f] = prim[(int64_t)f * I.ncell + g];
+  Cell<DIM, NM, NS>::prim_to_cons(P, W, U);
+  T* Us = (T*)I.U;
+  for (int f = 0; f < L::S; ++f) Us[(int64_t)f * I.ncell + g] = (T)U[f];
+}
+
+template <int DIM, int NM, int NS, class T>
+__global__ void __launch_bounds__(256) cons_to_prim_kernel(const Inst* insts, int ii, Params P,
+                                                           double* prim) {
+  using L = Lay<DIM, NM, NS>;
+  const Inst& I = insts[ii];
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= I.ncell) return;
+  const T* Us = (const T*)I.U;
+  double U[L::S], W[L::S];
+  for (int f = 0; f < L::S; ++f) U[f] = (double)Us[(int64_t)f * I.ncell + g];
+  Cell<DIM, NM, NS>::cons_to_prim(P, U, W);
+  for (int f = 0; f < L::S; ++f) prim[(int64_t)f * I.ncell + g] = W[f];
+}
+
+template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
+__global__ void __launch_bounds__(256) cfl_kernel(const Inst* insts, int ii, Params P, int parity) {
+  using St = Stage<DIM, NM, NS, T, C, TX, TY>;
+  using L = Lay<DIM, NM, NS>;
+  __shared__ double scratch[4];
+  const Inst& I = insts[ii];
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (g < I.ncell) {
+    const T* Us = (const T*)I.U;
+    double U[L::S];
+    for (int f = 0; f < L::S; ++f) U[f] = (double)Us[(int64_t)f * I.ncell + g];
+    v = St::cfl_sum(P, I, U);
+    if (!(v == v)) {
+      atomicOr(reinterpret_cast<unsigned int*>(&I.dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);
+      v = 0.0;
+    }
+  }
+  block_max_to<256>(v, scratch, &I.dts[DTS_DTINV + (parity & 1)]);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct Ops {
+  int S = 0, NC = 0, NTOT = 0, TX = 0, TY = 0, NT = 0;
+  size_t smem = 0;
+  void (*stage)(fv_ctx*, int, int) = nullptr;
+  void (*p2c)(fv_ctx*, int, const double*) = nullptr;
+  void (*c2p)(fv_ctx*, int, double*) = nullptr;
+  void (*cfl)(fv_ctx*, int, int) = nullptr;
+  size_t elem = 8;
+};
+
+struct fv_ctx {
+  int n_inst = 0, dim = 0, nm = 0, ns = 0, precision = 0;
+  Params P{};
+  hipStream_t stream = nullptr;
+  std::vector<Inst> insts;
+  Inst* insts_d = nullptr;
+  int* block_inst_d = nullptr;
+  unsigned long long* bins_d = nullptr;
+  int total_blocks = 0;
+  long long step = 0;
+  Ops ops;
+  std::vector<double> h_dt, h_tend;   // staging for async copies
+  std::string err;
+};
+
+static std::string g_init_error;
+
+static int fail(fv_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg; else g_init_error = msg;
+  return code;
+}
+
+static int hip_check(fv_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return FV_OK;
+  return fail(c, FV_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
+static Ops make_ops() {
+  using St = Stage<DIM, NM, NS, T, C, TX, TY>;
+  using L = Lay<DIM, NM, NS>;
+  Ops o;
+  o.S = L::S;
+  o.NC = L::NC;
+  o.NTOT = NM + DIM + 1;
+  o.TX = TX;
+  o.TY = TY;
+  o.NT = TX * TY;
+  o.elem = sizeof(T);
+  o.smem = St::smem_bytes();
+  o.stage = [](fv_ctx* c, int stage, int parity) {
+    hipLaunchKernelGGL((stage_kernel<DIM, NM, NS, T, C, TX, TY>), dim3(c->total_blocks),
+                       dim3(TX * TY), St::smem_bytes(), c->stream, c->insts_d,
+                       c->block_inst_d, c->P, stage, parity);
+  };
+  o.p2c = [](fv_ctx* c, int ii, const double* prim) {
+    const int64_t n = c->insts[ii].ncell;
+    hipLaunchKernelGGL((prim_to_cons_kernel<DIM, NM, NS, T>), dim3((unsigned)((n + 255) / 256)),
+                       dim3(256), 0, c->stream, c->insts_d, ii, c->P, prim);
+  };
+  o.c2p = [](fv_ctx* c, int ii, double* prim) {
+    const int64_t n = c->insts[ii].ncell;
+    hipLaunchKernelGGL((cons_to_prim_kernel<DIM, NM, NS, T>), dim3((unsigned)((n + 255) / 256)),
+                       dim3(256), 0, c->stream, c->insts_d, ii, c->P, prim);
+  };
+  o.cfl = [](fv_ctx* c, int ii, int parity) {
+    const int64_t n = c->insts[ii].ncell;
+    hipLaunchKernelGGL((cfl_kernel<DIM, NM, NS, T, C, TX, TY>), dim3((unsigned)((n + 255) / 256)),
+                       dim3(256), 0, c->stream, c->insts_d, ii, c->P, parity);
+  };
+  return o;
+}
+
+template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
+static hipError_t set_smem_attr() {
+  using St = Stage<DIM, NM, NS, T, C, TX, TY>;
+  return hipFuncSetAttribute((const void*)&stage_kernel<DIM, NM, NS, T, C, TX, TY>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)St::smem_bytes());
+}
+
+// supported combinations; returns false if none matches
+// set_attr: also raise the kernel's dynamic LDS limit (a HIP runtime call;
+// size-only queries skip it so that they run without a device)
+static bool select_ops(int dim, int nm, int ns, int prec, Ops& o, hipError_t& herr,
+                       bool set_attr = true) {
+  herr = hipSuccess;
+#define FV_SEL(D, M, S_, TT, CC, X, Y)                           \
+  if (dim == D && nm == M && ns == S_ && prec == (sizeof(TT) == 8 ? FV_FP64 : FV_FP32_BULK)) { \
+    o = make_ops<D, M, S_, TT, CC, X, Y>();                     \
+    if (set_attr) herr = set_smem_attr<D, M, S_, TT, CC, X, Y>(); \
+    return true;                                                \
+  }
+  FV_SEL(1, 1, 1, double, double, 256, 1)
+  FV_SEL(1, 2, 1, double, double, 256, 1)
+  FV_SEL(2, 1, 1, double, double, 32, 8)
+  FV_SEL(2, 2, 1, double, double, 32, 8)
+#undef FV_SEL
+  return false;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int validate(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
+                    const fv_material* mats, const fv_options* opt, int& ns,
+                    std::string& msg) {
+  if (n_inst < 1 || !grids || !mats || !opt) { msg = "null argument or n_inst < 1"; return FV_EINVAL; }
+  if (n_mat < 1 || n_mat > 2) { msg = "n_mat must be 1 or 2"; return FV_EINVAL; }
+  ns = 0;
+  for (int l = 0; l < n_mat; ++l) {
+    if (mats[l].kind != FV_MAT_SOLID && mats[l].kind != FV_MAT_GAS) { msg = "bad material kind"; return FV_EINVAL; }
+    if (mats[l].kind == FV_MAT_SOLID) {
+      if (l != ns) { msg = "solids must precede gases"; return FV_EINVAL; }
+      ++ns;
+      const fv_material& m = mats[l];
+      if (!(m.rho0 > 0 && m.K0 > 0 && m.alpha > 0 && m.G0 >= 0 && m.Gamma0 > 0 &&
+            m.D_crit > m.D0 && m.D_crit < 1 && m.eps_c > m.eps_th && m.eps_th > 0 &&
+            m.bonora_alpha > 0 && m.n_hard > 0 && m.yield >= 0)) {
+        msg = "invalid solid constants"; return FV_EINVAL;
+      }
+    } else if (!(mats[l].Gamma0 > 0)) { msg = "gas needs Gamma0 > 0"; return FV_EINVAL; }
+  }
+  if (ns > 1) { msg = "at most one solid"; return FV_EINVAL; }
+  if (opt->precision != FV_FP64 && opt->precision != FV_FP32_BULK) { msg = "bad precision"; return FV_EINVAL; }
+  if (!(opt->cfl > 0 && opt->cfl <= 1)) { msg = "cfl must be in (0, 1]"; return FV_EINVAL; }
+  if (!(opt->phi_floor > 0 && opt->phi_floor < 0.5)) { msg = "phi_floor must be in (0, 0.5)"; return FV_EINVAL; }
+  if (!(opt->weno_eps > 0)) { msg = "weno_eps must be > 0"; return FV_EINVAL; }
+  const int dim = grids[0].dim;
+  for (int i = 0; i < n_inst; ++i) {
+    const fv_grid& g = grids[i];
+    if (g.dim != dim) { msg = "all instances must share the dimension"; return FV_EINVAL; }
+    if (g.dim < 1 || g.dim > 2) { msg = "dim must be 1 or 2"; return FV_EINVAL; }
+    for (int k = 0; k < 3; ++k) {
+      if (g.n[k] < 1 || (k >= g.dim && g.n[k] != 1)) { msg = "bad cell counts"; return FV_EINVAL; }
+      if (!(g.hi[k] > g.lo[k])) { msg = "hi must exceed lo"; return FV_EINVAL; }
+      if (k < g.dim) {
+        for (int s = 0; s < 2; ++s)
+          if (g.bc[k][s] < FV_BC_TRANSMISSIVE || g.bc[k][s] > FV_BC_PERIODIC) { msg = "bad boundary kind"; return FV_EINVAL; }
+        if ((g.bc[k][0] == FV_BC_PERIODIC) != (g.bc[k][1] == FV_BC_PERIODIC)) { msg = "periodic sides must be paired"; return FV_EINVAL; }
+      }
+    }
+    if ((int64_t)g.n[0] * g.n[1] * g.n[2] > ((int64_t)1 << 31)) { msg = "too many cells"; return FV_EINVAL; }
+  }
+  return FV_OK;
+}
+
+struct WsPlan {
+  std::vector<size_t> u1, u2, bacc, dts;
+  std::vector<int> ntrans[6];
+  size_t insts = 0, block_inst = 0, bins = 0, total = 0;
+  int total_blocks = 0;
+  std::vector<int> tiles[3], block_begin;
+};
+
+static void plan_ws(int32_t n_inst, const fv_grid* grids, const Ops& o, WsPlan& W) {
+  size_t off = 0;
+  W.total_blocks = 0;
+  for (int k = 0; k < 3; ++k) W.tiles[k].resize(n_inst);
+  W.block_begin.resize(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    const fv_grid& g = grids[i];
+    const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    const size_t sb = align256((size_t)o.S * ncell * o.elem);
+    W.u1.push_back(off); off += sb;
+    W.u2.push_back(off); off += sb;
+    size_t nb = 0;
+    for (int a = 0; a < 3; ++a) {
+      const int nt = a < g.dim ? (a == 0 ? g.n[1] * g.n[2] : g.n[0] * g.n[2]) : 0;
+      nb += 2 * (size_t)nt * o.NC;
+    }
+    W.bacc.push_back(off); off += align256(nb * sizeof(double));
+    W.dts.push_back(off); off += align256(DTS_SIZE * sizeof(double));
+    const int tx = (g.n[0] + o.TX - 1) / o.TX;
+    const int ty = g.dim >= 2 ? (g.n[1] + o.TY - 1) / o.TY : 1;
+    W.tiles[0][i] = tx; W.tiles[1][i] = ty; W.tiles[2][i] = 1;
+    W.block_begin[i] = W.total_blocks;
+    W.total_blocks += tx * ty;
+  }
+  W.insts = off; off += align256(sizeof(Inst) * n_inst);
+  W.block_inst = off; off += align256(sizeof(int) * W.total_blocks);
+  W.bins = off; off += align256(sizeof(unsigned long long) * NBINS * (size_t)n_inst * 2 * o.NTOT * 3);
+  W.total = off;
+}
+
+static void fill_params(const fv_material* mats, int n_mat, const fv_options* opt, Params& P) {
+  std::memset(&P, 0, sizeof(P));
+  for (int l = 0; l < n_mat; ++l) {
+    const fv_material& m = mats[l];
+    MatP& q = P.mat[l];
+    q.kind = m.kind == FV_MAT_SOLID ? 0 : 1;
+    q.rho0 = m.rho0; q.K0 = m.K0; q.alpha = m.alpha; q.G0 = m.G0; q.beta = m.beta;
+    q.Gamma0 = m.Gamma0; q.yield = m.yield; q.Dcrit = m.D_crit; q.D0 = m.D0;
+    q.eps_th = m.eps_th; q.eps_c = m.eps_c; q.balpha = m.bonora_alpha;
+    q.nhard = m.n_hard; q.pgate = m.p_gate;
+    q.Dcrit_eff = m.D_crit * (1.0 - 1.0e-9);
+    q.invGamma = 1.0 / m.Gamma0;
+    auto small_int = [](double v) {
+      const double r = std::round(v);
+      return (r == v && r >= 1 && r <= 8) ? (int)r : 0;
+    };
+    if (q.kind == 0) {
+      q.alpha_i = small_int(m.alpha);
+      q.beta1_i = small_int(m.beta + 1.0);
+      q.nu = (3.0 * m.K0 - 2.0 * m.G0) / (2.0 * (3.0 * m.K0 + m.G0));
+      q.bonA = m.bonora_alpha * std::pow(m.D_crit - m.D0, 1.0 / m.bonora_alpha) /
+               std::log(m.eps_c / m.eps_th);
+      q.bonExp = (m.bonora_alpha - 1.0) / m.bonora_alpha;
+    }
+  }
+  P.cfl = opt->cfl;
+  P.phi_floor = opt->phi_floor;
+  P.weno_eps = opt->weno_eps;
+  P.c_min2 = 1.0e-6;
+  P.phi_fp64_cut = opt->phi_fp64_cut;
+}
+
+extern "C" {
+
+int32_t fv_state_fields(int32_t dim, int32_t n_mat, const fv_material* mats) {
+  if (dim < 1 || dim > 3 || n_mat < 1 || n_mat > 2 || !mats) return 0;
+  int ns = 0;
+  for (int l = 0; l < n_mat; ++l) ns += mats[l].kind == FV_MAT_SOLID;
+  const int nv = dim == 1 ? 3 : (dim == 2 ? 5 : 9);
+  return 2 * n_mat + 2 * ns + dim + 1 + nv + dim;
+}
+
+size_t fv_workspace_bytes(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
+                          const fv_material* mats, const fv_options* opt) {
+  int ns = 0;
+  std::string msg;
+  if (validate(n_inst, grids, n_mat, mats, opt, ns, msg) != FV_OK) return 0;
+  Ops o;
+  hipError_t he;
+  if (!select_ops(grids[0].dim, n_mat, ns, opt->precision, o, he, false)) return 0;
+  WsPlan W;
+  plan_ws(n_inst, grids, o, W);
+  return W.total;
+}
+
+int32_t fv_init(fv_ctx** out, int32_t n_inst, const fv_grid* grids, int32_t n_mat,
+                const fv_material* mats, const fv_options* opt, void* const* state,
+                const void* const* phi0, void* workspace, size_t workspace_bytes,
+                void* stream) {
+  if (!out) return fail(nullptr, FV_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ns = 0;
+  std::string msg;
+  int rc = validate(n_inst, grids, n_mat, mats, opt, ns, msg);
+  if (rc != FV_OK) return fail(nullptr, rc, msg);
+  if (!state || !phi0 || !workspace) return fail(nullptr, FV_EINVAL, "null device pointer");
+  for (int i = 0; i < n_inst; ++i)
+    if (!state[i] || !phi0[i]) return fail(nullptr, FV_EINVAL, "null state or phi0 pointer");
+  fv_ctx* c = new fv_ctx();
+  c->n_inst = n_inst;
+  c->dim = grids[0].dim;
+  c->nm = n_mat;
+  c->ns = ns;
+  c->precision = opt->precision;
+  c->stream = (hipStream_t)stream;
+  hipError_t he;
+  if (!select_ops(c->dim, n_mat, ns, opt->precision, c->ops, he)) {
+    delete c;
+    return fail(nullptr, FV_EINVAL, "unsupported dimension/material/precision combination");
+  }
+  if (he != hipSuccess) {
+    std::string m = std::string("hipFuncSetAttribute: ") + hipGetErrorString(he);
+    delete c;
+    return fail(nullptr, FV_EDEVICE, m);
+  }
+  fill_params(mats, n_mat, opt, c->P);
+  WsPlan W;
+  plan_ws(n_inst, grids, c->ops, W);
+  if (workspace_bytes < W.total) {
+    delete c;
+    return fail(nullptr, FV_ENOMEM, "workspace too small: need " + std::to_string(W.total) + " bytes");
+  }
+  char* ws = (char*)workspace;
+  c->insts.resize(n_inst);
+  std::vector<int> block_inst(W.total_blocks);
+  for (int i = 0; i < n_inst; ++i) {
+    const fv_grid& g = grids[i];
+    Inst& I = c->insts[i];
+    std::memset(&I, 0, sizeof(Inst));
+    I.U = state[i];
+    I.U1 = ws + W.u1[i];
+    I.U2 = ws + W.u2[i];
+    I.phi0 = phi0[i];
+    I.bacc = (double*)(ws + W.bacc[i]);
+    I.dts = (double*)(ws + W.dts[i]);
+    for (int k = 0; k < 3; ++k) {
+      I.n[k] = g.n[k];
+      I.lo[k] = g.lo[k];
+      I.dx[k] = (g.hi[k] - g.lo[k]) / g.n[k];
+      I.bc[k][0] = g.bc[k][0];
+      I.bc[k][1] = g.bc[k][1];
+    }
+    I.ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    I.tiles[0] = W.tiles[0][i]; I.tiles[1] = W.tiles[1][i]; I.tiles[2] = 1;
+    I.block_begin = W.block_begin[i];
+    I.nblocks = I.tiles[0] * I.tiles[1];
+    int off = 0;
+    for (int a = 0; a < 3; ++a) {
+      const int nt = a < g.dim ? (a == 0 ? g.n[1] * g.n[2] : g.n[0] * g.n[2]) : 0;
+      I.bacc_off[2 * a] = off; off += nt * c->ops.NC;
+      I.bacc_off[2 * a + 1] = off; off += nt * c->ops.NC;
+    }
+    for (int b = 0; b < I.nblocks; ++b) block_inst[I.block_begin + b] = i;
+  }
+  c->insts_d = (Inst*)(ws + W.insts);
+  c->block_inst_d = (int*)(ws + W.block_inst);
+  c->bins_d = (unsigned long long*)(ws + W.bins);
+  c->total_blocks = W.total_blocks;
+  rc = hip_check(c, hipMemcpyAsync(c->insts_d, c->insts.data(), sizeof(Inst) * n_inst,
+                                   hipMemcpyHostToDevice, c->stream), "copy instance table");
+  if (rc == FV_OK)
+    rc = hip_check(c, hipMemcpyAsync(c->block_inst_d, block_inst.data(), sizeof(int) * W.total_blocks,
+                                     hipMemcpyHostToDevice, c->stream), "copy block table");
+  if (rc == FV_OK) rc = hip_check(c, hipStreamSynchronize(c->stream), "init sync");
+  if (rc != FV_OK) {
+    g_init_error = c->err;
+    delete c;
+    return rc;
+  }
+  c->h_dt.assign(n_inst * DTS_SIZE, 0.0);
+  *out = c;
+  // zero accumulators and dt state
+  return fv_reset(c) == FV_OK ? FV_OK : FV_EDEVICE;
+}
+
+static int reset_inst(fv_ctx* c, int i) {
+  const Inst& I = c->insts[i];
+  const int q = (int)(c->step & 1);
+  size_t nb = 0;
+  for (int a = 0; a < c->dim; ++a) {
+    const int nt = a == 0 ? I.n[1] * I.n[2] : I.n[0] * I.n[2];
+    nb += 2 * (size_t)nt * c->ops.NC;
+  }
+  int rc = hip_check(c, hipMemsetAsync(I.bacc, 0, nb * sizeof(double), c->stream), "zero accumulators");
+  if (rc != FV_OK) return rc;
+  double* h = &c->h_dt[(size_t)i * DTS_SIZE];
+  for (int k = 0; k < DTS_SIZE; ++k) h[k] = 0.0;
+  h[DTS_TEND] = HUGE_VAL;
+  rc = hip_check(c, hipMemcpyAsync(I.dts, h, DTS_SIZE * sizeof(double), hipMemcpyHostToDevice, c->stream),
+                 "reset dt state");
+  if (rc != FV_OK) return rc;
+  c->ops.cfl(c, i, q);
+  return hip_check(c, hipGetLastError(), "cfl kernel");
+}
+
+int32_t fv_reset(fv_ctx* c) {
+  if (!c) return FV_EINVAL;
+  for (int i = 0; i < c->n_inst; ++i) {
+    const int rc = reset_inst(c, i);
+    if (rc != FV_OK) return rc;
+  }
+  return hip_check(c, hipStreamSynchronize(c->stream), "reset sync");
+}
+
+int32_t fv_load_primitive(fv_ctx* c, int32_t inst, const void* prim) {
+  if (!c) return FV_EINVAL;
+  if (inst < 0 || inst >= c->n_inst || !prim) return fail(c, FV_EINVAL, "bad instance or prim pointer");
+  c->ops.p2c(c, inst, (const double*)prim);
+  int rc = hip_check(c, hipGetLastError(), "prim_to_cons kernel");
+  if (rc != FV_OK) return rc;
+  rc = reset_inst(c, inst);
+  if (rc != FV_OK) return rc;
+  return hip_check(c, hipStreamSynchronize(c->stream), "load sync");
+}
+
+int32_t fv_primitive(fv_ctx* c, int32_t inst, void* prim) {
+  if (!c) return FV_EINVAL;
+  if (inst < 0 || inst >= c->n_inst || !prim) return fail(c, FV_EINVAL, "bad instance or prim pointer");
+  c->ops.c2p(c, inst, (double*)prim);
+  return hip_check(c, hipGetLastError(), "cons_to_prim kernel");
+}
+
+static int read_dts(fv_ctx* c, std::vector<double>& h) {
+  h.assign((size_t)c->n_inst * DTS_SIZE, 0.0);
+  for (int i = 0; i < c->n_inst; ++i) {
+    const int rc = hip_check(c, hipMemcpyAsync(&h[(size_t)i * DTS_SIZE], c->insts[i].dts,
+                                                DTS_SIZE * sizeof(double), hipMemcpyDeviceToHost,
+                                                c->stream), "read dt state");
+    if (rc != FV_OK) return rc;
+  }
+  int rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+  if (rc != FV_OK) return rc;
+  for (int i = 0; i < c->n_inst; ++i) {
+    unsigned flag;
+    std::memcpy(&flag, &h[(size_t)i * DTS_SIZE + DTS_FLAG], sizeof(unsigned));
+    if (flag & FLAG_NONPHYS)
+      return fail(c, FV_ENONPHYS, "non-physical state (NaN/Inf or non-positive density) in instance " +
+                                      std::to_string(i));
+  }
+  return FV_OK;
+}
+
+int32_t fv_cfl_dt(fv_ctx* c, double* dt_host) {
+  if (!c || !dt_host) return FV_EINVAL;
+  std::vector<double> h;
+  const int rc = read_dts(c, h);
+  if (rc != FV_OK) return rc;
+  const int q = (int)(c->step & 1);
+  for (int i = 0; i < c->n_inst; ++i) {
+    const double* d = &h[(size_t)i * DTS_SIZE];
+    double dt = d[DTS_DTFIX] > 0 ? d[DTS_DTFIX] : c->P.cfl / d[DTS_DTINV + q];
+    dt_host[i] = std::fmin(dt, d[DTS_TEND] - d[DTS_T + q]);
+  }
+  return FV_OK;
+}
+
+int32_t fv_time(fv_ctx* c, double* t_host) {
+  if (!c || !t_host) return FV_EINVAL;
+  std::vector<double> h;
+  const int rc = read_dts(c, h);
+  if (rc != FV_OK) return rc;
+  const int q = (int)(c->step & 1);
+  for (int i = 0; i < c->n_inst; ++i) t_host[i] = h[(size_t)i * DTS_SIZE + DTS_T + q];
+  return FV_OK;
+}
+
+int32_t fv_step(fv_ctx* c, const double* dt_host, int32_t n_steps, const double* t_end) {
+  if (!c) return FV_EINVAL;
+  if (n_steps < 0) return fail(c, FV_EINVAL, "n_steps < 0");
+  if (dt_host || t_end) {
+    // fixed step and end time of every instance (DTS_DTFIX, DTS_TEND)
+    int rc = hip_check(c, hipStreamSynchronize(c->stream), "sync before parameter write");
+    if (rc != FV_OK) return rc;
+    for (int i = 0; i < c->n_inst; ++i) {
+      if (dt_host && !(dt_host[i] >= 0)) return fail(c, FV_EINVAL, "dt must be >= 0");
+      double* h = &c->h_dt[(size_t)i * DTS_SIZE];
+      h[0] = t_end ? t_end[i] : 0.0;
+      h[1] = dt_host ? dt_host[i] : 0.0;
+      if (t_end) {
+        rc = hip_check(c, hipMemcpyAsync(c->insts[i].dts + DTS_TEND, &h[0], sizeof(double),
+                                         hipMemcpyHostToDevice, c->stream), "write t_end");
+        if (rc != FV_OK) return rc;
+      }
+      rc = hip_check(c, hipMemcpyAsync(c->insts[i].dts + DTS_DTFIX, &h[1], sizeof(double),
+                                       hipMemcpyHostToDevice, c->stream), "write dt");
+      if (rc != FV_OK) return rc;
+    }
+    rc = hip_check(c, hipStreamSynchronize(c->stream), "sync after parameter write");
+    if (rc != FV_OK) return rc;
+  }
+  for (int s = 0; s < n_steps; ++s) {
+    const int parity = (int)((c->step + s) & 1);
+    for (int st = 1; st <= 3; ++st) c->ops.stage(c, st, parity);
+  }
+  c->step += n_steps;
+  return hip_check(c, hipGetLastError(), "stage kernel launch");
+}
+
+int32_t fv_totals(fv_ctx* c, double* out) {
+  if (!c || !out) return FV_EINVAL;
+  std::vector<double> h;
+  int rc = read_dts(c, h);
+  if (rc != FV_OK) return rc;
+  const int NT = c->ops.NTOT, NC = c->ops.NC;
+  const int nsum = c->n_inst * NT * (1 + 2 * c->dim);
+  rc = hip_check(c, hipMemsetAsync(c->bins_d, 0, sizeof(unsigned long long) * NBINS * nsum, c->stream),
+                 "zero bins");
+  if (rc != FV_OK) return rc;
+  // interior fields: masses, momenta, energy; boundary sides: same rows of
+  // the conserved-flux vector (histories skipped)
+  const int nm = c->nm, ns = c->ns, dim = c->dim;
+  auto field_of = [&](int k) { return k < nm ? nm + k : (k < nm + dim ? 2 * nm + 2 * ns + (k - nm) : 2 * nm + 2 * ns + dim); };
+  auto flux_of = [&](int k) { return k < nm ? k : (k < nm + dim ? nm + 2 * ns + (k - nm) : nm + 2 * ns + dim); };
+  int slot = 0;
+  for (int i = 0; i < c->n_inst; ++i) {
+    const Inst& I = c->insts[i];
+    for (int k = 0; k < NT; ++k, ++slot) {
+      const int f = field_of(k);
+      const int nblk = (int)std::min<int64_t>((I.ncell + 255) / 256, 1024);
+      if (c->ops.elem == 8)
+        hipLaunchKernelGGL(exact_sum_kernel<double>, dim3(nblk), dim3(256), 0, c->stream,
+                           (const double*)I.U + (int64_t)f * I.ncell, I.ncell, (int64_t)1,
+                           c->bins_d + (size_t)slot * NBINS);
+      else
+        hipLaunchKernelGGL(exact_sum_kernel<float>, dim3(nblk), dim3(256), 0, c->stream,
+                           (const float*)I.U + (int64_t)f * I.ncell, I.ncell, (int64_t)1,
+                           c->bins_d + (size_t)slot * NBINS);
+    }
+    for (int a = 0; a < dim; ++a) {
+      const int nt = a == 0 ? I.n[1] * I.n[2] : I.n[0] * I.n[2];
+      for (int side = 0; side < 2; ++side) {
+        for (int k = 0; k < NT; ++k, ++slot) {
+          if (I.bc[a][side] == FV_BC_PERIODIC) continue;
+          const double* base = I.bacc + I.bacc_off[2 * a + side] + flux_of(k);
+          hipLaunchKernelGGL(exact_sum_kernel<double>, dim3(std::max(1, std::min(64, (nt + 255) / 256))),
+                             dim3(256), 0, c->stream, base, (int64_t)nt, (int64_t)NC,
+                             c->bins_d + (size_t)slot * NBINS);
+        }
+      }
+    }
+  }
+  rc = hip_check(c, hipGetLastError(), "exact sum kernels");
+  if (rc != FV_OK) return rc;
+  std::vector<unsigned long long> bins((size_t)NBINS * nsum);
+  rc = hip_check(c, hipMemcpyAsync(bins.data(), c->bins_d, bins.size() * sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, c->stream), "read bins");
+  if (rc != FV_OK) return rc;
+  rc = hip_check(c, hipStreamSynchronize(c->stream), "totals sync");
+  if (rc != FV_OK) return rc;
+  slot = 0;
+  for (int i = 0; i < c->n_inst; ++i) {
+    const Inst& I = c->insts[i];
+    const double vol = I.dx[0] * I.dx[1] * I.dx[2];
+    double* o = out + (size_t)i * 2 * NT;
+    for (int k = 0; k < NT; ++k, ++slot) o[k] = bins_to_double(&bins[(size_t)slot * NBINS]) * vol;
+    // boundary: per side exact sum times face area, then an exact sum of the
+    // per-side values
+    std::vector<std::vector<double>> per(NT);
+    for (int a = 0; a < dim; ++a) {
+      const double area = a == 0 ? I.dx[1] * I.dx[2] : I.dx[0] * I.dx[2];
+      for (int side = 0; side < 2; ++side)
+        for (int k = 0; k < NT; ++k, ++slot)
+          per[k].push_back(bins_to_double(&bins[(size_t)slot * NBINS]) * area);
+    }
+    for (int k = 0; k < NT; ++k) {
+      unsigned long long hb[NBINS] = {0};
+      for (double v : per[k]) {
+        // host copy of bin_add
+        uint64_t bits;
+        std::memcpy(&bits, &v, 8);
+        const int ex = (int)((bits >> 52) & 0x7FF);
+        uint64_t m = bits & ((1ull << 52) - 1);
+        if (ex == 0x7FF) continue;
+        int shift = 0;
+        if (ex != 0) { m |= 1ull << 52; shift = ex - 1; }
+        if (!m) continue;
+        const int k0 = shift >> 5, off = shift & 31;
+        const uint64_t t0 = (m & 0xFFFFFFFFull) << off, t1 = (m >> 32) << off;
+        const uint64_t c0 = t0 & 0xFFFFFFFFull, c1 = (t0 >> 32) + (t1 & 0xFFFFFFFFull), c2 = t1 >> 32;
+        const bool neg = bits >> 63;
+        hb[k0] += neg ? 0ull - c0 : c0;
+        hb[k0 + 1] += neg ? 0ull - c1 : c1;
+        hb[k0 + 2] += neg ? 0ull - c2 : c2;
+      }
+      o[NT + k] = bins_to_double(hb);
+    }
+  }
+  return FV_OK;
+}
+
+const char* fv_last_error(const fv_ctx* c) {
+  return c ? c->err.c_str() : g_init_error.c_str();
+}
+
+void fv_destroy(fv_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  delete c;
+}
+
+}  // extern "C"

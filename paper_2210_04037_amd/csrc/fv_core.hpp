@@ -1,0 +1,419 @@
+// Device math of the fracture hot path: closures, mixture, kinematics,
+// reconstruction, HLLC with the void-opening modifier, source step.
+//
+// Everything here is __host__ __device__ so that the per-thread phases of
+// the stage kernel can also be stepped on the CPU for debugging; the
+// library itself only ever runs them on the GPU.
+//
+// References are to arXiv 2210.04037 (Wallis, Barton, Nikiforakis):
+// Section 2.1 evolution equations, Section 2.2 thermodynamics and damage,
+// Section 2.3 closure models, Section 2.4 perturbation field, Section 3.1
+// fracture, Section 3.2 Lagrangian coordinates.
+#pragma once
+
+#include <stdint.h>
+#include <math.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define FV_HD __host__ __device__ __forceinline__
+#else
+#define FV_HD inline
+#endif
+
+namespace fv {
+
+// ----------------------------------------------------------------------------
+// scalar helpers (double and float overloads)
+// ----------------------------------------------------------------------------
+FV_HD double m_sqrt(double x) { return sqrt(x); }
+FV_HD float m_sqrt(float x) { return sqrtf(x); }
+FV_HD double m_log(double x) { return log(x); }
+FV_HD float m_log(float x) { return logf(x); }
+FV_HD double m_exp(double x) { return exp(x); }
+FV_HD float m_exp(float x) { return expf(x); }
+FV_HD double m_pow(double x, double y) { return pow(x, y); }
+FV_HD float m_pow(float x, float y) { return powf(x, y); }
+FV_HD double m_atanh(double x) { return atanh(x); }
+FV_HD float m_atanh(float x) { return atanhf(x); }
+FV_HD double m_abs(double x) { return fabs(x); }
+FV_HD float m_abs(float x) { return fabsf(x); }
+template <class C> FV_HD C m_min(C a, C b) { return a < b ? a : b; }
+template <class C> FV_HD C m_max(C a, C b) { return a > b ? a : b; }
+template <class C> FV_HD C m_clamp(C v, C lo, C hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// x^e with a fast path for small integer exponents (ei > 0).
+template <class C> FV_HD C powi_or(C x, C e, int ei) {
+  if (ei > 0) {
+    C r = x;
+    for (int k = 1; k < ei; ++k) r *= x;
+    return r;
+  }
+  return m_pow(x, e);
+}
+
+// ----------------------------------------------------------------------------
+// material and run parameters (passed by value to kernels)
+// ----------------------------------------------------------------------------
+struct MatP {
+  int kind;       // 0 solid (Romenskii), 1 ideal gas
+  int alpha_i;    // alpha as a small integer, else 0
+  int beta1_i;    // beta + 1 as a small integer, else 0
+  int pad_;
+  double rho0, K0, alpha, G0, beta, Gamma0;
+  double yield, Dcrit, D0, eps_th, eps_c, balpha, nhard, pgate;
+  // host-derived constants
+  double Dcrit_eff;  // D_crit (1 - 1e-9): critical test up to the rounding of
+                     // the advected ratio (phi rho D)/(phi rho)
+  double invGamma;   // 1 / Gamma0
+  double nu;         // Poisson ratio of the undamaged moduli
+  double bonA;       // alpha_B (Dc - D0)^(1/alpha_B) / ln(eps_c / eps_th)
+  double bonExp;     // (alpha_B - 1) / alpha_B
+};
+
+struct Params {
+  MatP mat[2];
+  double cfl;
+  double phi_floor;
+  double weno_eps;
+  double c_min2;
+  double phi_fp64_cut;
+};
+
+// ----------------------------------------------------------------------------
+// field layout of the conserved state (Section 2.1 equation order)
+// ----------------------------------------------------------------------------
+template <int DIM, int NM, int NS>
+struct Lay {
+  static constexpr int NV = DIM == 1 ? 3 : (DIM == 2 ? 5 : 9);
+  static constexpr int NH = DIM == 1 ? 3 : (DIM == 2 ? 4 : 6);
+  // conserved state
+  static constexpr int PHI = 0;
+  static constexpr int MASS = NM;
+  static constexpr int HIST = 2 * NM;
+  static constexpr int MOM = 2 * NM + 2 * NS;
+  static constexpr int ENE = MOM + DIM;
+  static constexpr int VB = ENE + 1;
+  static constexpr int XC = VB + NV;
+  static constexpr int S = XC + DIM;
+  // conserved-flux vector: masses, histories, momenta, energy
+  static constexpr int NC = NM + 2 * NS + DIM + 1;
+  static constexpr int C_MOM = NM + 2 * NS;
+  static constexpr int C_ENE = C_MOM + DIM;
+  // reconstructed primitives
+  static constexpr int R_PHI = 0;
+  static constexpr int R_RHO = NM;
+  static constexpr int R_HIST = 2 * NM;
+  static constexpr int R_U = 2 * NM + 2 * NS;
+  static constexpr int R_P = R_U + DIM;
+  static constexpr int R_H = R_P + 1;
+  static constexpr int R_V = R_H + NH;
+  static constexpr int NR = R_V + NV;
+  // extra per-cell tile values
+  static constexpr int W_X = NR;
+  static constexpr int W_SIG = NR + DIM;   // sigma_aa per direction
+  static constexpr int W_CRIT = NR + 2 * DIM;
+  static constexpr int NW = W_CRIT + 1;
+  // per-face data
+  static constexpr int Q_F = 0;
+  static constexpr int Q_UF = NC;
+  static constexpr int Q_UT = NC + 1;          // DIM-1 tangential comps
+  static constexpr int Q_PHI = Q_UT + (DIM - 1);
+  static constexpr int Q_X = Q_PHI + NM;
+  static constexpr int Q_V = Q_X + DIM;
+  static constexpr int Q_OS = Q_V + NV;        // 0 normal, 1 closed
+  static constexpr int Q_USL = Q_OS + 1;
+  static constexpr int Q_USR = Q_OS + 2;
+  static constexpr int NQ = Q_USR + 1;
+};
+
+// stored (i, j) components of the unimodular stretch
+template <int DIM> FV_HD int vb_i(int q) {
+  if (DIM == 1) return q;
+  if (DIM == 2) { const int t[5] = {0, 0, 1, 1, 2}; return t[q]; }
+  return q / 3;
+}
+template <int DIM> FV_HD int vb_j(int q) {
+  if (DIM == 1) return q;
+  if (DIM == 2) { const int t[5] = {0, 1, 0, 1, 2}; return t[q]; }
+  return q % 3;
+}
+// independent components of the symmetric Hencky strain
+template <int DIM> FV_HD int hk_i(int q) {
+  if (DIM == 1) return q;
+  if (DIM == 2) { const int t[4] = {0, 0, 1, 2}; return t[q]; }
+  const int t[6] = {0, 0, 0, 1, 1, 2}; return t[q];
+}
+template <int DIM> FV_HD int hk_j(int q) {
+  if (DIM == 1) return q;
+  if (DIM == 2) { const int t[4] = {0, 1, 1, 2}; return t[q]; }
+  const int t[6] = {0, 1, 2, 1, 2, 2}; return t[q];
+}
+
+// ----------------------------------------------------------------------------
+// single-material closures (Sections 2.2, 2.3)
+// ----------------------------------------------------------------------------
+// Reference terms of one material in Mie-Grueneisen form, as products with
+// the phasic density so that they stay finite for rho -> 0:
+//   rho e_ref = (1-D)(rho e~_c + G~ J^2),  p_ref = (1-D)(p~_c + beta G~ J^2),
+//   rho dp_ref/drho = (1-D)(rho dp~_c/drho + beta (beta+1) G~ J^2),
+// with the Romenskii cold energy e~_c = K0/(2 rho0 a^2)(eta^a - 1)^2 (the
+// denominator read as 2 rho0 a^2 so that a -> 0 is the log EOS) and shear
+// modulus G~ = G0 eta^(beta+1).  Gas: all zero.
+template <class C>
+struct RefT { C rho_eref, pref, rho_dpref, G; };
+
+template <class C>
+FV_HD RefT<C> ref_terms(const MatP& m, C rho, C J2, C D) {
+  RefT<C> r;
+  if (m.kind != 0) { r.rho_eref = 0; r.pref = 0; r.rho_dpref = 0; r.G = 0; return r; }
+  const C a = (C)m.alpha;
+  const C eta = rho / (C)m.rho0;
+  const C ea = powi_or(eta, a, m.alpha_i);
+  const C ea1 = ea * eta;
+  const C K0 = (C)m.K0;
+  const C rho_ec = rho * K0 / ((C)2 * (C)m.rho0 * a * a) * (ea - (C)1) * (ea - (C)1);
+  const C pc = K0 / a * ea1 * (ea - (C)1);
+  const C rho_dpc = K0 / a * ea1 * (((C)2 * a + (C)1) * ea - (a + (C)1));
+  const C Gt = (C)m.G0 * powi_or(eta, (C)m.beta + (C)1, m.beta1_i);
+  const C b = (C)m.beta;
+  const C w = (C)1 - D;
+  r.rho_eref = w * (rho_ec + Gt * J2);
+  r.pref = w * (pc + b * Gt * J2);
+  r.rho_dpref = w * (rho_dpc + b * (b + (C)1) * Gt * J2);
+  r.G = w * Gt;
+  return r;
+}
+
+template <class C>
+FV_HD C shear_modulus_undamaged(const MatP& m, C rho) {
+  return (C)m.G0 * powi_or(rho / (C)m.rho0, (C)m.beta + (C)1, m.beta1_i);
+}
+
+// ----------------------------------------------------------------------------
+// mixture (Allaire-type closure under mechanical and thermal equilibrium)
+// ----------------------------------------------------------------------------
+// p = [rho e - sum phi_l rho_l e_ref,l + sum phi_l p_ref,l / Gamma_l]
+//     / sum phi_l / Gamma_l.
+// The void carries no stress: sigma = -(1-nu) p I + 2 G_mix dev H with
+// G_mix = sum phi_l G_l; c^2 = (1-nu) sum phi_l xi_l rho_l c_l^2 / (xi rho)
+// + (4/3) G_mix / rho.
+template <int NM, int NS, class C>
+struct Mix {
+  RefT<C> t[NM];
+  C xi;
+};
+
+template <int NM, int NS, class C>
+FV_HD void mix_terms(const Params& P, const C* phi, const C* rho_l, const C* D,
+                     C J2, Mix<NM, NS, C>& mx) {
+  mx.xi = 0;
+#pragma unroll
+  for (int l = 0; l < NM; ++l) {
+    const C Dl = l < NS ? D[l < NS ? l : 0] : (C)0;
+    mx.t[l] = ref_terms<C>(P.mat[l], rho_l[l], J2, Dl);
+    mx.xi += phi[l] * (C)P.mat[l].invGamma;
+  }
+}
+
+template <int NM, int NS, class C>
+FV_HD C mix_pressure(const Params& P, const C* phi, const Mix<NM, NS, C>& mx,
+                     C rho_e) {
+  C num = rho_e;
+#pragma unroll
+  for (int l = 0; l < NM; ++l)
+    num = num - phi[l] * mx.t[l].rho_eref + phi[l] * mx.t[l].pref * (C)P.mat[l].invGamma;
+  return num / mx.xi;
+}
+
+template <int NM, int NS, class C>
+FV_HD C mix_energy(const Params& P, const C* phi, const Mix<NM, NS, C>& mx, C p) {
+  C re = mx.xi * p;
+#pragma unroll
+  for (int l = 0; l < NM; ++l)
+    re = re + phi[l] * mx.t[l].rho_eref - phi[l] * mx.t[l].pref * (C)P.mat[l].invGamma;
+  return re;
+}
+
+template <int NM, class C>
+FV_HD C solid_frac(const C* phi) {
+  C s = 0;
+#pragma unroll
+  for (int l = 0; l < NM; ++l) s += phi[l];
+  return m_clamp(s, (C)0, (C)1);
+}
+
+// returns c, writes G_mix
+template <int NM, int NS, class C>
+FV_HD C mix_sound(const Params& P, const C* phi, const Mix<NM, NS, C>& mx, C p,
+                  C rho, C& Gmix) {
+  C acc = 0;
+  Gmix = 0;
+#pragma unroll
+  for (int l = 0; l < NM; ++l) {
+    const C g = (C)P.mat[l].Gamma0;
+    acc += phi[l] * (C)P.mat[l].invGamma * (mx.t[l].rho_dpref + (g + (C)1) * (p - mx.t[l].pref));
+    Gmix += phi[l] * mx.t[l].G;
+  }
+  const C cb2 = solid_frac<NM>(phi) * acc / (mx.xi * rho);
+  const C c2 = m_max(cb2, (C)0) + (C)(4.0 / 3.0) * Gmix / rho;
+  return m_sqrt(m_max(c2, (C)P.c_min2));
+}
+
+// ----------------------------------------------------------------------------
+// kinematics: deviatoric Hencky strain of Vbar (Section 2.2, dev H = ln Vbar)
+// taken as 1/2 ln(Vbar Vbar^T) with the trace removed.
+// ----------------------------------------------------------------------------
+// log of a symmetric positive-definite 2x2 matrix [[b00, b01], [b01, b11]]:
+// log M = 1/2 ln(det M) I + g (M - m I), m = tr/2, r = eigen half-gap,
+// g = (ln l1 - ln l2)/(l1 - l2) = atanh(r/m)/r (series for small r/m).
+template <class C>
+FV_HD void sym2_log(C b00, C b01, C b11, C& l00, C& l01, C& l11) {
+  const C m = (C)0.5 * (b00 + b11);
+  const C d = (C)0.5 * (b00 - b11);
+  const C r = m_sqrt(d * d + b01 * b01);
+  const C hld = (C)0.5 * m_log(b00 * b11 - b01 * b01);
+  const C x = r / m;
+  const C xs = sizeof(C) == 8 ? (C)1e-3 : (C)5e-2;
+  C g;
+  if (x < xs) {
+    const C x2 = x * x;
+    g = ((C)1 + x2 * ((C)(1.0 / 3.0) + x2 * ((C)0.2 + x2 * (C)(1.0 / 7.0)))) / m;
+  } else {
+    g = m_atanh(x) / r;
+  }
+  l00 = hld + g * d;
+  l11 = hld - g * d;
+  l01 = g * b01;
+}
+
+// exp of a symmetric 2x2 matrix [[a00, a01], [a01, a11]]:
+// exp(A) = e^m [cosh(r) I + sinh(r)/r (A - m I)].
+template <class C>
+FV_HD void sym2_exp(C a00, C a01, C a11, C& e00, C& e01, C& e11) {
+  const C m = (C)0.5 * (a00 + a11);
+  const C d = (C)0.5 * (a00 - a11);
+  const C r = m_sqrt(d * d + a01 * a01);
+  const C em = m_exp(m);
+  C ch, sh;
+  const C rs = sizeof(C) == 8 ? (C)1e-3 : (C)5e-2;
+  if (r < rs) {
+    const C r2 = r * r;
+    ch = (C)1 + r2 * ((C)0.5 + r2 * ((C)(1.0 / 24.0) + r2 * (C)(1.0 / 720.0)));
+    sh = (C)1 + r2 * ((C)(1.0 / 6.0) + r2 * ((C)(1.0 / 120.0) + r2 * (C)(1.0 / 5040.0)));
+  } else {
+    const C ep = m_exp(r), en = m_exp(-r);
+    ch = (C)0.5 * (ep + en);
+    sh = (C)0.5 * (ep - en) / r;
+  }
+  e00 = em * (ch + sh * d);
+  e11 = em * (ch - sh * d);
+  e01 = em * sh * a01;
+}
+
+// dev H (full symmetric 3x3, zeros where the dimension keeps them zero)
+template <int DIM, class C>
+FV_HD void hencky(const C V[3][3], C H[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) H[i][j] = 0;
+  if (DIM == 1) {
+    const C h0 = m_log(m_abs(V[0][0])), h1 = m_log(m_abs(V[1][1])), h2 = m_log(m_abs(V[2][2]));
+    const C mm = (h0 + h1 + h2) / (C)3;
+    H[0][0] = h0 - mm; H[1][1] = h1 - mm; H[2][2] = h2 - mm;
+  } else {
+    const C b00 = V[0][0] * V[0][0] + V[0][1] * V[0][1];
+    const C b01 = V[0][0] * V[1][0] + V[0][1] * V[1][1];
+    const C b11 = V[1][0] * V[1][0] + V[1][1] * V[1][1];
+    C l00, l01, l11;
+    sym2_log(b00, b01, b11, l00, l01, l11);
+    const C h00 = (C)0.5 * l00, h11 = (C)0.5 * l11, h01 = (C)0.5 * l01;
+    const C h22 = m_log(m_abs(V[2][2]));
+    const C mm = (h00 + h11 + h22) / (C)3;
+    H[0][0] = h00 - mm; H[1][1] = h11 - mm; H[2][2] = h22 - mm;
+    H[0][1] = h01; H[1][0] = h01;
+  }
+}
+
+template <int DIM, class C>
+FV_HD C J2_of(const C H[3][3]) {
+  C s = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) s += H[i][j] * H[i][j];
+  return s;
+}
+
+// symmetric unimodular stretch exp(H) for a trace-free symmetric H
+template <int DIM, class C>
+FV_HD void stretch_from_log(const C H[3][3], C V[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) V[i][j] = 0;
+  if (DIM == 1) {
+    V[0][0] = m_exp(H[0][0]); V[1][1] = m_exp(H[1][1]); V[2][2] = m_exp(H[2][2]);
+  } else {
+    C e00, e01, e11;
+    sym2_exp(H[0][0], H[0][1], H[1][1], e00, e01, e11);
+    V[0][0] = e00; V[0][1] = e01; V[1][0] = e01; V[1][1] = e11;
+    V[2][2] = m_exp(H[2][2]);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// limiter and WENO3 (reconstruction readings of Section 3 / Section 3.2.1)
+// ----------------------------------------------------------------------------
+template <class C> FV_HD C van_leer(C dm, C dp) {
+  const C pr = dm * dp;
+  return pr > (C)0 ? (C)2 * pr / (dm + dp) : (C)0;
+}
+
+// face value from the left (upwind cell q0; stencil qm, q0, q1)
+template <class C> FV_HD C weno3_left(C qm, C q0, C q1, C eps) {
+  const C p0 = (C)-0.5 * qm + (C)1.5 * q0;
+  const C p1 = (C)0.5 * q0 + (C)0.5 * q1;
+  const C b0 = (q0 - qm) * (q0 - qm);
+  const C b1 = (q1 - q0) * (q1 - q0);
+  const C a0 = (C)(1.0 / 3.0) / ((eps + b0) * (eps + b0));
+  const C a1 = (C)(2.0 / 3.0) / ((eps + b1) * (eps + b1));
+  return (a0 * p0 + a1 * p1) / (a0 + a1);
+}
+
+// ----------------------------------------------------------------------------
+// Bonora damage (Section 2.2)
+// ----------------------------------------------------------------------------
+FV_HD double triaxiality(const MatP& m, double p, double seq, double rho) {
+  const double q = p / seq;
+  return 3.0 * (1.0 - 2.0 * m.nu) * (m.rho0 / rho) * q * q + (2.0 / 3.0) * (1.0 + m.nu);
+}
+
+FV_HD double eps_threshold(const MatP& m, double R) {
+  const double et = m.eps_th, ec = m.eps_c, n = m.nhard;
+  const double num = pow(ec, 2.0 * n) - pow(et, 2.0 * n);
+  const double den = pow(ec, 2.0 * n / R) - pow(et, 2.0 * n / R);
+  return pow(et, 1.0 / R) / pow(R, 1.0 / n) * pow(num / den, 1.0 / (2.0 * n));
+}
+
+FV_HD double bonora_rate(const MatP& m, double D, double eps, double R) {
+  if (D >= m.Dcrit) return 0.0;
+  const double y = m.Dcrit - D;
+  return m.bonA * R * pow(y, m.bonExp) / eps;
+}
+
+// classical RK4 in eps_p over [eps0, eps0 + h], every argument clamped
+FV_HD double damage_rk4(const MatP& m, double D, double eps0, double h, double R) {
+  const double Dc = m.Dcrit;
+  auto cl = [Dc](double v) { return v < 0.0 ? 0.0 : (v > Dc ? Dc : v); };
+  const double k1 = bonora_rate(m, D, eps0, R);
+  const double k2 = bonora_rate(m, cl(D + 0.5 * h * k1), eps0 + 0.5 * h, R);
+  const double k3 = bonora_rate(m, cl(D + 0.5 * h * k2), eps0 + 0.5 * h, R);
+  const double k4 = bonora_rate(m, cl(D + h * k3), eps0 + h, R);
+  return cl(D + h / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4));
+}
+
+}  // namespace fv

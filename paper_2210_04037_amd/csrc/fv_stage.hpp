@@ -1,0 +1,821 @@
+// One SSP-RK3 stage of the hyperbolic update on an LDS tile, plus the source
+// step and CFL reduction fused into the third stage.
+//
+// A block owns a TX x TY tile of output cells.  Phases (barriers between):
+//   1 load   : every tile cell and its two-cell halo is read from HBM once,
+//              converted to primitives and stored in LDS (structure of
+//              arrays, one row per variable);
+//   2 faces  : per direction, every face of the tile is computed exactly once
+//              (MUSCL + HLLC + void-opening modifier) into an LDS face buffer;
+//   3 gather : each thread adds the two faces of its own cell in that
+//              direction to its update accumulator (registers);
+//   4 finish : RK combination, volume-fraction clamp, and in stage 3 the
+//              plastic/damage source step, the non-physical check and the
+//              block maximum of the CFL wave-speed sum.
+// The phases are written as per-thread functions so that the same code can
+// be stepped on the CPU; on the GPU they run inside stage_kernel.
+#pragma once
+
+#include "fv_core.hpp"
+
+namespace fv {
+
+enum { BC_TRANSMISSIVE = 0, BC_FREE = 1, BC_PERIODIC = 2 };
+
+constexpr double TIE_REL = 1.0e-12;
+
+// Per-instance descriptor (device memory).
+struct Inst {
+  void* U;          // state (caller-owned), in/out
+  void* U1;         // stage-1 result (workspace)
+  void* U2;         // stage-2 result (workspace)
+  const void* phi0; // perturbation field on the initial mesh
+  double* bacc;     // outward boundary flux accumulators
+  double* dts;      // dt state, see DTS_* below
+  int n[3];
+  int tiles[3];
+  int bc[3][2];
+  int block_begin;
+  int nblocks;
+  int bacc_off[6];  // offset (in doubles) of each boundary side's slots
+  double lo[3];
+  double dx[3];
+  int64_t ncell;
+};
+
+// dt state layout (doubles): dtinv[2] (bits of non-negative doubles, so an
+// unsigned integer max is the floating max), t[2], t_end, dt_fixed, flags.
+enum { DTS_DTINV = 0, DTS_T = 2, DTS_TEND = 4, DTS_DTFIX = 5, DTS_FLAG = 6,
+       DTS_SIZE = 8 };
+enum { FLAG_NONPHYS = 1 };
+
+template <int DIM, int TX, int TY>
+struct Tile {
+  static constexpr int HX = TX + 4;
+  static constexpr int HY = DIM >= 2 ? TY + 4 : 1;
+  static constexpr int NCELL = HX * HY;
+  static constexpr int NT = TX * TY;
+  static constexpr int NFX = (TX + 1) * TY;
+  static constexpr int NFY = DIM >= 2 ? TX * (TY + 1) : 0;
+  static constexpr int NFACE = NFX > NFY ? NFX : NFY;
+  FV_HD static int cell(int hx, int hy) { return hy * HX + hx; }
+};
+
+template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
+struct Stage {
+  using L = Lay<DIM, NM, NS>;
+  using TL = Tile<DIM, TX, TY>;
+  static constexpr int S = L::S;
+  static constexpr int NW = L::NW;
+  static constexpr int NQ = L::NQ;
+  static constexpr int NC = L::NC;
+
+  // LDS layout: W[NW][NCELL] then FB[NQ][NFACE] (both of type C)
+  static constexpr size_t smem_elems() {
+    return (size_t)NW * TL::NCELL + (size_t)NQ * TL::NFACE;
+  }
+  static constexpr size_t smem_bytes() { return smem_elems() * sizeof(C); }
+
+  struct Ctx {
+    const Inst* I;
+    Params P;
+    int stage;      // 1, 2, 3
+    int parity;     // step & 1
+    int bx, by;     // tile coordinates
+    C dt;
+    const T* src;   // stage input
+    const T* base;  // U^n
+    T* out;         // stage output
+  };
+
+  FV_HD static int map_index(int g, int n, int bclo, int bchi) {
+    if (g < 0) return bclo == BC_PERIODIC ? g + n : 0;
+    if (g >= n) return bchi == BC_PERIODIC ? g - n : n - 1;
+    return g;
+  }
+
+  // ---------------------------------------------------------------- phase 1
+  FV_HD static void load_cell(const Ctx& cx, C* sm, int tc) {
+    const Inst& I = *cx.I;
+    const int hx = tc % TL::HX;
+    const int hy = tc / TL::HX;
+    const int gx = map_index(cx.bx * TX + hx - 2, I.n[0], I.bc[0][0], I.bc[0][1]);
+    int gy = 0;
+    if (DIM >= 2) gy = map_index(cx.by * TY + hy - 2, I.n[1], I.bc[1][0], I.bc[1][1]);
+    const int64_t g = (int64_t)gy * I.n[0] + gx;
+    C U[S];
+#pragma unroll
+    for (int f = 0; f < S; ++f) U[f] = (C)cx.src[(int64_t)f * I.ncell + g];
+    C* W = sm;
+    C phi[NM], rho_l[NM], mass[NM], D[NS > 0 ? NS : 1], eps[NS > 0 ? NS : 1];
+    C rho = 0;
+#pragma unroll
+    for (int l = 0; l < NM; ++l) {
+      phi[l] = U[L::PHI + l];
+      mass[l] = m_max(U[L::MASS + l], (C)0);
+      rho_l[l] = mass[l] / phi[l];
+      rho += mass[l];
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const C ms = U[L::MASS + s];
+      eps[s] = ms > (C)0 ? U[L::HIST + 2 * s] / ms : (C)0;
+      D[s] = ms > (C)0 ? U[L::HIST + 2 * s + 1] / ms : (C)0;
+    }
+    C u[3] = {0, 0, 0};
+    C ke = 0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) { u[k] = U[L::MOM + k] / rho; ke += u[k] * u[k]; }
+    const C rho_e = U[L::ENE] - (C)0.5 * rho * ke;
+    C V[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int q = 0; q < L::NV; ++q) V[vb_i<DIM>(q)][vb_j<DIM>(q)] = U[L::VB + q];
+    C H[3][3];
+    hencky<DIM, C>(V, H);
+    const C J2 = J2_of<DIM, C>(H);
+    Mix<NM, NS, C> mx;
+    mix_terms<NM, NS, C>(cx.P, phi, rho_l, D, J2, mx);
+    const C p = mix_pressure<NM, NS, C>(cx.P, phi, mx, rho_e);
+    C Gmix = 0;
+#pragma unroll
+    for (int l = 0; l < NM; ++l) Gmix += phi[l] * mx.t[l].G;
+    const C sf = solid_frac<NM, C>(phi);
+    C crit = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (D[s] >= (C)cx.P.mat[s].Dcrit_eff) crit = 1;
+    const int NCELL = TL::NCELL;
+#pragma unroll
+    for (int l = 0; l < NM; ++l) {
+      W[(L::R_PHI + l) * NCELL + tc] = phi[l];
+      W[(L::R_RHO + l) * NCELL + tc] = rho_l[l];
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      W[(L::R_HIST + 2 * s) * NCELL + tc] = eps[s];
+      W[(L::R_HIST + 2 * s + 1) * NCELL + tc] = D[s];
+    }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) W[(L::R_U + k) * NCELL + tc] = u[k];
+    W[L::R_P * NCELL + tc] = p;
+#pragma unroll
+    for (int q = 0; q < L::NH; ++q) W[(L::R_H + q) * NCELL + tc] = H[hk_i<DIM>(q)][hk_j<DIM>(q)];
+#pragma unroll
+    for (int q = 0; q < L::NV; ++q) W[(L::R_V + q) * NCELL + tc] = U[L::VB + q];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      W[(L::W_X + k) * NCELL + tc] = U[L::XC + k];
+      W[(L::W_SIG + k) * NCELL + tc] = (C)2 * Gmix * H[k][k] - sf * p;
+    }
+    W[L::W_CRIT * NCELL + tc] = crit;
+  }
+
+  // ---------------------------------------------------------------- phase 2
+  struct Side {
+    C phi[NM], rho_l[NM], eps[NS > 0 ? NS : 1], D[NS > 0 ? NS : 1];
+    C u[3], p, H[3][3], V[3][3];
+    C rho, rhoE, c, t[3];
+    C Uc[NC];
+  };
+
+  FV_HD static void unpack_side(const Params& P, const C* w, int a, Side& s) {
+#pragma unroll
+    for (int l = 0; l < NM; ++l) { s.phi[l] = w[L::R_PHI + l]; s.rho_l[l] = w[L::R_RHO + l]; }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) { s.eps[q] = w[L::R_HIST + 2 * q]; s.D[q] = w[L::R_HIST + 2 * q + 1]; }
+    s.u[0] = s.u[1] = s.u[2] = 0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) s.u[k] = w[L::R_U + k];
+    s.p = w[L::R_P];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) { s.H[i][j] = 0; s.V[i][j] = 0; }
+#pragma unroll
+    for (int q = 0; q < L::NH; ++q) {
+      const int i = hk_i<DIM>(q), j = hk_j<DIM>(q);
+      s.H[i][j] = w[L::R_H + q];
+      s.H[j][i] = w[L::R_H + q];
+    }
+    const C tr = (s.H[0][0] + s.H[1][1] + s.H[2][2]) / (C)3;
+    s.H[0][0] -= tr; s.H[1][1] -= tr; s.H[2][2] -= tr;
+#pragma unroll
+    for (int q = 0; q < L::NV; ++q) s.V[vb_i<DIM>(q)][vb_j<DIM>(q)] = w[L::R_V + q];
+    // face EOS: energy from the reconstructed pressure
+    const C J2 = J2_of<DIM, C>(s.H);
+    Mix<NM, NS, C> mx;
+    mix_terms<NM, NS, C>(P, s.phi, s.rho_l, s.D, J2, mx);
+    C rho = 0;
+#pragma unroll
+    for (int l = 0; l < NM; ++l) rho += s.phi[l] * s.rho_l[l];
+    s.rho = rho;
+    const C rho_e = mix_energy<NM, NS, C>(P, s.phi, mx, s.p);
+    s.rhoE = rho_e + (C)0.5 * rho * (s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2]);
+    C Gmix;
+    s.c = mix_sound<NM, NS, C>(P, s.phi, mx, s.p, rho, Gmix);
+    const C sf = solid_frac<NM, C>(s.phi);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) s.t[i] = (C)2 * Gmix * s.H[i][a] - (i == a ? sf * s.p : (C)0);
+#pragma unroll
+    for (int l = 0; l < NM; ++l) s.Uc[l] = s.phi[l] * s.rho_l[l];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      s.Uc[NM + 2 * q] = s.phi[q] * s.rho_l[q] * s.eps[q];
+      s.Uc[NM + 2 * q + 1] = s.phi[q] * s.rho_l[q] * s.D[q];
+    }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) s.Uc[L::C_MOM + k] = rho * s.u[k];
+    s.Uc[L::C_ENE] = s.rhoE;
+  }
+
+  // physical flux U u_n - (0, 0, sigma n, u . sigma n)  (Section 2.1)
+  FV_HD static void phys_flux(const Side& s, int a, C* F) {
+    const C un = s.u[a];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) F[q] = s.Uc[q] * un;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) F[L::C_MOM + k] -= s.t[k];
+    F[L::C_ENE] -= s.u[0] * s.t[0] + s.u[1] * s.t[1] + s.u[2] * s.t[2];
+  }
+
+  FV_HD static void star_flux(const Side& s, int a, C SK, C Ss, const C* FK, C* Fs) {
+    const C un = s.u[a];
+    const C chi = (SK - un) / (SK - Ss);
+    C Us[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) Us[q] = s.Uc[q] * chi;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+      Us[L::C_MOM + k] = chi * s.rho * (s.u[k] + (k == a ? Ss - un : (C)0));
+    Us[L::C_ENE] = chi * (s.rhoE + (Ss - un) * (s.rho * Ss - s.t[a] / (SK - un)));
+#pragma unroll
+    for (int q = 0; q < NC; ++q) Fs[q] = FK[q] + SK * (Us[q] - s.Uc[q]);
+  }
+
+  // Face a of the tile: W pointers of the four stencil cells (cm, c0 | c1, c2)
+  // and the face's position relative to the domain boundary.
+  FV_HD static void compute_face(const Ctx& cx, const C* sm, int a, int cm, int c0,
+                                 int c1, int c2, int gface, int fslot,
+                                 int bslot, C* fb) {
+    const Inst& I = *cx.I;
+    const Params& P = cx.P;
+    const int NCELL = TL::NCELL;
+    const C* W = sm;
+    C wl[L::NR], wr[L::NR];
+#pragma unroll
+    for (int v = 0; v < L::NR; ++v) {
+      const C qm = W[v * NCELL + cm], q0 = W[v * NCELL + c0];
+      const C q1 = W[v * NCELL + c1], q2 = W[v * NCELL + c2];
+      wl[v] = q0 + (C)0.5 * van_leer(q0 - qm, q1 - q0);
+      wr[v] = q1 - (C)0.5 * van_leer(q1 - q0, q2 - q1);
+    }
+    Side sL, sR;
+    unpack_side(P, wl, a, sL);
+    unpack_side(P, wr, a, sR);
+    const C unL = sL.u[a], unR = sR.u[a];
+    const C SL = m_min(unL - sL.c, unR - sR.c);
+    const C SR = m_max(unL + sL.c, unR + sR.c);
+    const C num = (sL.t[a] - sR.t[a]) +
+                  (sL.rho * unL * (SL - unL) - sR.rho * unR * (SR - unR));
+    const C den = sL.rho * (SL - unL) - sR.rho * (SR - unR);
+    const C Ss = num / den;
+    // contact and face speeds below TIE_REL of the largest signal speed are
+    // stationary: the upwind choices take the mean of the two sides (the star
+    // fluxes differ by the tangential-traction jump at a zero contact speed)
+    const C tie = (C)TIE_REL * m_max(m_abs(SL), m_abs(SR));
+    C F[NC];
+    {
+      C FL[NC], FR[NC];
+      phys_flux(sL, a, FL);
+      phys_flux(sR, a, FR);
+      if (SL >= (C)0) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q) F[q] = FL[q];
+      } else if (SR <= (C)0) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q) F[q] = FR[q];
+      } else {
+        C FsL[NC], FsR[NC];
+        star_flux(sL, a, SL, Ss, FL, FsL);
+        star_flux(sR, a, SR, Ss, FR, FsR);
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+          F[q] = Ss > tie ? FsL[q] : (Ss < -tie ? FsR[q] : (C)0.5 * (FsL[q] + FsR[q]));
+      }
+    }
+    C uf = SL > (C)0 ? unL : (SR < (C)0 ? unR : Ss);
+    C ut[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      ut[k] = Ss > tie ? sL.u[k] : (Ss < -tie ? sR.u[k] : (C)0.5 * (sL.u[k] + sR.u[k]));
+    // upwinded geometric face values
+    const bool up = uf > tie, dn = uf < -tie;
+    C phif[NM], Vf[L::NV], Xf[DIM];
+#pragma unroll
+    for (int l = 0; l < NM; ++l)
+      phif[l] = up ? sL.phi[l] : (dn ? sR.phi[l] : (C)0.5 * (sL.phi[l] + sR.phi[l]));
+#pragma unroll
+    for (int q = 0; q < L::NV; ++q) {
+      const C vl = wl[L::R_V + q], vr = wr[L::R_V + q];
+      Vf[q] = up ? vl : (dn ? vr : (C)0.5 * (vl + vr));
+    }
+    const C ext = (C)(I.dx[a] * I.n[a]);
+    const C weps = (C)P.weno_eps * ext * ext;
+    C XL[DIM], XR[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const C xm = W[(L::W_X + k) * NCELL + cm], x0 = W[(L::W_X + k) * NCELL + c0];
+      const C x1 = W[(L::W_X + k) * NCELL + c1], x2 = W[(L::W_X + k) * NCELL + c2];
+      XL[k] = weno3_left(xm, x0, x1, weps);
+      XR[k] = weno3_left(x2, x1, x0, weps);
+      Xf[k] = up ? XL[k] : (dn ? XR[k] : (C)0.5 * (XL[k] + XR[k]));
+    }
+    // one-sided free-surface velocities
+    const C usL = unL - sL.t[a] / (sL.rho * sL.c);
+    const C usR = unR + sR.t[a] / (sR.rho * sR.c);
+    C os = 0;
+    const int n = I.n[a];
+    const bool lo_b = gface == 0, hi_b = gface == n;
+    const bool periodic = I.bc[a][0] == BC_PERIODIC;
+    if ((!lo_b && !hi_b) || periodic) {
+      // void-opening modifier (Section 3.1)
+      const bool crit = W[L::W_CRIT * NCELL + c0] > (C)0 || W[L::W_CRIT * NCELL + c1] > (C)0;
+      const C tens = W[(L::W_SIG + a) * NCELL + c0] + W[(L::W_SIG + a) * NCELL + c1];
+      if (crit && tens > (C)0) {
+        os = 1;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) F[q] = 0;
+      }
+    } else if ((lo_b && I.bc[a][0] == BC_FREE) || (hi_b && I.bc[a][1] == BC_FREE)) {
+      const Side& sK = lo_b ? sR : sL;
+      const C us = lo_b ? usR : usL;
+      const bool outward = lo_b ? us < (C)0 : us > (C)0;
+      if (outward) {
+        // material leaves at the free-surface velocity, no traction
+#pragma unroll
+        for (int q = 0; q < NC; ++q) F[q] = sK.Uc[q] * us;
+        uf = us;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ut[k] = sK.u[k];
+#pragma unroll
+        for (int l = 0; l < NM; ++l) phif[l] = sK.phi[l];
+#pragma unroll
+        for (int q = 0; q < L::NV; ++q) Vf[q] = lo_b ? wr[L::R_V + q] : wl[L::R_V + q];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) Xf[k] = lo_b ? XR[k] : XL[k];
+      } else {
+        os = 1;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) F[q] = 0;
+      }
+    }
+    // outward boundary flux accumulation, RK3 weights 1/6, 1/6, 2/3
+    if (!periodic && (lo_b || hi_b)) {
+      const C w = cx.stage == 3 ? (C)(2.0 / 3.0) : (C)(1.0 / 6.0);
+      const C sgn = lo_b ? (C)-1 : (C)1;
+      double* acc = I.bacc + I.bacc_off[2 * a + (hi_b ? 1 : 0)] + (int64_t)bslot * NC;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) acc[q] += (double)(w * cx.dt * (sgn * F[q]));
+    }
+    // store
+    const int NF = TL::NFACE;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) fb[(L::Q_F + q) * NF + fslot] = F[q];
+    fb[L::Q_UF * NF + fslot] = uf;
+    {
+      int k2 = 0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k)
+        if (k != a) { fb[(L::Q_UT + k2) * NF + fslot] = ut[k]; ++k2; }
+    }
+#pragma unroll
+    for (int l = 0; l < NM; ++l) fb[(L::Q_PHI + l) * NF + fslot] = phif[l];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) fb[(L::Q_X + k) * NF + fslot] = Xf[k];
+#pragma unroll
+    for (int q = 0; q < L::NV; ++q) fb[(L::Q_V + q) * NF + fslot] = Vf[q];
+    fb[L::Q_OS * NF + fslot] = os;
+    fb[L::Q_USL * NF + fslot] = usL;
+    fb[L::Q_USR * NF + fslot] = usR;
+  }
+
+  // Face item -> stencil and slot.  Returns false if the face lies outside
+  // the domain (partial tiles).
+  FV_HD static bool face_item(const Ctx& cx, int a, int item, int& cm, int& c0,
+                              int& c1, int& c2, int& gface, int& fslot,
+                              int& bslot) {
+    const Inst& I = *cx.I;
+    if (a == 0) {
+      const int fx = item % (TX + 1), ty = item / (TX + 1);
+      if (ty >= TY) return false;
+      gface = cx.bx * TX + fx;
+      const int gy = cx.by * TY + ty;
+      if (gface > I.n[0] || (DIM >= 2 && gy >= I.n[1])) return false;
+      const int hy = DIM >= 2 ? ty + 2 : 0;
+      cm = TL::cell(fx, hy); c0 = TL::cell(fx + 1, hy);
+      c1 = TL::cell(fx + 2, hy); c2 = TL::cell(fx + 3, hy);
+      fslot = ty * (TX + 1) + fx;
+      bslot = DIM >= 2 ? gy : 0;
+      return true;
+    }
+    const int tx = item % TX, fy = item / TX;
+    if (fy > TY) return false;
+    gface = cx.by * TY + fy;
+    const int gx = cx.bx * TX + tx;
+    if (gface > I.n[1] || gx >= I.n[0]) return false;
+    const int hx = tx + 2;
+    cm = TL::cell(hx, fy); c0 = TL::cell(hx, fy + 1);
+    c1 = TL::cell(hx, fy + 2); c2 = TL::cell(hx, fy + 3);
+    fslot = fy * TX + tx;
+    bslot = gx;
+    return true;
+  }
+
+  FV_HD static int face_items(int a) { return a == 0 ? TL::NFX : TL::NFY; }
+
+  // ---------------------------------------------------------------- phase 3
+  // contribution of one face to the owning cell (side 0: the cell is the
+  // face's left neighbour, side 1: its right neighbour)
+  struct FaceC {
+    C F[NC];
+    C vel;
+    C phif[NM];
+    C Xfl[DIM];
+    C Vfl[L::NV];
+    C row[3];
+  };
+
+  FV_HD static void face_contrib(const C* fb, int fslot, int a, int side,
+                                 const C* Xc, const C Vc[3][3], const C* uc,
+                                 FaceC& o) {
+    const int NF = TL::NFACE;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) o.F[q] = fb[(L::Q_F + q) * NF + fslot];
+    const C os = fb[L::Q_OS * NF + fslot];
+    C uv[3];
+    C Vm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    if (os == (C)0) {
+      const C uf = fb[L::Q_UF * NF + fslot];
+      o.vel = uf;
+      uv[0] = uv[1] = uv[2] = 0;
+      int k2 = 0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        if (k == a) uv[k] = uf;
+        else { uv[k] = fb[(L::Q_UT + k2) * NF + fslot]; ++k2; }
+      }
+#pragma unroll
+      for (int l = 0; l < NM; ++l) o.phif[l] = fb[(L::Q_PHI + l) * NF + fslot] * uf;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) o.Xfl[k] = fb[(L::Q_X + k) * NF + fslot] * uf;
+#pragma unroll
+      for (int q = 0; q < L::NV; ++q) Vm[vb_i<DIM>(q)][vb_j<DIM>(q)] = fb[(L::Q_V + q) * NF + fslot];
+    } else {
+      const C us = fb[(side == 0 ? L::Q_USL : L::Q_USR) * NF + fslot];
+      o.vel = us;
+      uv[0] = uc[0]; uv[1] = uc[1]; uv[2] = uc[2];
+      uv[a] = us;
+#pragma unroll
+      for (int l = 0; l < NM; ++l) o.phif[l] = 0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) o.Xfl[k] = Xc[k] * us;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Vm[i][j] = Vc[i][j];
+    }
+#pragma unroll
+    for (int q = 0; q < L::NV; ++q) {
+      const int i = vb_i<DIM>(q), j = vb_j<DIM>(q);
+      o.Vfl[q] = Vm[i][j] * uv[a] - Vm[a][j] * uv[i];
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) o.row[j] = Vm[a][j];
+  }
+
+  // own cell of this thread inside the tile
+  FV_HD static bool own_cell(const Ctx& cx, int tid, int& tx, int& ty, int64_t& g) {
+    const Inst& I = *cx.I;
+    tx = tid % TX;
+    ty = tid / TX;
+    const int gx = cx.bx * TX + tx;
+    const int gy = cx.by * TY + ty;
+    if (gx >= I.n[0]) return false;
+    if (DIM >= 2 && gy >= I.n[1]) return false;
+    g = DIM >= 2 ? (int64_t)gy * I.n[0] + gx : gx;
+    return true;
+  }
+
+  FV_HD static void gather(const Ctx& cx, const C* sm, const C* fb, int a,
+                           int tx, int ty, C* acc) {
+    const int NCELL = TL::NCELL;
+    const C* W = sm;
+    const int hx = tx + 2, hy = DIM >= 2 ? ty + 2 : 0;
+    const int cc = TL::cell(hx, hy);
+    C Xc[DIM], uc[3] = {0, 0, 0}, phic[NM];
+    C Vc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) { Xc[k] = W[(L::W_X + k) * NCELL + cc]; uc[k] = W[(L::R_U + k) * NCELL + cc]; }
+#pragma unroll
+    for (int l = 0; l < NM; ++l) phic[l] = W[(L::R_PHI + l) * NCELL + cc];
+#pragma unroll
+    for (int q = 0; q < L::NV; ++q) Vc[vb_i<DIM>(q)][vb_j<DIM>(q)] = W[(L::R_V + q) * NCELL + cc];
+    int fm, fp;
+    if (a == 0) { fm = ty * (TX + 1) + tx; fp = fm + 1; }
+    else { fm = ty * TX + tx; fp = fm + TX; }
+    FaceC m, p;
+    face_contrib(fb, fm, a, 1, Xc, Vc, uc, m);
+    face_contrib(fb, fp, a, 0, Xc, Vc, uc, p);
+    const C inv = (C)1 / (C)cx.I->dx[a];
+    const C div = (p.vel - m.vel) * inv;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      int f;
+      if (q < NM) f = L::MASS + q;
+      else if (q < NM + 2 * NS) f = L::HIST + (q - NM);
+      else if (q < L::C_ENE) f = L::MOM + (q - L::C_MOM);
+      else f = L::ENE;
+      acc[f] += -(p.F[q] - m.F[q]) * inv;
+    }
+#pragma unroll
+    for (int l = 0; l < NM; ++l)
+      acc[L::PHI + l] += -(p.phif[l] - m.phif[l]) * inv + phic[l] * div;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+      acc[L::XC + k] += -(p.Xfl[k] - m.Xfl[k]) * inv + Xc[k] * div;
+#pragma unroll
+    for (int q = 0; q < L::NV; ++q) {
+      const int i = vb_i<DIM>(q), j = vb_j<DIM>(q);
+      const C beta = (p.row[j] - m.row[j]) * inv;
+      acc[L::VB + q] += -(p.Vfl[q] - m.Vfl[q]) * inv + (C)(2.0 / 3.0) * Vc[i][j] * div - uc[i] * beta;
+    }
+  }
+
+  // ---------------------------------------------------------------- phase 4
+  // Source step on the new state of one cell (FP64), Section 2.4 / 3.1 /
+  // 3.2.2 readings: phi0 gather, radial return, Bonora RK4, Vbar rebuild.
+  FV_HD static double phi0_gather(const Inst& I, const double* X) {
+    const T* f = (const T*)I.phi0;
+    int i0[3] = {0, 0, 0};
+    double w[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const int nk = I.n[k];
+      double s = (X[k] - (I.lo[k] + 0.5 * I.dx[k])) / I.dx[k];
+      s = s < 0.0 ? 0.0 : (s > (double)(nk - 1) ? (double)(nk - 1) : s);
+      double fl = floor(s);
+      const double top = nk >= 2 ? (double)(nk - 2) : 0.0;
+      if (fl > top) fl = top;
+      i0[k] = (int)fl;
+      w[k] = s - fl;
+    }
+    auto at = [&](int dx_, int dy_, int dz_) -> double {
+      const int x = m_min(i0[0] + dx_, I.n[0] - 1);
+      const int y = DIM >= 2 ? m_min(i0[1] + dy_, I.n[1] - 1) : 0;
+      const int z = DIM >= 3 ? m_min(i0[2] + dz_, I.n[2] - 1) : 0;
+      return (double)f[((int64_t)z * I.n[1] + y) * I.n[0] + x];
+    };
+    auto lerp = [](double a, double b, double t) { return a + t * (b - a); };
+    if (DIM == 1) return lerp(at(0, 0, 0), at(1, 0, 0), w[0]);
+    const double f0 = lerp(at(0, 0, 0), at(1, 0, 0), w[0]);
+    const double f1 = lerp(at(0, 1, 0), at(1, 1, 0), w[0]);
+    if (DIM == 2) return lerp(f0, f1, w[1]);
+    const double g0 = lerp(f0, f1, w[1]);
+    const double f2 = lerp(at(0, 0, 1), at(1, 0, 1), w[0]);
+    const double f3 = lerp(at(0, 1, 1), at(1, 1, 1), w[0]);
+    return lerp(g0, lerp(f2, f3, w[1]), w[2]);
+  }
+
+  // Returns the cell's CFL sum  sum_a (|u_a| + c)/dx_a  after the source step.
+  FV_HD static double source_and_cfl(const Params& P, const Inst& I, double* U) {
+    double phi[NM], mass[NM], rho_l[NM], eps[NS > 0 ? NS : 1], D[NS > 0 ? NS : 1];
+    double rho = 0;
+#pragma unroll
+    for (int l = 0; l < NM; ++l) {
+      phi[l] = U[L::PHI + l];
+      mass[l] = U[L::MASS + l] > 0.0 ? U[L::MASS + l] : 0.0;
+      rho_l[l] = mass[l] / phi[l];
+      rho += mass[l];
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const double ms = U[L::MASS + s];
+      eps[s] = ms > 0.0 ? U[L::HIST + 2 * s] / ms : 0.0;
+      D[s] = ms > 0.0 ? U[L::HIST + 2 * s + 1] / ms : 0.0;
+    }
+    double u[3] = {0, 0, 0}, ke = 0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) { u[k] = U[L::MOM + k] / rho; ke += u[k] * u[k]; }
+    const double rho_e = U[L::ENE] - 0.5 * rho * ke;
+    double V[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int q = 0; q < L::NV; ++q) V[vb_i<DIM>(q)][vb_j<DIM>(q)] = U[L::VB + q];
+    double H[3][3];
+    hencky<DIM, double>(V, H);
+    const double J2 = J2_of<DIM, double>(H);
+    Mix<NM, NS, double> mx;
+    mix_terms<NM, NS, double>(P, phi, rho_l, D, J2, mx);
+    const double p = mix_pressure<NM, NS, double>(P, phi, mx, rho_e);
+    double X[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) X[k] = U[L::XC + k];
+    const double pert = phi0_gather(I, X);
+    // radial return of dev H to the perturbed mixture yield surface
+    double Ymix = 0, Gm = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const MatP& m = P.mat[s];
+      const double w = 1.0 - D[s];
+      Gm += phi[s] * w * shear_modulus_undamaged<double>(m, rho_l[s]);
+      const double sy = D[s] < m.Dcrit_eff ? pert * m.yield : 0.0;
+      Ymix += phi[s] * w * sy;
+    }
+    const double Jmax = Gm > 0.0 ? Ymix / (sqrt(6.0) * Gm) : 0.0;
+    const double J = sqrt(J2);
+    double scale = 1.0, deps = 0.0;
+    if (J > Jmax) { scale = Jmax / J; deps = sqrt(2.0 / 3.0) * (J - Jmax); }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) H[i][j] *= scale;
+    double Vn[3][3];
+    stretch_from_log<DIM, double>(H, Vn);
+#pragma unroll
+    for (int q = 0; q < L::NV; ++q) U[L::VB + q] = Vn[vb_i<DIM>(q)][vb_j<DIM>(q)];
+    double Dn[NS > 0 ? NS : 1];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const MatP& m = P.mat[s];
+      const double seq = (1.0 - D[s]) * pert * m.yield;
+      bool gate = (p < m.pgate) && (deps > 0.0) && (D[s] < m.Dcrit_eff);
+      const bool ok = seq > 0.0;
+      const double R = ok ? triaxiality(m, p, seq, rho_l[s]) : 1.0;
+      if (gate) {
+        const double thr = eps_threshold(m, R);
+        gate = (eps[s] > thr) || !ok;
+      }
+      Dn[s] = D[s];
+      if (gate) Dn[s] = ok ? damage_rk4(m, D[s], eps[s], deps, R) : m.Dcrit;
+      const double ms = U[L::MASS + s];
+      U[L::HIST + 2 * s] = ms * (eps[s] + deps);
+      U[L::HIST + 2 * s + 1] = ms * Dn[s];
+    }
+    // CFL sum on the new state
+    const double J2n = J2_of<DIM, double>(H);
+    Mix<NM, NS, double> mx2;
+    mix_terms<NM, NS, double>(P, phi, rho_l, Dn, J2n, mx2);
+    const double p2 = mix_pressure<NM, NS, double>(P, phi, mx2, rho_e);
+    double Gmix;
+    const double c = mix_sound<NM, NS, double>(P, phi, mx2, p2, rho, Gmix);
+    double sum = 0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) sum += (fabs(u[k]) + c) / I.dx[k];
+    return sum;
+  }
+
+  // wave-speed sum of a state without a source step (initial CFL)
+  FV_HD static double cfl_sum(const Params& P, const Inst& I, const double* U) {
+    double phi[NM], rho_l[NM], D[NS > 0 ? NS : 1];
+    double rho = 0;
+#pragma unroll
+    for (int l = 0; l < NM; ++l) {
+      phi[l] = U[L::PHI + l];
+      const double ml = U[L::MASS + l] > 0.0 ? U[L::MASS + l] : 0.0;
+      rho_l[l] = ml / phi[l];
+      rho += ml;
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const double ms = U[L::MASS + s];
+      D[s] = ms > 0.0 ? U[L::HIST + 2 * s + 1] / ms : 0.0;
+    }
+    double u[3] = {0, 0, 0}, ke = 0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) { u[k] = U[L::MOM + k] / rho; ke += u[k] * u[k]; }
+    const double rho_e = U[L::ENE] - 0.5 * rho * ke;
+    double V[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int q = 0; q < L::NV; ++q) V[vb_i<DIM>(q)][vb_j<DIM>(q)] = U[L::VB + q];
+    double H[3][3];
+    hencky<DIM, double>(V, H);
+    const double J2 = J2_of<DIM, double>(H);
+    Mix<NM, NS, double> mx;
+    mix_terms<NM, NS, double>(P, phi, rho_l, D, J2, mx);
+    const double p = mix_pressure<NM, NS, double>(P, phi, mx, rho_e);
+    double Gmix;
+    const double c = mix_sound<NM, NS, double>(P, phi, mx, p, rho, Gmix);
+    double sum = 0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) sum += (fabs(u[k]) + c) / I.dx[k];
+    return sum;
+  }
+
+  // RK combination + clamp (+ source and CFL in stage 3) for one cell.
+  // Returns the CFL sum (stage 3) or 0, and sets *bad for a non-physical
+  // state.
+  FV_HD static double finish_cell(const Ctx& cx, int64_t g, const C* acc, bool* bad) {
+    const Inst& I = *cx.I;
+    double Un[S];
+#pragma unroll
+    for (int f = 0; f < S; ++f) {
+      const C us = (C)cx.src[(int64_t)f * I.ncell + g];
+      const C v = us + cx.dt * acc[f];
+      C o;
+      if (cx.stage == 1) {
+        o = v;
+      } else {
+        const C ub = (C)cx.base[(int64_t)f * I.ncell + g];
+        o = cx.stage == 2 ? (C)0.75 * ub + (C)0.25 * v : ub / (C)3 + (C)(2.0 / 3.0) * v;
+      }
+      Un[f] = (double)o;
+    }
+#pragma unroll
+    for (int l = 0; l < NM; ++l) Un[L::PHI + l] = m_clamp(Un[L::PHI + l], cx.P.phi_floor, 1.0);
+    double cfl = 0;
+    if (cx.stage == 3) cfl = source_and_cfl(cx.P, I, Un);
+    double rho = 0;
+    bool nan = false;
+#pragma unroll
+    for (int f = 0; f < S; ++f) nan = nan || !(Un[f] == Un[f]) || Un[f] - Un[f] != 0.0;
+#pragma unroll
+    for (int l = 0; l < NM; ++l) rho += Un[L::MASS + l];
+    *bad = nan || !(rho > 0.0);
+#pragma unroll
+    for (int f = 0; f < S; ++f) cx.out[(int64_t)f * I.ncell + g] = (T)Un[f];
+    return cfl;
+  }
+};
+
+// Per-cell primitive <-> conserved conversions (used by the load/diagnostic
+// kernels).  Primitive layout: the state's field order with rho_l for the
+// phasic mass, (eps_p, D) for the history densities, u for the momentum and
+// p for the total energy; volume fractions are clamped to [phi_floor, 1].
+template <int DIM, int NM, int NS>
+struct Cell {
+  using L = Lay<DIM, NM, NS>;
+  FV_HD static void prim_to_cons(const Params& P, const double* W, double* U) {
+    double phi[NM], rho_l[NM], D[NS > 0 ? NS : 1];
+    for (int l = 0; l < NM; ++l) {
+      phi[l] = m_clamp(W[L::PHI + l], P.phi_floor, 1.0);
+      rho_l[l] = W[L::MASS + l];
+    }
+    for (int s = 0; s < NS; ++s) D[s] = W[L::HIST + 2 * s + 1];
+    double V[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int q = 0; q < L::NV; ++q) V[vb_i<DIM>(q)][vb_j<DIM>(q)] = W[L::VB + q];
+    double H[3][3];
+    hencky<DIM, double>(V, H);
+    const double J2 = J2_of<DIM, double>(H);
+    Mix<NM, NS, double> mx;
+    mix_terms<NM, NS, double>(P, phi, rho_l, D, J2, mx);
+    const double p = W[L::ENE];
+    const double rho_e = mix_energy<NM, NS, double>(P, phi, mx, p);
+    double rho = 0;
+    for (int l = 0; l < NM; ++l) rho += phi[l] * rho_l[l];
+    double ke = 0;
+    for (int k = 0; k < DIM; ++k) ke += W[L::MOM + k] * W[L::MOM + k];
+    for (int l = 0; l < NM; ++l) { U[L::PHI + l] = phi[l]; U[L::MASS + l] = phi[l] * rho_l[l]; }
+    for (int s = 0; s < NS; ++s) {
+      U[L::HIST + 2 * s] = phi[s] * rho_l[s] * W[L::HIST + 2 * s];
+      U[L::HIST + 2 * s + 1] = phi[s] * rho_l[s] * W[L::HIST + 2 * s + 1];
+    }
+    for (int k = 0; k < DIM; ++k) U[L::MOM + k] = rho * W[L::MOM + k];
+    U[L::ENE] = rho_e + 0.5 * rho * ke;
+    for (int q = 0; q < L::NV; ++q) U[L::VB + q] = W[L::VB + q];
+    for (int k = 0; k < DIM; ++k) U[L::XC + k] = W[L::XC + k];
+  }
+
+  FV_HD static void cons_to_prim(const Params& P, const double* U, double* W) {
+    double phi[NM], rho_l[NM], D[NS > 0 ? NS : 1], eps[NS > 0 ? NS : 1];
+    double rho = 0;
+    for (int l = 0; l < NM; ++l) {
+      phi[l] = U[L::PHI + l];
+      const double ml = m_max(U[L::MASS + l], 0.0);
+      rho_l[l] = ml / phi[l];
+      rho += ml;
+    }
+    for (int s = 0; s < NS; ++s) {
+      const double ms = U[L::MASS + s];
+      eps[s] = ms > 0.0 ? U[L::HIST + 2 * s] / ms : 0.0;
+      D[s] = ms > 0.0 ? U[L::HIST + 2 * s + 1] / ms : 0.0;
+    }
+    double u[3] = {0, 0, 0}, ke = 0;
+    for (int k = 0; k < DIM; ++k) { u[k] = U[L::MOM + k] / rho; ke += u[k] * u[k]; }
+    const double rho_e = U[L::ENE] - 0.5 * rho * ke;
+    double V[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int q = 0; q < L::NV; ++q) V[vb_i<DIM>(q)][vb_j<DIM>(q)] = U[L::VB + q];
+    double H[3][3];
+    hencky<DIM, double>(V, H);
+    const double J2 = J2_of<DIM, double>(H);
+    Mix<NM, NS, double> mx;
+    mix_terms<NM, NS, double>(P, phi, rho_l, D, J2, mx);
+    const double p = mix_pressure<NM, NS, double>(P, phi, mx, rho_e);
+    for (int l = 0; l < NM; ++l) { W[L::PHI + l] = phi[l]; W[L::MASS + l] = rho_l[l]; }
+    for (int s = 0; s < NS; ++s) { W[L::HIST + 2 * s] = eps[s]; W[L::HIST + 2 * s + 1] = D[s]; }
+    for (int k = 0; k < DIM; ++k) W[L::MOM + k] = u[k];
+    W[L::ENE] = p;
+    for (int q = 0; q < L::NV; ++q) W[L::VB + q] = U[L::VB + q];
+    for (int k = 0; k < DIM; ++k) W[L::XC + k] = U[L::XC + k];
+  }
+};
+
+}  // namespace fv

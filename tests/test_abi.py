@@ -1,0 +1,72 @@
+"""Host-side checks of the C-ABI library (CPU only, no device calls): it
+loads, exports every entry point declared in include/fv.h, sizes state and
+workspace, and rejects invalid arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import fvinputs as F
+from paper_2210_04037_amd import abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    if not os.path.exists(abi.LIB_PATH):
+        pytest.skip("libfv.so not built (run __graft_entry__.build())")
+    return abi.load()
+
+
+def test_exports_match_header():
+    lib = _lib()
+    hdr = open(os.path.join(ROOT, "include", "fv.h")).read()
+    declared = set(re.findall(r"\b(fv_[a-z_0-9]+)\s*\(", hdr))
+    assert declared == set(abi.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_state_fields_and_workspace():
+    lib = _lib()
+    c = F.make_case(2, n=64)
+    mats = abi.material_array(c.mats)
+    assert lib.fv_state_fields(2, 2, mats) == 16
+    c1 = F.make_case(1, n=50)
+    assert lib.fv_state_fields(1, 1, abi.material_array(c1.mats)) == 10
+    g = (abi.FvGrid * 1)(abi.grid_struct(c))
+    o = abi.options_struct("fp64")
+    n = lib.fv_workspace_bytes(1, g, 2, mats, ctypes.byref(o))
+    # two stage copies of the state at least
+    assert n >= 2 * 16 * 64 * 64 * 8
+    bad = abi.options_struct("fp64", cfl=1.5)
+    assert lib.fv_workspace_bytes(1, g, 2, mats, ctypes.byref(bad)) == 0
+
+
+def test_init_rejects_invalid_arguments():
+    lib = _lib()
+    c = F.make_case(2, n=32)
+    mats = abi.material_array(c.mats)
+    g = (abi.FvGrid * 1)(abi.grid_struct(c))
+    o = abi.options_struct("fp64")
+    ctx = ctypes.c_void_p()
+    ptrs = (ctypes.c_void_p * 1)(ctypes.c_void_p(0x1000))
+    # periodic on one side only
+    g[0].bc[0][0] = abi.FV_BC["periodic"]
+    rc = lib.fv_init(ctypes.byref(ctx), 1, g, 2, mats, ctypes.byref(o), ptrs,
+                     ptrs, ctypes.c_void_p(0x1000), 1 << 30, None)
+    assert rc == abi.FV_EINVAL
+    assert b"periodic" in lib.fv_last_error(None)
+    g[0].bc[0][0] = abi.FV_BC["transmissive"]
+    # gas before solid
+    rev = abi.material_array([c.mats[1], c.mats[0]])
+    rc = lib.fv_init(ctypes.byref(ctx), 1, g, 2, rev, ctypes.byref(o), ptrs,
+                     ptrs, ctypes.c_void_p(0x1000), 1 << 30, None)
+    assert rc == abi.FV_EINVAL
+    # null state pointer
+    nulls = (ctypes.c_void_p * 1)()
+    rc = lib.fv_init(ctypes.byref(ctx), 1, g, 2, mats, ctypes.byref(o), nulls,
+                     ptrs, ctypes.c_void_p(0x1000), 1 << 30, None)
+    assert rc == abi.FV_EINVAL
+    lib.fv_destroy(None)
