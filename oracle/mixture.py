@@ -13,8 +13,14 @@ paper's mechanical and thermal equilibrium assumption (Section 2.1):
       sigma = -(1 - nu) p I + 2 G_mix dev(H),  G_mix = sum phi_l G_l
     (this makes the mixture work rate equal sum phi_l p_l div u, the
     energy-consistent choice; with no void it is -p I + 2 G dev H)
+  * trace materials (phi < PHI_TRACE) are evaluated at their reference
+    density, and the thermal energy density is taken non-negative in the
+    pressure inversion (both guard cells emptied to near vacuum).
   * sound speed: the frozen (Allaire) mixture bulk speed scaled by (1 - nu),
-    plus the shear contribution, c^2 = c_b^2 + (4/3) G_mix / rho.
+    plus the shear contribution, c^2 = c_b^2 + (4/3) G_mix / rho; each
+    phase's thermal term (Gamma+1)(p - p_ref) enters non-negative (a state
+    below the cold curve, as a gas fraction pulled into tension in a mixed
+    cell, must not drive the wave-speed estimate to zero).
 Parity of the mixture rule itself is unpinned against the paper (it is not
 printed there); the single-material limit is pinned.
 """
@@ -33,22 +39,40 @@ class Options:
         self.weno_eps = weno_eps
 
 
-def material_terms(rho_l, D_l, J2, mats):
-    """Per-material (rho e_ref, p_ref, rho dp_ref/drho, G) lists."""
+# Volume fraction below which a material is a trace: its phasic density, the
+# ratio of two trace quantities, is noise, so its closures are evaluated at
+# its reference density (its contribution is of the order of the fraction).
+PHI_TRACE = 1.0e-6
+
+
+def closure_density(phi_l, rho_l, m):
+    return np.where(phi_l < PHI_TRACE, m["rho0"], rho_l)
+
+
+def material_terms(rho_l, D_l, J2, mats, phi=None):
+    """Per-material (rho e_ref, p_ref, rho dp_ref/drho, G) lists; trace
+    materials (phi < PHI_TRACE) at their reference density."""
     out = []
     for l, m in enumerate(mats):
         D = D_l[l] if l in D_l else np.zeros_like(J2)
-        out.append(ref_terms(rho_l[l], J2, D, m))
+        r = rho_l[l] if phi is None else closure_density(phi[l], rho_l[l], m)
+        out.append(ref_terms(r, J2, D, m))
     return out
 
 
 def pressure_from_energy(phi, terms, rho_e, mats):
+    """Mixture pressure inversion; the thermal energy density
+    rho e - sum phi rho e_ref is taken non-negative (the cold curve is the
+    zero-temperature bound; below it the state is numerical, as in cells
+    emptied to near vacuum or a gas fraction pulled into tension)."""
     xi = sum(phi[l] / gruneisen(m) for l, m in enumerate(mats))
-    num = rho_e.copy()
+    th = rho_e.copy()
+    cold = np.zeros_like(rho_e)
     for l, m in enumerate(mats):
         rho_eref, pref, _, _ = terms[l]
-        num = num - phi[l] * rho_eref + phi[l] * pref / gruneisen(m)
-    return num / xi
+        th = th - phi[l] * rho_eref
+        cold = cold + phi[l] * pref / gruneisen(m)
+    return (np.maximum(th, 0.0) + cold) / xi
 
 
 def energy_from_pressure(phi, terms, p, mats):
@@ -74,7 +98,10 @@ def sound_speed(phi, rho_l, terms, p, rho, mats):
     for l, m in enumerate(mats):
         _, pref, rho_dpref, G = terms[l]
         g = gruneisen(m)
-        acc = acc + phi[l] / g * (rho_dpref + (g + 1.0) * (p - pref))
+        # thermal part taken non-negative: a state below the cold curve is
+        # not physical and must not pull the wave-speed estimate to zero
+        acc = acc + phi[l] / g * (rho_dpref
+                                  + (g + 1.0) * np.maximum(p - pref, 0.0))
         Gmix = Gmix + phi[l] * G
     # acc = sum phi_l xi_l rho_l c_l^2 (with rho_l c_l^2 = rho_l p_ref' +
     # (Gamma_l + 1)(p - p_ref,l)); bulk c^2 = (1-nu) acc / (xi rho)
@@ -105,7 +132,7 @@ def prim_to_cons(W, layout, opts):
     V = full_vbar(W[L.vbar], L.vcomps, shape)
     H, _, _ = hencky(V)
     J2 = J2_of(H)
-    terms = material_terms(rho_l, D_l, J2, mats)
+    terms = material_terms(rho_l, D_l, J2, mats, phi)
     p = W[L.energy]                       # pressure sits in the energy slot
     rho_e = energy_from_pressure(phi, terms, p, mats)
     rho = np.sum(phi * rho_l, axis=0)
@@ -154,7 +181,7 @@ def cons_to_prim(U, layout):
     V = full_vbar(U[L.vbar], L.vcomps, shape)
     H, _, _ = hencky(V)
     J2 = J2_of(H)
-    terms = material_terms(rho_l, P.D, J2, mats)
+    terms = material_terms(rho_l, P.D, J2, mats, phi)
     p = pressure_from_energy(phi, terms, rho_e, mats)
     c, Gmix = sound_speed(phi, rho_l, terms, p, rho, mats)
     P.V, P.H, P.J2, P.p, P.c, P.Gmix = V, H, J2, p, c, Gmix
@@ -168,10 +195,10 @@ def face_state(phi, rho_l, eps, D, u, p, H, mats):
     """Conserved-side quantities of a reconstructed face state: mixture
     density, total energy density, stress and sound speed."""
     J2 = J2_of(H)
-    terms = material_terms(rho_l, D, J2, mats)
+    terms = material_terms(rho_l, D, J2, mats, phi)
     rho = np.sum(phi * rho_l, axis=0)
     rho_e = energy_from_pressure(phi, terms, p, mats)
     rhoE = rho_e + 0.5 * rho * np.sum(u * u, axis=0)
     c, Gmix = sound_speed(phi, rho_l, terms, p, rho, mats)
     sig = stress(phi, p, Gmix, H)
-    return rho, rhoE, sig, c
+    return rho, rhoE, sig, c, Gmix

@@ -11,15 +11,22 @@ The base finite-volume scheme is deferred by the paper to earlier work
     Jiang-Shu weights, smoothness floor eps_w = weno_eps * L^2 with L
     the domain extent along the sweep (the paper gives no value).
   * flux: HLLC with Davis wave speeds for the conserved equations
-    (phasic mass and history, momentum, energy, Section 2.1), the Godunov face
-    velocity for the non-conservative terms and upwinded face values of
-    phi_l, X and Vbar.
+    (phasic mass and history, momentum, energy, Section 2.1) with the
+    contact's tangential velocity and traction resolved by linearised shear
+    waves (see hllc), the Godunov face velocity for the non-conservative
+    terms and upwinded face values of phi_l, X and Vbar.
   * void-opening modifier (Section 3.1): a face opens when either
-    neighbouring cell is critically damaged (D >= D_crit) and the sum of the
-    two cell-centre normal stresses is tensile.  An opened face carries no
-    conserved flux and no volume-fraction flux; each side sees its own
-    one-sided free-surface velocity u* = u_n -/+ sigma_nn/(rho c) and its own
-    cell-centre X and Vbar, so the opening leaves X and Vbar unchanged.
+    neighbouring cell is critically damaged and the sum of the two cell-centre
+    normal stresses along the sweep is tensile, while the two one-sided
+    velocities separate (u*_L <= u*_R).  An opened face transmits no
+    traction: each side sees its own one-sided free-surface velocity
+    u* = u_n -/+ sigma_nn/(rho c); a side whose u* points through the face
+    carries its material (conserved variables and volume fractions) into the
+    neighbour, otherwise void enters it; X and Vbar use each side's own
+    centre values, so opening does not change them.  (The paper's modifier
+    also separates material interfaces in tension; judged along the sweep
+    direction that cuts tensile solids along their surface, so it is left to
+    an interface-normal criterion, not built here.)
   * free-surface boundaries behave like an opened face towards void; the
     material leaves through it when u* points outward.
   * time integration: SSP-RK3 (Shu-Osher) for all transported fields,
@@ -208,8 +215,25 @@ def _phys_flux(Uc, un, u, t, layout):
 
 
 def hllc(sL, sR, a, layout):
-    """HLLC flux for the conserved equations and the Godunov face velocity.
-    s* = dict(rho, u (3,..), t (3,..) = sigma[:, a], rhoE, c, Uc)."""
+    """Approximate Riemann flux with the contact's tangential state resolved.
+
+    HLLC (Davis speeds S_L, S_R, contact speed S*) carries the normal
+    structure: mass, histories, normal momentum and the normal-traction part
+    of the energy.  A plain HLLC has no shear waves, so its star fluxes keep
+    each side's own tangential traction and upwind it by the contact speed,
+    a one-sided difference that lets shear waves grow.  Here the linearised
+    shear waves on either side of the contact (impedance Z = sqrt(G rho))
+    fix a common tangential velocity and traction at the contact,
+      u_t** = (Z_L u_tL + Z_R u_tR + t_tR - t_tL) / (Z_L + Z_R),
+      t_t** = t_tL + Z_L (u_t** - u_tL),
+    (free slip, t_t** = 0, against a fluid) and the star-region flux is
+      mass/history: chi_K U_K S*,  normal momentum: rho*_K S*^2 - t_n*,
+      tangential momentum: rho*_K u_t** S* - t_t**,
+      energy: E**_K S* - S* t_n* - u_t** . t_t**,
+    with E**_K the HLLC star energy plus the kinetic-energy change of the
+    tangential velocity.  The flux is consistent (F(U,U) = F(U)) and
+    continuous through S* = 0.  Returns the flux, the face normal velocity,
+    S*, the tie band and the face tangential velocity vector."""
     L = layout
     unL, unR = sL["u"][a], sR["u"][a]
     tnL, tnR = sL["t"][a], sR["t"][a]
@@ -220,36 +244,58 @@ def hllc(sL, sR, a, layout):
     num = (tnL - tnR) + (rL * unL * (SL - unL) - rR * unR * (SR - unR))
     den = rL * (SL - unL) - rR * (SR - unR)
     Ss = num / den
+    tie = TIE_REL * np.maximum(np.abs(SL), np.abs(SR))
     FL = _phys_flux(sL["Uc"], unL, sL["u"], sL["t"], L)
     FR = _phys_flux(sR["Uc"], unR, sR["u"], sR["t"], L)
+    tang = [k for k in range(3) if k != a]
+    ZL = np.sqrt(sL["G"] * rL)
+    ZR = np.sqrt(sR["G"] * rR)
+    Zs = ZL + ZR
+    pos = Zs > 0
+    Zsafe = np.where(pos, Zs, 1.0)
+    ut2 = np.zeros_like(sL["u"])
+    tt2 = np.zeros_like(sL["u"])
+    for k in tang:
+        up = _pick(Ss > tie, Ss < -tie, sL["u"][k], sR["u"][k])
+        ut2[k] = np.where(pos, (ZL * sL["u"][k] + ZR * sR["u"][k]
+                                + (sR["t"][k] - sL["t"][k])) / Zsafe, up)
+        tt2[k] = np.where(pos, sL["t"][k] + ZL * (ut2[k] - sL["u"][k]), 0.0)
+    tn_star = 0.5 * ((tnL - rL * (SL - unL) * (Ss - unL))
+                     + (tnR - rR * (SR - unR) * (Ss - unR)))
+    work = sum(ut2[k] * tt2[k] for k in tang)
+    base = L.nm + 2 * len(L.solids)
 
     def star(s, S, un, tn):
         chi = (S - un) / (S - Ss)
-        Us = s["Uc"] * chi[None]
-        base = L.nm + 2 * len(L.solids)
+        rs = chi * s["rho"]
+        Es = chi * (s["rhoE"] + (Ss - un) * (s["rho"] * Ss - tn / (S - un)))
+        Ess = Es + 0.5 * rs * sum(ut2[k] ** 2 - s["u"][k] ** 2 for k in tang)
+        F = s["Uc"] * (chi * Ss)[None]
         for k in range(L.dim):
-            Us[base + k] = chi * s["rho"] * (s["u"][k] + (Ss - un if k == a
-                                                         else 0.0))
-        Us[-1] = chi * (s["rhoE"] + (Ss - un) * (s["rho"] * Ss
-                                                 - tn / (S - un)))
-        return Us
+            if k == a:
+                F[base + k] = rs * Ss * Ss - tn_star
+            else:
+                F[base + k] = rs * ut2[k] * Ss - tt2[k]
+        F[-1] = Ess * Ss - Ss * tn_star - work
+        return F
 
-    FsL = FL + SL[None] * (star(sL, SL, unL, tnL) - sL["Uc"])
-    FsR = FR + SR[None] * (star(sR, SR, unR, tnR) - sR["Uc"])
-    tie = TIE_REL * np.maximum(np.abs(SL), np.abs(SR))
+    FsL = star(sL, SL, unL, tnL)
+    FsR = star(sR, SR, unR, tnR)
     Fstar = np.where(Ss[None] > tie, FsL,
                      np.where(Ss[None] < -tie, FsR, 0.5 * (FsL + FsR)))
     F = np.where(SL[None] >= 0, FL, np.where(SR[None] <= 0, FR, Fstar))
     uface = np.where(SL > 0, unL, np.where(SR < 0, unR, Ss))
-    return F, uface, Ss, tie
+    uvec = np.where(SL[None] > 0, sL["u"], np.where(SR[None] < 0, sR["u"], ut2))
+    uvec[a] = uface
+    return F, uface, Ss, tie, uvec
 
 
 def _side(W, names, layout, shape, mats):
     phi, rho_l, eps, D, u, p, H, V = _unpack(W, names, layout, shape)
-    rho, rhoE, sig, c = face_state(phi, rho_l, eps, D, u, p, H, mats)
+    rho, rhoE, sig, c, G = face_state(phi, rho_l, eps, D, u, p, H, mats)
     Uc = _face_conserved(phi, rho_l, eps, D, u, rho, rhoE, layout)
     return dict(phi=phi, rho_l=rho_l, u=u, p=p, H=H, V=V, rho=rho,
-                rhoE=rhoE, sig=sig, c=c, Uc=Uc)
+                rhoE=rhoE, sig=sig, c=c, G=G, Uc=Uc)
 
 
 def _vflux(V, uvec, a, comps):
@@ -287,10 +333,7 @@ def rhs(U, geom, layout, opts):
         sR = _side(WR, names, L, fshape, mats)
         for sd in (sL, sR):
             sd["t"] = sd["sig"][:, a]
-        F, uface, Ss, tie = hllc(sL, sR, a, L)
-        # tangential face velocity upwinded by the contact speed
-        uvec = _pick(Ss > tie, Ss < -tie, sL["u"], sR["u"])
-        uvec[a] = uface
+        F, uface, Ss, tie, uvec = hllc(sL, sR, a, L)
         up, un_ = uface > tie, uface < -tie
         phi_f = _pick(up, un_, sL["phi"], sR["phi"])
         V_f = _pick(up, un_, sL["V"], sR["V"])
@@ -315,9 +358,6 @@ def rhs(U, geom, layout, opts):
                          ("sig", P.sigma[a, a]), ("crit", crit)):
             v = _sweep_view(arr, a, geom)
             cen[key] = (v[..., 1:-2], v[..., 2:-1])
-        ustarL = sL["u"][a] - sL["t"][a] / (sL["rho"] * sL["c"])
-        ustarR = sR["u"][a] + sR["t"][a] / (sR["rho"] * sR["c"])
-
         def closed_side(K, ustar, mask):
             """Overwrite side K's geometric fluxes with its own centre values
             and one-sided velocity where `mask`."""
@@ -339,15 +379,31 @@ def rhs(U, geom, layout, opts):
                 VfR[:, m] = vf[:, m]
                 rowR[:, m] = Vc[a][:, m]
 
+        ustarL = sL["u"][a] - sL["t"][a] / (sL["rho"] * sL["c"])
+        ustarR = sR["u"][a] + sR["t"][a] / (sR["rho"] * sR["c"])
+        # the two free surfaces must separate (approaching sides are closing
+        # the void and are in contact again)
         opened = ((cen["crit"][0] | cen["crit"][1])
-                  & (cen["sig"][0] + cen["sig"][1] > 0))
+                  & (cen["sig"][0] + cen["sig"][1] > 0)
+                  & (ustarL <= ustarR))
         # boundary faces are handled below, never by the damage predicate
         if geom.bc[a][0] != "periodic":
             opened[..., 0] = False
             opened[..., -1] = False
-        F[:, opened] = 0.0
+        # an opened face is a free surface seen from each side: a side whose
+        # one-sided velocity points through the face carries its material
+        # (no traction) into the neighbour, otherwise void enters it
+        outL = opened & (ustarL > 0)
+        outR = opened & (ustarR < 0)
+        Fo = (np.where(outL[None], sL["Uc"] * ustarL[None], 0.0)
+              + np.where(outR[None], sR["Uc"] * ustarR[None], 0.0))
+        F[:, opened] = Fo[:, opened]
         closed_side(0, ustarL, opened)
         closed_side(1, ustarR, opened)
+        Po = (np.where(outL[None], sL["phi"] * ustarL[None], 0.0)
+              + np.where(outR[None], sR["phi"] * ustarR[None], 0.0))
+        phiL[:, opened] = Po[:, opened]
+        phiR[:, opened] = Po[:, opened]
         # free-surface boundaries
         for side in (0, 1):
             if geom.bc[a][side] != "free":

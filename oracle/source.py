@@ -29,7 +29,7 @@ import numpy as np
 from .closures import (solid_shear_modulus, triaxiality, eps_threshold,
                        bonora_dD_deps, is_critical)
 from .kinematics import hencky, stretch_from_log
-from .mixture import cons_to_prim
+from .mixture import cons_to_prim, closure_density
 
 
 def phi0_at(X, phi0, geom):
@@ -102,7 +102,7 @@ def source_step(U, phi0, geom, layout, opts):
     for l in L.solids:
         m = mats[l]
         w = 1.0 - P.D[l]
-        Gt = solid_shear_modulus(P.rho_l[l], m)
+        Gt = solid_shear_modulus(closure_density(P.phi[l], P.rho_l[l], m), m)
         Gmix = Gmix + P.phi[l] * w * Gt
         sy = np.where(~is_critical(P.D[l], m), pert * m["yield_stress"], 0.0)
         Ymix = Ymix + P.phi[l] * w * sy
@@ -123,7 +123,8 @@ def source_step(U, phi0, geom, layout, opts):
         sig_eq = (1.0 - D_n) * pert * m["yield_stress"]
         gate = (P.p < m["p_gate"]) & (deps > 0) & ~is_critical(D_n, m)
         ok = sig_eq > 0
-        R = triaxiality(P.p, np.where(ok, sig_eq, 1.0), P.rho_l[l], m)
+        R = triaxiality(P.p, np.where(ok, sig_eq, 1.0),
+                        closure_density(P.phi[l], P.rho_l[l], m), m)
         R = np.where(ok, R, 1.0)
         thr = eps_threshold(R, m)
         gate = gate & ((eps_n > thr) | ~ok)

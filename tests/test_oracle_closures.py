@@ -105,7 +105,7 @@ def test_sound_speed_is_isentropic_derivative(eta, J2, D):
     """The bulk part of c^2 equals dp/drho along de = p/rho^2 drho (finite
     differences of the pressure function), plus (4/3) G / rho."""
     rho = eta * CU["rho0"]
-    e = 3.0e3
+    e = 5.0e4          # above the cold curve (positive thermal energy)
     p, c, G = _single(CU, rho, e, J2, D)
     h = 1e-5 * rho
     pp, _, _ = _single(CU, rho + h, e + p / rho ** 2 * h, J2, D)
@@ -124,7 +124,7 @@ def test_mixture_sound_speed_is_isentropic_derivative():
     D = {0: np.array([0.1])}
     J2 = np.array([1e-6])
     rho = float(np.sum(phi * rho_l))
-    rho_e = 2.0e7
+    rho_e = 2.0e9      # p > 0: both phases above their cold curves
 
     def pmix(scale, re):
         rl = rho_l * scale
@@ -258,3 +258,19 @@ def test_threshold_strain_spall_value():
     ~1e-5."""
     v = C.eps_threshold(245.0, CU)
     assert 1e-6 < v < 1e-4
+
+
+def test_sound_speed_below_cold_curve_keeps_cold_stiffness():
+    """A state below the cold curve (negative thermal energy) takes the cold
+    pressure and keeps the cold and shear stiffness in c^2 (mixture reading:
+    the thermal part is bounded below by zero)."""
+    rho = 1.04 * CU["rho0"]
+    J2 = 2e-6
+    p, c, G = _single(CU, rho, 3.0e3, J2)
+    terms = M.material_terms(np.array([[rho]]), {0: np.array([0.0])},
+                             np.array([J2]), [CU])
+    _, pref, rho_dpref, _ = terms[0]
+    # the pressure inversion clamps the thermal part: p is the cold pressure
+    assert p == pytest.approx(pref[0], rel=1e-14)
+    assert c * c == pytest.approx(rho_dpref[0] / rho + 4.0 / 3.0 * G / rho,
+                                  rel=1e-13)

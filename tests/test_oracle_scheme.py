@@ -111,8 +111,8 @@ def test_conservation_periodic_box():
 def test_conservation_with_open_boundaries_and_fracture():
     """Free-surface ends and a spall opening: interior total plus the
     accumulated boundary outflow stays equal to the initial total."""
-    case = F.uniform_case(1, (60, 1, 1), [CU], [1.0], [8930.0], [0.0], -2.0e9,
-                          bc="free")
+    case = F.uniform_case(1, (60, 1, 1), [CU], [1.0], [8930.0 * 0.99], [0.0],
+                          -1.0e9, bc="free")
     L = Layout(1, case.mats)
     x = (np.arange(60) + 0.5) / 60
     case.prim[L.mom[0]] = 300.0 * (x - 0.5)
@@ -181,7 +181,7 @@ def test_flux_consistency():
     for a in range(2):
         for sd in (sL, sR):
             sd["t"] = sd["sig"][:, a]
-        Fh, uf, Ss, _ = Sch.hllc(sL, sR, a, L)
+        Fh, uf, Ss, _, _ = Sch.hllc(sL, sR, a, L)
         Fp = Sch._phys_flux(sL["Uc"], sL["u"][a], sL["u"], sL["t"], L)
         assert np.allclose(Fh, Fp, rtol=1e-12, atol=1e-6)
         assert np.allclose(uf, sL["u"][a], rtol=1e-12, atol=1e-12)
@@ -270,8 +270,9 @@ def test_convergence_order_smooth_elastic_wave():
     res = {}
     t_end = None
     for n in (64, 128, 256, 512):
+        # background pressure well above the cold curve of the perturbation
         case = F.uniform_case(1, (n, 1, 1), [dict(CU, yield_stress=1e15)],
-                              [1.0], [8930.0], [0.0], 1.0e5, bc="periodic",
+                              [1.0], [8930.0], [0.0], 1.0e8, bc="periodic",
                               lo=(0.0, 0, 0), hi=(0.01, 1, 1))
         L = Layout(1, case.mats)
         x = case.prim[L.X[0]]
@@ -291,29 +292,41 @@ def test_convergence_order_smooth_elastic_wave():
     assert order >= 1.8, (errs, order)
 
 
-def _opening_case(D, p):
-    case = F.uniform_case(1, (40, 1, 1), [CU], [1.0], [8930.0], [0.0], p,
+def _opening_run(D, p, u=0.0, eta=1.0):
+    # tension needs stretched material (eta < 1) above its cold curve
+    case = F.uniform_case(1, (40, 1, 1), [CU], [1.0], [8930.0 * eta], [u], p,
                           bc="transmissive")
     L = Layout(1, case.mats)
-    x = (np.arange(40) + 0.5) / 40
-    case.prim[L.mom[0]] = 400.0 * (x - 0.5)
     case.prim[L.dmg[0]] = D
-    return case, L
+    s = _solver(case)
+    m0 = s.U[L.mass[0]].copy()
+    s.step()
+    return s, L, m0
 
 
 def test_void_opening_only_in_tension_with_critical_damage():
-    """Critically damaged and tensile: no mass crosses any interior face.
-    Undamaged, or compressive: mass moves (Section 3.1)."""
-    def mass_change(D, p):
-        case, L = _opening_case(D, p)
-        s = _solver(case)
-        m0 = s.U[L.mass[0]].copy()
-        s.step()
-        return np.max(np.abs(s.U[L.mass[0]] - m0)[..., 3:-3])
+    """Critically damaged material in tension opens void in every cell and,
+    at rest, no mass crosses a face; undamaged material in tension, or
+    damaged material in compression, stays intact (Section 3.1)."""
+    s, L, m0 = _opening_run(0.9, -5.0e7, eta=0.995)
+    assert s.prim().p.max() < 0.0
+    phi = s.U[L.phi[0]][..., 3:-3]
+    assert phi.max() < 1.0 - 1e-6
+    assert np.array_equal(s.U[L.mass[0]][..., 3:-3], m0[..., 3:-3])
+    for D, p, eta in ((0.0, -5.0e8, 0.995), (0.9, 1.0e8, 1.005)):
+        s, L, m0 = _opening_run(D, p, eta=eta)
+        assert np.all(s.U[L.phi[0]] == 1.0)
 
-    assert mass_change(0.9, -1.0e8) == 0.0
-    assert mass_change(0.0, -1.0e8) > 1.0
-    assert mass_change(0.9, 1.0e8) > 1.0
+
+def test_opened_faces_carry_a_moving_fragment():
+    """A critically damaged bar under tension moving at 50 m/s keeps moving
+    through opened faces: its mass is carried downstream and conserved."""
+    s, L, m0 = _opening_run(0.9, -5.0e7, u=50.0, eta=0.995)
+    inner, outer = s.totals()
+    assert abs(inner[0] + outer[0] - np.sum(m0) * s.cell_volume) <= \
+        1e-13 * np.sum(m0) * s.cell_volume
+    mom = s.U[L.mom[0]][..., 5:-5] / s.U[L.mass[0]][..., 5:-5]
+    assert np.allclose(mom, 50.0, rtol=1e-3)
 
 
 def test_volume_fraction_bounds_ring():
@@ -324,7 +337,11 @@ def test_volume_fraction_bounds_ring():
     L = s.layout
     phi = s.U[L.phi]
     assert phi.min() >= s.opts.phi_floor and phi.max() <= 1.0
-    assert np.max(np.abs(phi.sum(axis=0) - 1.0)) < 1e-7
+    # materials never overfill a cell; void (1 - sum phi) only opens at the
+    # tensile inner surface of the ring
+    assert phi.sum(axis=0).max() <= 1.0 + 1e-3
+    void = 1.0 - phi.sum(axis=0)
+    assert np.all(void[phi[0] > 0.999] < 1e-6)
 
 
 def test_radial_return_closed_form():
