@@ -373,6 +373,10 @@ static bool select_ops(int dim, int nm, int ns, int prec, Ops& o, hipError_t& he
   FV_SEL(1, 2, 1, double, double, 256, 1)
   FV_SEL(2, 1, 1, double, double, 32, 8)
   FV_SEL(2, 2, 1, double, double, 32, 8)
+  FV_SEL(1, 1, 1, float, float, 256, 1)
+  FV_SEL(1, 2, 1, float, float, 256, 1)
+  FV_SEL(2, 1, 1, float, float, 32, 8)
+  FV_SEL(2, 2, 1, float, float, 32, 8)
 #undef FV_SEL
   return false;
 }
@@ -471,6 +475,7 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
     q.eps_th = m.eps_th; q.eps_c = m.eps_c; q.balpha = m.bonora_alpha;
     q.nhard = m.n_hard; q.pgate = m.p_gate;
     q.Dcrit_eff = m.D_crit * (1.0 - 1.0e-9);
+    q.Dcrit_eff32 = m.D_crit * (1.0 - 1.0e-6);
     q.invGamma = 1.0 / m.Gamma0;
     auto small_int = [](double v) {
       const double r = std::round(v);

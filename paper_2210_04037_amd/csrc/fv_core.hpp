@@ -65,8 +65,9 @@ struct MatP {
   double rho0, K0, alpha, G0, beta, Gamma0;
   double yield, Dcrit, D0, eps_th, eps_c, balpha, nhard, pgate;
   // host-derived constants
-  double Dcrit_eff;  // D_crit (1 - 1e-9): critical test up to the rounding of
-                     // the advected ratio (phi rho D)/(phi rho)
+  double Dcrit_eff;    // D_crit (1 - 1e-9): critical test up to the rounding of
+                       // the advected ratio (phi rho D)/(phi rho), FP64 state
+  double Dcrit_eff32;  // D_crit (1 - 1e-6): the same for an FP32 state
   double invGamma;   // 1 / Gamma0
   double nu;         // Poisson ratio of the undamaged moduli
   double bonA;       // alpha_B (Dc - D0)^(1/alpha_B) / ln(eps_c / eps_th)
@@ -206,6 +207,16 @@ struct Mix {
   C xi;
 };
 
+// A material below this volume fraction is a trace: its phasic density (the
+// ratio of two trace quantities) is noise, so its closures are evaluated at
+// its reference density.
+constexpr double PHI_TRACE = 1.0e-6;
+
+template <class C>
+FV_HD C closure_density(const MatP& m, C phi_l, C rho_l) {
+  return phi_l < (C)PHI_TRACE ? (C)m.rho0 : rho_l;
+}
+
 template <int NM, int NS, class C>
 FV_HD void mix_terms(const Params& P, const C* phi, const C* rho_l, const C* D,
                      C J2, Mix<NM, NS, C>& mx) {
@@ -213,19 +224,23 @@ FV_HD void mix_terms(const Params& P, const C* phi, const C* rho_l, const C* D,
 #pragma unroll
   for (int l = 0; l < NM; ++l) {
     const C Dl = l < NS ? D[l < NS ? l : 0] : (C)0;
-    mx.t[l] = ref_terms<C>(P.mat[l], rho_l[l], J2, Dl);
+    mx.t[l] = ref_terms<C>(P.mat[l], closure_density(P.mat[l], phi[l], rho_l[l]), J2, Dl);
     mx.xi += phi[l] * (C)P.mat[l].invGamma;
   }
 }
 
+// Pressure inversion; the thermal energy density rho e - sum phi rho e_ref is
+// taken non-negative (the cold curve is the zero-temperature bound).
 template <int NM, int NS, class C>
 FV_HD C mix_pressure(const Params& P, const C* phi, const Mix<NM, NS, C>& mx,
                      C rho_e) {
-  C num = rho_e;
+  C th = rho_e, cold = 0;
 #pragma unroll
-  for (int l = 0; l < NM; ++l)
-    num = num - phi[l] * mx.t[l].rho_eref + phi[l] * mx.t[l].pref * (C)P.mat[l].invGamma;
-  return num / mx.xi;
+  for (int l = 0; l < NM; ++l) {
+    th = th - phi[l] * mx.t[l].rho_eref;
+    cold = cold + phi[l] * mx.t[l].pref * (C)P.mat[l].invGamma;
+  }
+  return (m_max(th, (C)0) + cold) / mx.xi;
 }
 
 template <int NM, int NS, class C>
@@ -254,7 +269,10 @@ FV_HD C mix_sound(const Params& P, const C* phi, const Mix<NM, NS, C>& mx, C p,
 #pragma unroll
   for (int l = 0; l < NM; ++l) {
     const C g = (C)P.mat[l].Gamma0;
-    acc += phi[l] * (C)P.mat[l].invGamma * (mx.t[l].rho_dpref + (g + (C)1) * (p - mx.t[l].pref));
+    // thermal term non-negative: a state below the cold curve (a gas
+    // fraction pulled into tension) must not collapse the wave speed
+    acc += phi[l] * (C)P.mat[l].invGamma *
+           (mx.t[l].rho_dpref + (g + (C)1) * m_max(p - mx.t[l].pref, (C)0));
     Gmix += phi[l] * mx.t[l].G;
   }
   const C cb2 = solid_frac<NM>(phi) * acc / (mx.xi * rho);

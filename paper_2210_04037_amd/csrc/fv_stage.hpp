@@ -22,7 +22,9 @@ namespace fv {
 
 enum { BC_TRANSMISSIVE = 0, BC_FREE = 1, BC_PERIODIC = 2 };
 
-constexpr double TIE_REL = 1.0e-12;
+// relative band of a stationary contact, per arithmetic precision
+constexpr double TIE_REL64 = 1.0e-12;
+constexpr double TIE_REL32 = 1.0e-6;
 
 // Per-instance descriptor (device memory).
 struct Inst {
@@ -88,6 +90,35 @@ struct Stage {
     T* out;         // stage output
   };
 
+  // critical-damage level for the stored precision (the advected ratio
+  // (phi rho D)/(phi rho) returns D_crit only to the storage rounding)
+  FV_HD static double crit_level(const MatP& m) {
+    return sizeof(T) == 8 ? m.Dcrit_eff : m.Dcrit_eff32;
+  }
+
+  // FP64 island of the FP32-bulk policy: the mixture pressure inversion of a
+  // cell holding a trace volume fraction, with the phasic masses, energy and
+  // the sums in double (reference terms from the FP32 closures).
+  FV_HD static C island_pressure(const Params& P, const C* U, const Mix<NM, NS, C>& mx) {
+    double rho = 0, xi = 0;
+#pragma unroll
+    for (int l = 0; l < NM; ++l) {
+      rho += m_max((double)U[L::MASS + l], 0.0);
+      xi += (double)U[L::PHI + l] * P.mat[l].invGamma;
+    }
+    double m2 = 0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) m2 += (double)U[L::MOM + k] * (double)U[L::MOM + k];
+    double th = (double)U[L::ENE] - 0.5 * m2 / rho, cold = 0;
+#pragma unroll
+    for (int l = 0; l < NM; ++l) {
+      const double ph = (double)U[L::PHI + l];
+      th = th - ph * (double)mx.t[l].rho_eref;
+      cold = cold + ph * (double)mx.t[l].pref * P.mat[l].invGamma;
+    }
+    return (C)((m_max(th, 0.0) + cold) / xi);
+  }
+
   FV_HD static int map_index(int g, int n, int bclo, int bchi) {
     if (g < 0) return bclo == BC_PERIODIC ? g + n : 0;
     if (g >= n) return bchi == BC_PERIODIC ? g - n : n - 1;
@@ -135,7 +166,14 @@ struct Stage {
     const C J2 = J2_of<DIM, C>(H);
     Mix<NM, NS, C> mx;
     mix_terms<NM, NS, C>(cx.P, phi, rho_l, D, J2, mx);
-    const C p = mix_pressure<NM, NS, C>(cx.P, phi, mx, rho_e);
+    C p;
+    bool island = false;
+    if (sizeof(C) == 4) {
+#pragma unroll
+      for (int l = 0; l < NM; ++l) island = island || phi[l] < (C)cx.P.phi_fp64_cut;
+    }
+    if (island) p = island_pressure(cx.P, U, mx);
+    else p = mix_pressure<NM, NS, C>(cx.P, phi, mx, rho_e);
     C Gmix = 0;
 #pragma unroll
     for (int l = 0; l < NM; ++l) Gmix += phi[l] * mx.t[l].G;
@@ -143,7 +181,7 @@ struct Stage {
     C crit = 0;
 #pragma unroll
     for (int s = 0; s < NS; ++s)
-      if (D[s] >= (C)cx.P.mat[s].Dcrit_eff) crit = 1;
+      if (D[s] >= (C)crit_level(cx.P.mat[s])) crit = 1;
     const int NCELL = TL::NCELL;
 #pragma unroll
     for (int l = 0; l < NM; ++l) {
@@ -174,7 +212,7 @@ struct Stage {
   struct Side {
     C phi[NM], rho_l[NM], eps[NS > 0 ? NS : 1], D[NS > 0 ? NS : 1];
     C u[3], p, H[3][3], V[3][3];
-    C rho, rhoE, c, t[3];
+    C rho, rhoE, c, G, t[3];
     C Uc[NC];
   };
 
@@ -213,6 +251,7 @@ struct Stage {
     s.rhoE = rho_e + (C)0.5 * rho * (s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2]);
     C Gmix;
     s.c = mix_sound<NM, NS, C>(P, s.phi, mx, s.p, rho, Gmix);
+    s.G = Gmix;
     const C sf = solid_frac<NM, C>(s.phi);
 #pragma unroll
     for (int i = 0; i < 3; ++i) s.t[i] = (C)2 * Gmix * s.H[i][a] - (i == a ? sf * s.p : (C)0);
@@ -238,18 +277,27 @@ struct Stage {
     F[L::C_ENE] -= s.u[0] * s.t[0] + s.u[1] * s.t[1] + s.u[2] * s.t[2];
   }
 
-  FV_HD static void star_flux(const Side& s, int a, C SK, C Ss, const C* FK, C* Fs) {
+  // Star-region flux of side K with the contact's tangential state resolved
+  // (see compute_face): mass/history chi U S*, normal momentum
+  // rho* S*^2 - t_n*, tangential momentum rho* u_t** S* - t_t**, energy
+  // E** S* - S* t_n* - u_t** . t_t**.
+  FV_HD static void star_flux(const Side& s, int a, C SK, C Ss, C tn_star,
+                              const C* ut2, const C* tt2, C work, C* Fs) {
     const C un = s.u[a];
     const C chi = (SK - un) / (SK - Ss);
-    C Us[NC];
+    const C rs = chi * s.rho;
+    const C Es = chi * (s.rhoE + (Ss - un) * (s.rho * Ss - s.t[a] / (SK - un)));
+    C dke = 0;
 #pragma unroll
-    for (int q = 0; q < NC; ++q) Us[q] = s.Uc[q] * chi;
+    for (int k = 0; k < 3; ++k)
+      if (k != a) dke += ut2[k] * ut2[k] - s.u[k] * s.u[k];
+    const C Ess = Es + (C)0.5 * rs * dke;
+#pragma unroll
+    for (int q = 0; q < L::C_MOM; ++q) Fs[q] = s.Uc[q] * (chi * Ss);
 #pragma unroll
     for (int k = 0; k < DIM; ++k)
-      Us[L::C_MOM + k] = chi * s.rho * (s.u[k] + (k == a ? Ss - un : (C)0));
-    Us[L::C_ENE] = chi * (s.rhoE + (Ss - un) * (s.rho * Ss - s.t[a] / (SK - un)));
-#pragma unroll
-    for (int q = 0; q < NC; ++q) Fs[q] = FK[q] + SK * (Us[q] - s.Uc[q]);
+      Fs[L::C_MOM + k] = k == a ? rs * Ss * Ss - tn_star : rs * ut2[k] * Ss - tt2[k];
+    Fs[L::C_ENE] = Ess * Ss - Ss * tn_star - work;
   }
 
   // Face a of the tile: W pointers of the four stencil cells (cm, c0 | c1, c2)
@@ -282,32 +330,47 @@ struct Stage {
     // contact and face speeds below TIE_REL of the largest signal speed are
     // stationary: the upwind choices take the mean of the two sides (the star
     // fluxes differ by the tangential-traction jump at a zero contact speed)
-    const C tie = (C)TIE_REL * m_max(m_abs(SL), m_abs(SR));
-    C F[NC];
-    {
-      C FL[NC], FR[NC];
-      phys_flux(sL, a, FL);
-      phys_flux(sR, a, FR);
-      if (SL >= (C)0) {
+    const C tie = (C)(sizeof(C) == 8 ? TIE_REL64 : TIE_REL32) * m_max(m_abs(SL), m_abs(SR));
+    // Contact tangential state from the linearised shear waves on either
+    // side (impedance Z = sqrt(G rho)); free slip against a fluid.  Without
+    // it the star fluxes would take one side's tangential traction,
+    // upwinded by S*, which lets shear waves grow.
+    const C ZL = m_sqrt(sL.G * sL.rho), ZR = m_sqrt(sR.G * sR.rho);
+    const C Zs = ZL + ZR;
+    C ut2[3] = {0, 0, 0}, tt2[3] = {0, 0, 0};
 #pragma unroll
-        for (int q = 0; q < NC; ++q) F[q] = FL[q];
-      } else if (SR <= (C)0) {
-#pragma unroll
-        for (int q = 0; q < NC; ++q) F[q] = FR[q];
+    for (int k = 0; k < 3; ++k) {
+      if (k == a) continue;
+      if (Zs > (C)0) {
+        ut2[k] = (ZL * sL.u[k] + ZR * sR.u[k] + (sR.t[k] - sL.t[k])) / Zs;
+        tt2[k] = sL.t[k] + ZL * (ut2[k] - sL.u[k]);
       } else {
-        C FsL[NC], FsR[NC];
-        star_flux(sL, a, SL, Ss, FL, FsL);
-        star_flux(sR, a, SR, Ss, FR, FsR);
-#pragma unroll
-        for (int q = 0; q < NC; ++q)
-          F[q] = Ss > tie ? FsL[q] : (Ss < -tie ? FsR[q] : (C)0.5 * (FsL[q] + FsR[q]));
+        ut2[k] = Ss > tie ? sL.u[k] : (Ss < -tie ? sR.u[k] : (C)0.5 * (sL.u[k] + sR.u[k]));
       }
+    }
+    const C tn_star = (C)0.5 * ((sL.t[a] - sL.rho * (SL - unL) * (Ss - unL)) +
+                                (sR.t[a] - sR.rho * (SR - unR) * (Ss - unR)));
+    C work = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (k != a) work += ut2[k] * tt2[k];
+    C F[NC];
+    if (SL >= (C)0) {
+      phys_flux(sL, a, F);
+    } else if (SR <= (C)0) {
+      phys_flux(sR, a, F);
+    } else {
+      C FsL[NC], FsR[NC];
+      star_flux(sL, a, SL, Ss, tn_star, ut2, tt2, work, FsL);
+      star_flux(sR, a, SR, Ss, tn_star, ut2, tt2, work, FsR);
+#pragma unroll
+      for (int q = 0; q < NC; ++q)
+        F[q] = Ss > tie ? FsL[q] : (Ss < -tie ? FsR[q] : (C)0.5 * (FsL[q] + FsR[q]));
     }
     C uf = SL > (C)0 ? unL : (SR < (C)0 ? unR : Ss);
     C ut[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      ut[k] = Ss > tie ? sL.u[k] : (Ss < -tie ? sR.u[k] : (C)0.5 * (sL.u[k] + sR.u[k]));
+    for (int k = 0; k < 3; ++k) ut[k] = SL > (C)0 ? sL.u[k] : (SR < (C)0 ? sR.u[k] : ut2[k]);
     // upwinded geometric face values
     const bool up = uf > tie, dn = uf < -tie;
     C phif[NM], Vf[L::NV], Xf[DIM];
@@ -338,13 +401,22 @@ struct Stage {
     const bool lo_b = gface == 0, hi_b = gface == n;
     const bool periodic = I.bc[a][0] == BC_PERIODIC;
     if ((!lo_b && !hi_b) || periodic) {
-      // void-opening modifier (Section 3.1)
+      // void-opening modifier (Section 3.1): next to a critically damaged
+      // cell, when the pair is in tension
       const bool crit = W[L::W_CRIT * NCELL + c0] > (C)0 || W[L::W_CRIT * NCELL + c1] > (C)0;
       const C tens = W[(L::W_SIG + a) * NCELL + c0] + W[(L::W_SIG + a) * NCELL + c1];
-      if (crit && tens > (C)0) {
+      // open only while the two free surfaces separate
+      if (crit && tens > (C)0 && usL <= usR) {
+        // no traction; a side whose one-sided velocity points through the
+        // face carries its material into the neighbour, else void enters it
         os = 1;
+        const C oL = usL > (C)0 ? usL : (C)0;
+        const C oR = usR < (C)0 ? usR : (C)0;
 #pragma unroll
-        for (int q = 0; q < NC; ++q) F[q] = 0;
+        for (int q = 0; q < NC; ++q) F[q] = sL.Uc[q] * oL + sR.Uc[q] * oR;
+        // opened faces store the shared volume-fraction flux in Q_PHI
+#pragma unroll
+        for (int l = 0; l < NM; ++l) phif[l] = sL.phi[l] * oL + sR.phi[l] * oR;
       }
     } else if ((lo_b && I.bc[a][0] == BC_FREE) || (hi_b && I.bc[a][1] == BC_FREE)) {
       const Side& sK = lo_b ? sR : sL;
@@ -367,6 +439,8 @@ struct Stage {
         os = 1;
 #pragma unroll
         for (int q = 0; q < NC; ++q) F[q] = 0;
+#pragma unroll
+        for (int l = 0; l < NM; ++l) phif[l] = 0;
       }
     }
     // outward boundary flux accumulation, RK3 weights 1/6, 1/6, 2/3
@@ -476,7 +550,7 @@ struct Stage {
       uv[0] = uc[0]; uv[1] = uc[1]; uv[2] = uc[2];
       uv[a] = us;
 #pragma unroll
-      for (int l = 0; l < NM; ++l) o.phif[l] = 0;
+      for (int l = 0; l < NM; ++l) o.phif[l] = fb[(L::Q_PHI + l) * NF + fslot];
 #pragma unroll
       for (int k = 0; k < DIM; ++k) o.Xfl[k] = Xc[k] * us;
 #pragma unroll
@@ -626,8 +700,8 @@ struct Stage {
     for (int s = 0; s < NS; ++s) {
       const MatP& m = P.mat[s];
       const double w = 1.0 - D[s];
-      Gm += phi[s] * w * shear_modulus_undamaged<double>(m, rho_l[s]);
-      const double sy = D[s] < m.Dcrit_eff ? pert * m.yield : 0.0;
+      Gm += phi[s] * w * shear_modulus_undamaged<double>(m, closure_density(m, phi[s], rho_l[s]));
+      const double sy = D[s] < crit_level(m) ? pert * m.yield : 0.0;
       Ymix += phi[s] * w * sy;
     }
     const double Jmax = Gm > 0.0 ? Ymix / (sqrt(6.0) * Gm) : 0.0;
@@ -647,9 +721,9 @@ struct Stage {
     for (int s = 0; s < NS; ++s) {
       const MatP& m = P.mat[s];
       const double seq = (1.0 - D[s]) * pert * m.yield;
-      bool gate = (p < m.pgate) && (deps > 0.0) && (D[s] < m.Dcrit_eff);
+      bool gate = (p < m.pgate) && (deps > 0.0) && (D[s] < crit_level(m));
       const bool ok = seq > 0.0;
-      const double R = ok ? triaxiality(m, p, seq, rho_l[s]) : 1.0;
+      const double R = ok ? triaxiality(m, p, seq, closure_density(m, phi[s], rho_l[s])) : 1.0;
       if (gate) {
         const double thr = eps_threshold(m, R);
         gate = (eps[s] > thr) || !ok;

@@ -240,3 +240,27 @@ def test_full_size_ring_sampled_windows():
         for f in range(L.S):
             sc = np.max(np.abs(U[f])) + 1e-300
             assert np.max(np.abs(got[f] - ref[f])) <= TOL * sc, (x0, y0, f)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_size_ring_long_run_stays_physical(precision):
+    """400 steps of the 1024^2 ring (1.45 us): no non-physical flag, and the
+    plastic strain of the bulk solid stays at the in-plane expansion value
+    (strain rate 150 / 26.5 mm ~ 5.7e3 /s, so eps_p ~ 0.008)."""
+    from paper_2210_04037_amd.solver import GpuSolver
+    case = F.make_case(2)
+    print(f"[long] ring 1024^2 {precision} 400 steps", flush=True)
+    g = GpuSolver(case, precision=precision)
+    g.step(400)
+    dt = g.cfl_dt()                     # raises on the device flag
+    W = g.primitive(0)
+    t = g.time()[0]
+    g.close()
+    assert dt[0] > 0
+    L = Layout(2, case.mats)
+    solid = W[L.phi[0]] > 0.99
+    eps = W[L.eps[0]][solid]
+    assert solid.sum() > 1000
+    assert np.isfinite(W).all()
+    assert 0.3 * 5.66e3 * t < np.median(eps) < 3.0 * 5.66e3 * t
+    assert W[L.dmg[0]][solid].max() < 0.5
