@@ -104,6 +104,21 @@ def run_gpu(case, precision, steps, warmup):
     return ms, S, elem, t
 
 
+def calibrate_copy(nbytes=1 << 30, reps=5):
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters of rocprofv3 to bytes."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read_per_copy": nbytes,
+                      "bytes_written_per_copy": nbytes, "copies": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,7 +127,12 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a 1 GiB device copy (counter scaling)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is "
               "not supported (the multi-GPU sharding is a design note only)",
