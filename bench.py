@@ -23,7 +23,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2210_04037_amd", "csrc", f)
-                  for f in ("fv_core.hpp", "fv_stage.hpp", "fv_api.hip")]
+                  for f in ("fv_core.hpp", "fv_stage.hpp", "fv_kernels.hpp",
+                            "fv_api.hip", "fv_fp32.hip")]
 
 
 def kernel_source_hash():

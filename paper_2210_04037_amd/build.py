@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfv.so")
 
 FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-shared", "-fPIC",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
@@ -23,18 +23,38 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
+# per translation unit: the FP32-bulk kernels take fast reciprocals and
+# approximate transcendental functions, the FP64 form keeps IEEE arithmetic
+UNITS = [
+    ("fv_api.hip", []),
+    ("fv_fp32.hip", ["-fno-hip-fp32-correctly-rounded-divide-sqrt",
+                     "-freciprocal-math", "-fapprox-func", "-fno-math-errno"]),
+]
+
+
 def build(verbose=False, extra=()):
-    src = os.path.join(CSRC, "fv_api.hip")
+    objs = []
+    for src, flags in UNITS:
+        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
+        cmd = ([hipcc()] + FLAGS + flags + list(extra)
+               + ["-c", "-o", obj, os.path.join(CSRC, src)])
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError(f"hipcc failed on {src}")
+        objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + list(extra) + ["-o", tmp, src]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed")
-    if verbose and r.stderr:
-        sys.stderr.write(r.stderr)
+        raise RuntimeError("link failed")
+    for o in objs:
+        os.remove(o)
     os.replace(tmp, LIB)
     return LIB
 

@@ -12,85 +12,17 @@
 #include <string>
 #include <vector>
 
-#include "fv_stage.hpp"
-#include "../../include/fv.h"
+#include "fv_kernels.hpp"
 
 using namespace fv;
+using namespace fvk;
+
+namespace fvk {
+// FP32-bulk launchers, defined in fv_fp32.hip
+bool select_ops_fp32(int dim, int nm, int ns, Ops& o, hipError_t& herr, bool set_attr);
+}
 
 namespace {
-
-constexpr int NBINS = 70;  // 32-bit bins covering every finite double
-
-// ---------------------------------------------------------------------------
-// reductions
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// Block maximum of a non-negative value, then an integer atomicMax on its
-// bit pattern (order-preserving for non-negative doubles), so the result is
-// independent of the order in which blocks finish.
-template <int NT>
-__device__ void block_max_to(double v, double* scratch, double* target) {
-  v = wave_max(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  constexpr int NWV = (NT + 63) / 64;
-  if (lane == 0) scratch[wid] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = scratch[0];
-    for (int w = 1; w < NWV; ++w) m = fmax(m, scratch[w]);
-    if (m > 0.0)
-      atomicMax(reinterpret_cast<unsigned long long*>(target),
-                (unsigned long long)__double_as_longlong(m));
-  }
-}
-
-// Exact sum into 32-bit bins of the integer value * 2^1074.
-__device__ __forceinline__ void bin_add(unsigned long long* bins, double v) {
-  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-  const int ex = (int)((bits >> 52) & 0x7FF);
-  if (ex == 0x7FF) return;              // non-finite values are flagged elsewhere
-  unsigned long long m = bits & ((1ull << 52) - 1);
-  int shift;
-  if (ex == 0) {
-    shift = 0;                          // subnormal: m * 2^-1074
-  } else {
-    m |= 1ull << 52;
-    shift = ex - 1;                     // m * 2^(ex - 1075) = m * 2^(shift - 1074)
-  }
-  if (m == 0) return;
-  const int k0 = shift >> 5, off = shift & 31;
-  const unsigned long long mlo = m & 0xFFFFFFFFull, mhi = m >> 32;
-  const unsigned long long t0 = mlo << off, t1 = mhi << off;
-  const unsigned long long c0 = t0 & 0xFFFFFFFFull;
-  const unsigned long long c1 = (t0 >> 32) + (t1 & 0xFFFFFFFFull);
-  const unsigned long long c2 = t1 >> 32;
-  const bool neg = (bits >> 63) != 0;
-  // two's complement wrap-around makes unsigned adds of negated chunks exact
-  atomicAdd(&bins[k0], neg ? (0ull - c0) : c0);
-  atomicAdd(&bins[k0 + 1], neg ? (0ull - c1) : c1);
-  if (c2) atomicAdd(&bins[k0 + 2], neg ? (0ull - c2) : c2);
-}
-
-template <class T>
-__global__ void __launch_bounds__(256) exact_sum_kernel(const T* data, int64_t n,
-                                                        int64_t stride,
-                                                        unsigned long long* out) {
-  __shared__ unsigned long long bins[NBINS];
-  for (int k = threadIdx.x; k < NBINS; k += blockDim.x) bins[k] = 0;
-  __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    bin_add(bins, (double)data[i * stride]);
-  __syncthreads();
-  for (int k = threadIdx.x; k < NBINS; k += blockDim.x)
-    if (bins[k]) atomicAdd(&out[k], bins[k]);
-}
-
 // Correctly rounded (ties to even) value of sum_k bins[k] 2^(32k) 2^-1074.
 double bins_to_double(const unsigned long long* ub) {
   long long bins[NBINS];
@@ -142,164 +74,7 @@ double bins_to_double(const unsigned long long* ub) {
   return neg ? -r : r;
 }
 
-// ---------------------------------------------------------------------------
-// stage kernel
-// ---------------------------------------------------------------------------
-template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY)
-stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int parity) {
-  using St = Stage<DIM, NM, NS, T, C, TX, TY>;
-  using TL = typename St::TL;
-  constexpr int NT = TX * TY;
-  extern __shared__ double smem_d[];
-  C* sm = reinterpret_cast<C*>(smem_d);
-  C* fb = sm + (size_t)St::NW * TL::NCELL;
-  const int b = blockIdx.x;
-  const int ii = block_inst[b];
-  const Inst& I = insts[ii];
-  double* dts = I.dts;
-  const int q = parity & 1;
-  const double t = dts[DTS_T + q];
-  const double dtinv = dts[DTS_DTINV + q];
-  double dt = dts[DTS_DTFIX] > 0.0 ? dts[DTS_DTFIX] : P.cfl / dtinv;
-  dt = fmin(dt, dts[DTS_TEND] - t);
-  const int lb = b - I.block_begin;
-  const int tid = threadIdx.x;
-  if (!(dt > 0.0)) {
-    if (stage == 1 && lb == 0 && tid == 0) {
-      dts[DTS_T + 1 - q] = t;
-      dts[DTS_DTINV + 1 - q] = dtinv;
-    }
-    return;
-  }
-  if (stage == 1 && lb == 0 && tid == 0) {
-    dts[DTS_T + 1 - q] = t + dt;
-    dts[DTS_DTINV + 1 - q] = 0.0;
-  }
-  typename St::Ctx cx;
-  cx.I = &I;
-  cx.P = P;
-  cx.stage = stage;
-  cx.parity = q;
-  cx.bx = lb % I.tiles[0];
-  cx.by = lb / I.tiles[0];
-  cx.dt = (C)dt;
-  const T* U = (const T*)I.U;
-  cx.base = U;
-  cx.src = stage == 1 ? U : (stage == 2 ? (const T*)I.U1 : (const T*)I.U2);
-  cx.out = stage == 1 ? (T*)I.U1 : (stage == 2 ? (T*)I.U2 : (T*)I.U);
-
-  for (int tc = tid; tc < TL::NCELL; tc += NT) St::load_cell(cx, sm, tc);
-  __syncthreads();
-
-  C acc[St::S];
-#pragma unroll
-  for (int f = 0; f < St::S; ++f) acc[f] = 0;
-  int tx, ty;
-  int64_t g = 0;
-  const bool own = St::own_cell(cx, tid, tx, ty, g);
-#pragma unroll
-  for (int a = 0; a < DIM; ++a) {
-    const int nit = St::face_items(a);
-    for (int it = tid; it < nit; it += NT) {
-      int cm, c0, c1, c2, gf, fs, bs;
-      if (St::face_item(cx, a, it, cm, c0, c1, c2, gf, fs, bs))
-        St::compute_face(cx, sm, a, cm, c0, c1, c2, gf, fs, bs, fb);
-    }
-    __syncthreads();
-    if (own) St::gather(cx, sm, fb, a, tx, ty, acc);
-    __syncthreads();
-  }
-  double cflv = 0.0;
-  if (own) {
-    bool bad = false;
-    cflv = St::finish_cell(cx, g, acc, &bad);
-    if (bad) atomicOr(reinterpret_cast<unsigned int*>(&dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);
-  }
-  if (stage == 3) block_max_to<NT>(cflv, reinterpret_cast<double*>(smem_d), &dts[DTS_DTINV + 1 - q]);
-}
-
-// ---------------------------------------------------------------------------
-// primitive <-> conserved, CFL
-// ---------------------------------------------------------------------------
-template <int DIM, int NM, int NS, class T>
-__global__ void __launch_bounds__(256) prim_to_cons_kernel(const Inst* insts, int ii, Params P,
-                                                           const double* prim) {
-  using L = Lay<DIM, NM, NS>;
-  const Inst& I = insts[ii];
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= I.ncell) return;
-  double W[L::S], U[L::S];
-  for (int f = 0; f < L::S; ++f) W[f] = prim[(int64_t)f * I.ncell + g];
-  Cell<DIM, NM, NS>::prim_to_cons(P, W, U);
-  T* Us = (T*)I.U;
-  for (int f = 0; f < L::S; ++f) Us[(int64_t)f * I.ncell + g] = (T)U[f];
-}
-
-template <int DIM, int NM, int NS, class T>
-__global__ void __launch_bounds__(256) cons_to_prim_kernel(const Inst* insts, int ii, Params P,
-                                                           double* prim) {
-  using L = Lay<DIM, NM, NS>;
-  const Inst& I = insts[ii];
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= I.ncell) return;
-  const T* Us = (const T*)I.U;
-  double U[L::S], W[L::S];
-  for (int f = 0; f < L::S; ++f) U[f] = (double)Us[(int64_t)f * I.ncell + g];
-  Cell<DIM, NM, NS>::cons_to_prim(P, U, W);
-  for (int f = 0; f < L::S; ++f) prim[(int64_t)f * I.ncell + g] = W[f];
-}
-
-template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
-__global__ void __launch_bounds__(256) cfl_kernel(const Inst* insts, int ii, Params P, int parity) {
-  using St = Stage<DIM, NM, NS, T, C, TX, TY>;
-  using L = Lay<DIM, NM, NS>;
-  __shared__ double scratch[4];
-  const Inst& I = insts[ii];
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double v = 0.0;
-  if (g < I.ncell) {
-    const T* Us = (const T*)I.U;
-    double U[L::S];
-    for (int f = 0; f < L::S; ++f) U[f] = (double)Us[(int64_t)f * I.ncell + g];
-    v = St::cfl_sum(P, I, U);
-    if (!(v == v)) {
-      atomicOr(reinterpret_cast<unsigned int*>(&I.dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);
-      v = 0.0;
-    }
-  }
-  block_max_to<256>(v, scratch, &I.dts[DTS_DTINV + (parity & 1)]);
-}
-
 }  // namespace
-
-// ---------------------------------------------------------------------------
-// context
-// ---------------------------------------------------------------------------
-struct Ops {
-  int S = 0, NC = 0, NTOT = 0, TX = 0, TY = 0, NT = 0;
-  size_t smem = 0;
-  void (*stage)(fv_ctx*, int, int) = nullptr;
-  void (*p2c)(fv_ctx*, int, const double*) = nullptr;
-  void (*c2p)(fv_ctx*, int, double*) = nullptr;
-  void (*cfl)(fv_ctx*, int, int) = nullptr;
-  size_t elem = 8;
-};
-
-struct fv_ctx {
-  int n_inst = 0, dim = 0, nm = 0, ns = 0, precision = 0;
-  Params P{};
-  hipStream_t stream = nullptr;
-  std::vector<Inst> insts;
-  Inst* insts_d = nullptr;
-  int* block_inst_d = nullptr;
-  unsigned long long* bins_d = nullptr;
-  int total_blocks = 0;
-  long long step = 0;
-  Ops ops;
-  std::vector<double> h_dt, h_tend;   // staging for async copies
-  std::string err;
-};
 
 static std::string g_init_error;
 
@@ -313,71 +88,17 @@ static int hip_check(fv_ctx* c, hipError_t e, const char* what) {
   return fail(c, FV_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
-static Ops make_ops() {
-  using St = Stage<DIM, NM, NS, T, C, TX, TY>;
-  using L = Lay<DIM, NM, NS>;
-  Ops o;
-  o.S = L::S;
-  o.NC = L::NC;
-  o.NTOT = NM + DIM + 1;
-  o.TX = TX;
-  o.TY = TY;
-  o.NT = TX * TY;
-  o.elem = sizeof(T);
-  o.smem = St::smem_bytes();
-  o.stage = [](fv_ctx* c, int stage, int parity) {
-    hipLaunchKernelGGL((stage_kernel<DIM, NM, NS, T, C, TX, TY>), dim3(c->total_blocks),
-                       dim3(TX * TY), St::smem_bytes(), c->stream, c->insts_d,
-                       c->block_inst_d, c->P, stage, parity);
-  };
-  o.p2c = [](fv_ctx* c, int ii, const double* prim) {
-    const int64_t n = c->insts[ii].ncell;
-    hipLaunchKernelGGL((prim_to_cons_kernel<DIM, NM, NS, T>), dim3((unsigned)((n + 255) / 256)),
-                       dim3(256), 0, c->stream, c->insts_d, ii, c->P, prim);
-  };
-  o.c2p = [](fv_ctx* c, int ii, double* prim) {
-    const int64_t n = c->insts[ii].ncell;
-    hipLaunchKernelGGL((cons_to_prim_kernel<DIM, NM, NS, T>), dim3((unsigned)((n + 255) / 256)),
-                       dim3(256), 0, c->stream, c->insts_d, ii, c->P, prim);
-  };
-  o.cfl = [](fv_ctx* c, int ii, int parity) {
-    const int64_t n = c->insts[ii].ncell;
-    hipLaunchKernelGGL((cfl_kernel<DIM, NM, NS, T, C, TX, TY>), dim3((unsigned)((n + 255) / 256)),
-                       dim3(256), 0, c->stream, c->insts_d, ii, c->P, parity);
-  };
-  return o;
-}
 
-template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
-static hipError_t set_smem_attr() {
-  using St = Stage<DIM, NM, NS, T, C, TX, TY>;
-  return hipFuncSetAttribute((const void*)&stage_kernel<DIM, NM, NS, T, C, TX, TY>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)St::smem_bytes());
-}
-
-// supported combinations; returns false if none matches
 // set_attr: also raise the kernel's dynamic LDS limit (a HIP runtime call;
 // size-only queries skip it so that they run without a device)
 static bool select_ops(int dim, int nm, int ns, int prec, Ops& o, hipError_t& herr,
                        bool set_attr = true) {
   herr = hipSuccess;
-#define FV_SEL(D, M, S_, TT, CC, X, Y)                           \
-  if (dim == D && nm == M && ns == S_ && prec == (sizeof(TT) == 8 ? FV_FP64 : FV_FP32_BULK)) { \
-    o = make_ops<D, M, S_, TT, CC, X, Y>();                     \
-    if (set_attr) herr = set_smem_attr<D, M, S_, TT, CC, X, Y>(); \
-    return true;                                                \
-  }
+  if (prec == FV_FP32_BULK) return select_ops_fp32(dim, nm, ns, o, herr, set_attr);
   FV_SEL(1, 1, 1, double, double, 256, 1)
   FV_SEL(1, 2, 1, double, double, 256, 1)
   FV_SEL(2, 1, 1, double, double, 32, 8)
   FV_SEL(2, 2, 1, double, double, 32, 8)
-  FV_SEL(1, 1, 1, float, float, 256, 1)
-  FV_SEL(1, 2, 1, float, float, 256, 1)
-  FV_SEL(2, 1, 1, float, float, 32, 8)
-  FV_SEL(2, 2, 1, float, float, 32, 8)
-#undef FV_SEL
   return false;
 }
 

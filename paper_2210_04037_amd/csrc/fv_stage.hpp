@@ -359,13 +359,16 @@ struct Stage {
       phys_flux(sL, a, F);
     } else if (SR <= (C)0) {
       phys_flux(sR, a, F);
+    } else if (Ss > tie) {
+      star_flux(sL, a, SL, Ss, tn_star, ut2, tt2, work, F);
+    } else if (Ss < -tie) {
+      star_flux(sR, a, SR, Ss, tn_star, ut2, tt2, work, F);
     } else {
       C FsL[NC], FsR[NC];
       star_flux(sL, a, SL, Ss, tn_star, ut2, tt2, work, FsL);
       star_flux(sR, a, SR, Ss, tn_star, ut2, tt2, work, FsR);
 #pragma unroll
-      for (int q = 0; q < NC; ++q)
-        F[q] = Ss > tie ? FsL[q] : (Ss < -tie ? FsR[q] : (C)0.5 * (FsL[q] + FsR[q]));
+      for (int q = 0; q < NC; ++q) F[q] = (C)0.5 * (FsL[q] + FsR[q]);
     }
     C uf = SL > (C)0 ? unL : (SR < (C)0 ? unR : Ss);
     C ut[3];
@@ -734,16 +737,37 @@ struct Stage {
       U[L::HIST + 2 * s] = ms * (eps[s] + deps);
       U[L::HIST + 2 * s + 1] = ms * Dn[s];
     }
-    // CFL sum on the new state
-    const double J2n = J2_of<DIM, double>(H);
-    Mix<NM, NS, double> mx2;
-    mix_terms<NM, NS, double>(P, phi, rho_l, Dn, J2n, mx2);
-    const double p2 = mix_pressure<NM, NS, double>(P, phi, mx2, rho_e);
-    double Gmix;
-    const double c = mix_sound<NM, NS, double>(P, phi, mx2, p2, rho, Gmix);
+    // CFL sum on the new state, in the policy precision C
+    C phic[NM], rlc[NM], Dc[NS > 0 ? NS : 1];
+#pragma unroll
+    for (int l = 0; l < NM; ++l) { phic[l] = (C)phi[l]; rlc[l] = (C)rho_l[l]; }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) Dc[s] = (C)Dn[s];
+    const C J2n = (C)J2_of<DIM, double>(H);
+    Mix<NM, NS, C> mx2;
+    mix_terms<NM, NS, C>(P, phic, rlc, Dc, J2n, mx2);
+    bool isl = false;
+#pragma unroll
+    for (int l = 0; l < NM; ++l) isl = isl || phic[l] < (C)P.phi_fp64_cut;
+    C p2;
+    if (sizeof(C) == 8 || !isl) {
+      p2 = mix_pressure<NM, NS, C>(P, phic, mx2, (C)rho_e);
+    } else {
+      // FP64 island, as in the stages: the inversion of a trace cell in double
+      double xi = 0, th = rho_e, cold = 0;
+#pragma unroll
+      for (int l = 0; l < NM; ++l) {
+        xi += phi[l] * P.mat[l].invGamma;
+        th -= phi[l] * (double)mx2.t[l].rho_eref;
+        cold += phi[l] * (double)mx2.t[l].pref * P.mat[l].invGamma;
+      }
+      p2 = (C)((m_max(th, 0.0) + cold) / xi);
+    }
+    C Gmix;
+    const C c = mix_sound<NM, NS, C>(P, phic, mx2, p2, (C)rho, Gmix);
     double sum = 0;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) sum += (fabs(u[k]) + c) / I.dx[k];
+    for (int k = 0; k < DIM; ++k) sum += (fabs(u[k]) + (double)c) / I.dx[k];
     return sum;
   }
 
