@@ -1,5 +1,9 @@
 """Throughput of the fracture hot path on one MI355X.
 
+The timed form is the FP32-bulk one by default; the plain FP64 form runs
+after it on the same workload for the comparison (its throughput and the
+per-field L1 error of FP32-bulk against it).
+
 One step = one full time step of the whole hot path over the 1024^2
 expanding-ring workload: three SSP-RK3 stage launches (reconstruction, HLLC
 with the void-opening modifier, conservative update) with the source step
@@ -84,9 +88,12 @@ def cpu_baseline(case, seconds=15.0):
 
 
 def run_gpu(case, precision, steps, warmup):
+    """Time `steps` steps after `warmup` untimed ones; return the timing and
+    the primitive state and conservation totals at the end."""
     import torch
     from paper_2210_04037_amd.solver import GpuSolver
     g = GpuSolver(case, precision=precision, device="cuda:0")
+    tot0, _ = g.totals()
     g.step(warmup)
     torch.cuda.synchronize()
     s = g.stream
@@ -99,10 +106,46 @@ def run_gpu(case, precision, steps, warmup):
     ms = e0.elapsed_time(e1)
     t = g.time()[0]
     g.cfl_dt()          # raises if the device flagged a non-physical state
+    tot1, out1 = g.totals()
+    W = g.primitive(0)
     S = g.S
     elem = 8 if precision == "fp64" else 4
     g.close()
-    return ms, S, elem, t
+    return dict(ms=ms, S=S, elem=elem, t=t, W=W, tot0=tot0[0],
+                tot1=tot1[0] + out1[0])
+
+
+def precision_report(case, r32, r64):
+    """Per-field L1 of the FP32-bulk run against the FP64 run after the same
+    steps (relative to the FP64 field's L1; eps_p and D over solid cells),
+    and the relative conservation drift of the FP32-bulk run."""
+    import numpy as np
+    from paper_2210_04037_amd.abi import state_rows
+    rows = state_rows(case.dim, len(case.mats),
+                      [m["kind"] == "solid" for m in case.mats])
+    W32, W64 = r32["W"], r64["W"]
+
+    def l1(a, b, mask=None):
+        if mask is not None:
+            a, b = a[mask], b[mask]
+        den = np.sum(np.abs(b))
+        return float(np.sum(np.abs(a - b)) / den) if den > 0 else 0.0
+
+    rho = lambda W: np.sum(W[rows["phi"]] * W[rows["mass"]], axis=0)
+    spd = lambda W: np.sqrt(np.sum(W[rows["mom"]] ** 2, axis=0))
+    solid = W64[rows["phi"][0]] > 0.5
+    nm = len(case.mats)
+    c0, c1 = r32["tot0"], r32["tot1"]
+    return {
+        "l1_rel_vs_fp64": {
+            "rho": l1(rho(W32), rho(W64)), "u": l1(spd(W32), spd(W64)),
+            "eps_p": l1(W32[rows["eps"][0]], W64[rows["eps"][0]], solid),
+            "D": l1(W32[rows["dmg"][0]], W64[rows["dmg"][0]], solid)},
+        "bars": {"rho": 1e-4, "u": 1e-3, "eps_p": 1e-3, "D": 1e-2},
+        "mass_drift": max(abs(c1[l] - c0[l]) / abs(c0[l]) for l in range(nm)),
+        "energy_drift": abs(c1[-1] - c0[-1]) / abs(c0[-1]),
+        "sim_time_fp32_fp64": [r32["t"], r64["t"]],
+    }
 
 
 def calibrate_copy(nbytes=1 << 30, reps=5):
@@ -125,7 +168,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"],
+                    help="timed form: fp32 = FP32-bulk (default), fp64 = plain")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the run of the other form (throughput and "
+                         "per-field L1 error of FP32-bulk against FP64)")
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -142,7 +189,9 @@ def main():
     import fvinputs as F
     case = F.make_case(2, n=args.n)
     ncell = case.n_cells
-    ms, S, elem, t_sim = run_gpu(case, args.precision, args.steps, args.warmup)
+    other = "fp64" if args.precision == "fp32" else "fp32"
+    r = run_gpu(case, args.precision, args.steps, args.warmup)
+    ms, S, elem = r["ms"], r["S"], r["elem"]
     cu_s = ncell * args.steps / (ms * 1e-3)
     launches = 3 * args.steps
     avg_launch_s = ms * 1e-3 / launches
@@ -168,8 +217,11 @@ def main():
             "workload": (f"2D expanding ring {args.n}x{args.n} over a 60 mm "
                          "square: copper-like annulus 25-26.5 mm in gas, "
                          "150 m/s r/R, Gaussian phi0 (0.2 mm, 5%)"),
-            "cells": ncell, "state_fields": S, "precision": args.precision,
-            "simulated_time_s": t_sim,
+            "cells": ncell, "state_fields": S,
+            "precision": ("fp32-bulk (FP64 EOS island, FP64 plastic return "
+                          "and damage, exact totals)"
+                          if args.precision == "fp32" else "fp64"),
+            "simulated_time_s": r["t"],
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -180,6 +232,13 @@ def main():
             "avg_launch_ms": avg_launch_s * 1e3,
         },
     }
+    if not args.no_compare:
+        r2 = run_gpu(case, other, args.steps, args.warmup)
+        out[f"{other}_form"] = {
+            "value": ncell * args.steps / (r2["ms"] * 1e-3),
+            "ms_per_step": r2["ms"] / args.steps}
+        r32, r64 = (r, r2) if args.precision == "fp32" else (r2, r)
+        out["precision"] = precision_report(case, r32, r64)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)

@@ -175,6 +175,35 @@ int32_t fv_time(fv_ctx* ctx, double* t_host);
  * rounded sum of the same values.  Synchronises; FV_ENONPHYS if flagged. */
 int32_t fv_totals(fv_ctx* ctx, double* out);
 
+/* One fragment of fv_fragments. */
+typedef struct {
+  int64_t label;            /* smallest linear cell index (x fastest) */
+  int64_t n_cells;
+  double mass;              /* sum of phi_s rho_s over its cells, correctly
+                               rounded, times the cell volume */
+  int32_t touches_boundary; /* 1 if a cell lies on a domain side */
+  int32_t reserved;
+} fv_fragment;
+
+/* Bytes of device workspace fv_fragments needs for instance inst and at
+ * most cap fragments.  Returns 0 for invalid arguments. */
+size_t fv_fragment_workspace_bytes(const fv_ctx* ctx, int32_t inst, int64_t cap);
+
+/* Fragments of instance inst (Sections 4.2 and 4.3 delineate fragments at the
+ * volume-fraction contour): the connected sets of cells whose solid volume
+ * fraction exceeds cut (compared in double), connected through cell faces (2
+ * neighbours in 1D, 4 in 2D; not across periodic sides).
+ * labels: device int32[ncell], caller-owned, out: the fragment label of each
+ * cell (its smallest linear cell index) or -1 for a non-material cell.
+ * frag_ws: device buffer of frag_ws_bytes >= fv_fragment_workspace_bytes.
+ * out: host array of cap entries, filled in label order; *n_frag: the number
+ * of fragments.  Deterministic and bit-exact.  Synchronises.  FV_ENOMEM if
+ * there are more than cap fragments (*n_frag then holds the count and the
+ * labels are complete, out is untouched); FV_EINVAL without a solid, for
+ * more than 2^31 - 1 cells or a non-finite cut. */
+int32_t fv_fragments(fv_ctx* ctx, int32_t inst, double cut, int32_t* labels, void* frag_ws,
+                     size_t frag_ws_bytes, int64_t cap, int64_t* n_frag, fv_fragment* out);
+
 /* Text of the last error of ctx (or of the last failed fv_init when ctx is
  * NULL).  Valid until the next call on ctx. */
 const char* fv_last_error(const fv_ctx* ctx);

@@ -15,7 +15,8 @@ PRECISIONS = {"fp64": FV_FP64, "fp32": FV_FP32_BULK}
 
 EXPORTS = ["fv_state_fields", "fv_workspace_bytes", "fv_init",
            "fv_load_primitive", "fv_reset", "fv_primitive", "fv_cfl_dt",
-           "fv_step", "fv_time", "fv_totals", "fv_last_error", "fv_destroy"]
+           "fv_step", "fv_time", "fv_totals", "fv_fragment_workspace_bytes",
+           "fv_fragments", "fv_last_error", "fv_destroy"]
 
 
 class FvGrid(ctypes.Structure):
@@ -36,6 +37,12 @@ class FvOptions(ctypes.Structure):
                 ("phi_floor", ctypes.c_double), ("weno_eps", ctypes.c_double),
                 ("phi_fp64_cut", ctypes.c_double),
                 ("tile", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32)]
+
+
+class FvFragment(ctypes.Structure):
+    _fields_ = [("label", ctypes.c_int64), ("n_cells", ctypes.c_int64),
+                ("mass", ctypes.c_double), ("touches_boundary", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class FvError(RuntimeError):
@@ -75,6 +82,11 @@ def load(path=LIB_PATH):
     lib.fv_primitive.restype = i32
     lib.fv_cfl_dt.argtypes = [vp, P(dbl)]
     lib.fv_cfl_dt.restype = i32
+    lib.fv_fragment_workspace_bytes.argtypes = [vp, i32, ctypes.c_int64]
+    lib.fv_fragment_workspace_bytes.restype = ctypes.c_size_t
+    lib.fv_fragments.argtypes = [vp, i32, dbl, vp, vp, ctypes.c_size_t,
+                                 ctypes.c_int64, P(ctypes.c_int64), P(FvFragment)]
+    lib.fv_fragments.restype = i32
     lib.fv_step.argtypes = [vp, P(dbl), i32, P(dbl)]
     lib.fv_step.restype = i32
     lib.fv_time.argtypes = [vp, P(dbl)]
@@ -123,3 +135,33 @@ def options_struct(precision="fp64", cfl=0.6, phi_floor=1e-8, weno_eps=1e-6,
     o.weno_eps = weno_eps
     o.phi_fp64_cut = phi_fp64_cut
     return o
+
+
+def state_rows(dim, n_mat, solid):
+    """Row indices of the state (and primitive) fields in the layout that
+    include/fv.h documents: volume fractions, phasic masses, (eps_p, D) of
+    each solid, momentum, energy, stored stretch components, Lagrangian
+    coordinates.  `solid` flags which materials are solids."""
+    k = 0
+    rows = {"phi": list(range(k, k + n_mat))}
+    k += n_mat
+    rows["mass"] = list(range(k, k + n_mat))
+    k += n_mat
+    rows["eps"], rows["dmg"] = [], []
+    for l in range(n_mat):
+        if solid[l]:
+            rows["eps"].append(k)
+            rows["dmg"].append(k + 1)
+            k += 2
+    rows["mom"] = list(range(k, k + dim))
+    k += dim
+    rows["energy"] = k
+    k += 1
+    nv = {1: 3, 2: 5, 3: 9}[dim]
+    rows["vbar"] = list(range(k, k + nv))
+    k += nv
+    rows["X"] = list(range(k, k + dim))
+    k += dim
+    rows["S"] = k
+    return rows
+

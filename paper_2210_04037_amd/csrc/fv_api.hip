@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "fv_kernels.hpp"
+#include "fv_ccl.hpp"
 
 using namespace fv;
 using namespace fvk;
@@ -542,6 +543,122 @@ int32_t fv_totals(fv_ctx* c, double* out) {
       }
       o[NT + k] = bins_to_double(hb);
     }
+  }
+  return FV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// fragments
+// ---------------------------------------------------------------------------
+namespace {
+struct FragPlan {
+  size_t fid, bcount, n_root, flabel, fcount, fflag, fbins, total;
+  int nblk;
+};
+
+FragPlan plan_frag(int64_t ncell, int64_t cap) {
+  FragPlan F{};
+  F.nblk = (int)((ncell + 255) / 256);
+  size_t o = 0;
+  F.fid = o;     o = align256(o + sizeof(int) * (size_t)ncell);
+  F.bcount = o;  o = align256(o + sizeof(int) * (size_t)F.nblk);
+  F.n_root = o;  o = align256(o + sizeof(long long));
+  F.flabel = o;  o = align256(o + sizeof(int) * (size_t)cap);
+  F.fcount = o;  o = align256(o + sizeof(unsigned long long) * (size_t)cap);
+  F.fflag = o;   o = align256(o + sizeof(unsigned int) * (size_t)cap);
+  F.fbins = o;   o = align256(o + sizeof(unsigned long long) * NBINS * (size_t)cap);
+  F.total = o;
+  return F;
+}
+}  // namespace
+
+size_t fv_fragment_workspace_bytes(const fv_ctx* c, int32_t inst, int64_t cap) {
+  if (!c || inst < 0 || inst >= c->n_inst || cap < 0) return 0;
+  return plan_frag(c->insts[inst].ncell, cap).total;
+}
+
+int32_t fv_fragments(fv_ctx* c, int32_t inst, double cut, int32_t* labels, void* frag_ws,
+                     size_t frag_ws_bytes, int64_t cap, int64_t* n_frag, fv_fragment* out) {
+  if (!c) return FV_EINVAL;
+  if (inst < 0 || inst >= c->n_inst) return fail(c, FV_EINVAL, "bad instance");
+  if (!labels || !frag_ws || !n_frag) return fail(c, FV_EINVAL, "null labels, workspace or n_frag");
+  if (cap < 0 || (cap > 0 && !out)) return fail(c, FV_EINVAL, "bad cap or null output array");
+  if (!(cut == cut) || cut - cut != 0.0) return fail(c, FV_EINVAL, "cut must be finite");
+  if (c->ns < 1) return fail(c, FV_EINVAL, "no solid material");
+  const Inst& I = c->insts[inst];
+  if (I.ncell > 0x7FFFFFFF) return fail(c, FV_EINVAL, "more than 2^31 - 1 cells");
+  const FragPlan F = plan_frag(I.ncell, cap);
+  if (frag_ws_bytes < F.total)
+    return fail(c, FV_ENOMEM, "fragment workspace too small: need " + std::to_string(F.total) + " bytes");
+  *n_frag = 0;
+  char* ws = static_cast<char*>(frag_ws);
+  int* fid = reinterpret_cast<int*>(ws + F.fid);
+  int* bcount = reinterpret_cast<int*>(ws + F.bcount);
+  long long* n_root = reinterpret_cast<long long*>(ws + F.n_root);
+  int* flabel = reinterpret_cast<int*>(ws + F.flabel);
+  unsigned long long* fcount = reinterpret_cast<unsigned long long*>(ws + F.fcount);
+  unsigned int* fflag = reinterpret_cast<unsigned int*>(ws + F.fflag);
+  unsigned long long* fbins = reinterpret_cast<unsigned long long*>(ws + F.fbins);
+  const CclGrid g{I.n[0], I.n[1], I.n[2], I.ncell};
+  const dim3 grid((unsigned)F.nblk), blk(256);
+  hipStream_t s = c->stream;
+  // the solid is material 0: its volume fraction is field 0, its phasic
+  // mass field nm
+  if (c->ops.elem == 8)
+    hipLaunchKernelGGL(ccl_init_kernel<double>, grid, blk, 0, s, (const double*)I.U, cut, g, labels);
+  else
+    hipLaunchKernelGGL(ccl_init_kernel<float>, grid, blk, 0, s, (const float*)I.U, cut, g, labels);
+  hipLaunchKernelGGL(ccl_merge_kernel, grid, blk, 0, s, g, labels);
+  hipLaunchKernelGGL(ccl_compress_kernel, grid, blk, 0, s, g, labels);
+  hipLaunchKernelGGL(ccl_count_kernel, grid, blk, 0, s, g, (const int*)labels, bcount);
+  hipLaunchKernelGGL(ccl_scan_kernel, dim3(1), dim3(1024), 0, s, F.nblk, bcount, n_root);
+  int rc = hip_check(c, hipGetLastError(), "labelling kernels");
+  if (rc != FV_OK) return rc;
+  long long nr = 0;
+  rc = hip_check(c, hipMemcpyAsync(&nr, n_root, sizeof(nr), hipMemcpyDeviceToHost, s), "read count");
+  if (rc == FV_OK) rc = hip_check(c, hipStreamSynchronize(s), "labelling sync");
+  if (rc != FV_OK) return rc;
+  *n_frag = nr;
+  if (nr > cap)
+    return fail(c, FV_ENOMEM, std::to_string(nr) + " fragments exceed cap " + std::to_string(cap));
+  if (nr == 0) return FV_OK;
+  hipLaunchKernelGGL(ccl_assign_kernel, grid, blk, 0, s, g, (const int*)labels, (const int*)bcount,
+                     fid, flabel);
+  rc = hip_check(c, hipMemsetAsync(fcount, 0, sizeof(unsigned long long) * nr, s), "zero counts");
+  if (rc == FV_OK) rc = hip_check(c, hipMemsetAsync(fflag, 0, sizeof(unsigned int) * nr, s), "zero flags");
+  if (rc == FV_OK)
+    rc = hip_check(c, hipMemsetAsync(fbins, 0, sizeof(unsigned long long) * NBINS * nr, s), "zero bins");
+  if (rc != FV_OK) return rc;
+  if (c->ops.elem == 8)
+    hipLaunchKernelGGL(ccl_stats_kernel<double>, grid, blk, 0, s, g, (const int*)labels, (const int*)fid,
+                       (const double*)I.U + (int64_t)c->nm * I.ncell, fbins, fcount, fflag);
+  else
+    hipLaunchKernelGGL(ccl_stats_kernel<float>, grid, blk, 0, s, g, (const int*)labels, (const int*)fid,
+                       (const float*)I.U + (int64_t)c->nm * I.ncell, fbins, fcount, fflag);
+  rc = hip_check(c, hipGetLastError(), "fragment statistics kernel");
+  if (rc != FV_OK) return rc;
+  std::vector<int> hl((size_t)nr);
+  std::vector<unsigned long long> hc((size_t)nr), hb((size_t)nr * NBINS);
+  std::vector<unsigned int> hf((size_t)nr);
+  rc = hip_check(c, hipMemcpyAsync(hl.data(), flabel, sizeof(int) * nr, hipMemcpyDeviceToHost, s), "read labels");
+  if (rc == FV_OK)
+    rc = hip_check(c, hipMemcpyAsync(hc.data(), fcount, sizeof(unsigned long long) * nr, hipMemcpyDeviceToHost, s),
+                   "read counts");
+  if (rc == FV_OK)
+    rc = hip_check(c, hipMemcpyAsync(hf.data(), fflag, sizeof(unsigned int) * nr, hipMemcpyDeviceToHost, s),
+                   "read flags");
+  if (rc == FV_OK)
+    rc = hip_check(c, hipMemcpyAsync(hb.data(), fbins, sizeof(unsigned long long) * NBINS * nr,
+                                     hipMemcpyDeviceToHost, s), "read bins");
+  if (rc == FV_OK) rc = hip_check(c, hipStreamSynchronize(s), "fragment sync");
+  if (rc != FV_OK) return rc;
+  const double vol = I.dx[0] * I.dx[1] * I.dx[2];
+  for (long long f = 0; f < nr; ++f) {
+    out[f].label = hl[f];
+    out[f].n_cells = (int64_t)hc[f];
+    out[f].mass = bins_to_double(&hb[(size_t)f * NBINS]) * vol;
+    out[f].touches_boundary = hf[f] ? 1 : 0;
+    out[f].reserved = 0;
   }
   return FV_OK;
 }

@@ -183,9 +183,11 @@ __global__ void __launch_bounds__(256) prim_to_cons_kernel(const Inst* insts, in
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= I.ncell) return;
   double W[L::S], U[L::S];
+#pragma unroll
   for (int f = 0; f < L::S; ++f) W[f] = prim[(int64_t)f * I.ncell + g];
   Cell<DIM, NM, NS>::prim_to_cons(P, W, U);
   T* Us = (T*)I.U;
+#pragma unroll
   for (int f = 0; f < L::S; ++f) Us[(int64_t)f * I.ncell + g] = (T)U[f];
 }
 
@@ -198,8 +200,10 @@ __global__ void __launch_bounds__(256) cons_to_prim_kernel(const Inst* insts, in
   if (g >= I.ncell) return;
   const T* Us = (const T*)I.U;
   double U[L::S], W[L::S];
+#pragma unroll
   for (int f = 0; f < L::S; ++f) U[f] = (double)Us[(int64_t)f * I.ncell + g];
   Cell<DIM, NM, NS>::cons_to_prim(P, U, W);
+#pragma unroll
   for (int f = 0; f < L::S; ++f) prim[(int64_t)f * I.ncell + g] = W[f];
 }
 
@@ -214,6 +218,7 @@ __global__ void __launch_bounds__(256) cfl_kernel(const Inst* insts, int ii, Par
   if (g < I.ncell) {
     const T* Us = (const T*)I.U;
     double U[L::S];
+#pragma unroll
     for (int f = 0; f < L::S; ++f) U[f] = (double)Us[(int64_t)f * I.ncell + g];
     v = St::cfl_sum(P, I, U);
     if (!(v == v)) {

@@ -116,6 +116,30 @@ class GpuSolver:
         self.torch.cuda.synchronize(self.device)
         return self.states[i].double().cpu().numpy()
 
+    def fragments(self, i=0, cut=0.5, cap=None):
+        """Fragment labels (nz, ny, nx) int32 (-1 outside material) and the
+        fragment list [(label, n_cells, mass, touches_boundary)] in label
+        order, from the library's device labelling."""
+        torch = self.torch
+        c = self.cases[i]
+        ncell = int(np.prod(c.n))
+        cap = ncell // 2 + 1 if cap is None else int(cap)
+        nbytes = self.lib.fv_fragment_workspace_bytes(self.ctx, i, cap)
+        if nbytes == 0:
+            raise abi.FvError(abi.FV_EINVAL, "fragment workspace size")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        labels = torch.empty(ncell, dtype=torch.int32, device=self.device)
+        out = (abi.FvFragment * max(cap, 1))()
+        nf = ctypes.c_int64()
+        self._c(self.lib.fv_fragments(
+            self.ctx, i, float(cut), ctypes.c_void_p(labels.data_ptr()),
+            ctypes.c_void_p(ws.data_ptr()), nbytes, cap, ctypes.byref(nf), out))
+        nx, ny, nz = c.n
+        lab = labels.cpu().numpy().reshape(nz, ny, nx)
+        frags = [(int(f.label), int(f.n_cells), float(f.mass),
+                  bool(f.touches_boundary)) for f in out[:nf.value]]
+        return lab, frags
+
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:
             self.lib.fv_destroy(self.ctx)

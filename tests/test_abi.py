@@ -70,3 +70,23 @@ def test_init_rejects_invalid_arguments():
                      ptrs, ctypes.c_void_p(0x1000), 1 << 30, None)
     assert rc == abi.FV_EINVAL
     lib.fv_destroy(None)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_state_rows_match_library_and_oracle_layout(cfg):
+    """The binding's field map agrees with the library's field count and
+    with the oracle's layout (written independently from the same order)."""
+    from oracle.layout import Layout
+    lib = _lib()
+    c = F.make_case(cfg, n=16)
+    rows = abi.state_rows(c.dim, len(c.mats),
+                          [m["kind"] == "solid" for m in c.mats])
+    assert rows["S"] == lib.fv_state_fields(c.dim, len(c.mats),
+                                            abi.material_array(c.mats))
+    L = Layout(c.dim, c.mats)
+    assert rows["S"] == L.S
+    assert rows["phi"] == L.phi and rows["mass"] == L.mass
+    assert rows["eps"] == [L.eps[l] for l in L.solids]
+    assert rows["dmg"] == [L.dmg[l] for l in L.solids]
+    assert rows["mom"] == L.mom and rows["energy"] == L.energy
+    assert rows["vbar"] == L.vbar and rows["X"] == L.X

@@ -1,0 +1,140 @@
+"""Device fragment labelling (through the C ABI) against the oracle's flood
+fill on the same state: labels, cell counts, masses and boundary flags are
+compared bit for bit (integer work, and masses that are correctly rounded
+sums on both sides).  The oracle reads the state the device labelled, so
+both take the material decision phi_s > cut on the same values in double."""
+import numpy as np
+import pytest
+
+import fvinputs as F
+from oracle import fragments as Fr
+
+pytestmark = pytest.mark.gpu
+
+
+def _masked_case(mask, seed, dim=2, at_cut_frac=0.01):
+    """Copper/gas state with the solid present (phi_s = 0.999) where mask is
+    set and absent (1e-8) elsewhere; a few cells sit exactly at the cut."""
+    nz, ny, nx = mask.shape
+    rng = np.random.default_rng(seed)
+    c = F.uniform_case(dim, (nx, ny, nz), [F.COPPER, F.GAS], [0.5, 0.5],
+                       [8930.0, 1.0], [0.0] * dim, 1e5, bc="transmissive")
+    phi = np.where(mask, 0.999, 1e-8)
+    at_cut = rng.random(mask.shape) < at_cut_frac
+    phi = np.where(at_cut, 0.5, phi)
+    c.prim[0] = phi
+    c.prim[1] = 1.0 - phi
+    c.prim[2] = 8930.0 * (1.0 + 0.01 * rng.standard_normal(mask.shape))
+    return c
+
+
+def _compare(g, case, i=0, cut=0.5):
+    lab, frags = g.fragments(i, cut)
+    U = g.state(i)
+    ref_lab = Fr.label(U[0], cut)
+    vol = float(np.prod([(case.hi[k] - case.lo[k]) / case.n[k]
+                         for k in range(3)]))
+    ref = Fr.fragments(U[0], U[len(case.mats)], vol, cut)
+    assert np.array_equal(lab.astype(np.int64), ref_lab)
+    assert len(frags) == len(ref)
+    for a, b in zip(frags, ref):
+        assert a[0] == b[0] and a[1] == b[1] and a[3] == b[3], (a, b)
+        assert a[2] == b[2], (a, b)        # bit-exact mass
+    return frags
+
+
+def _blobs(shape, seed, frac):
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal(shape)
+    k = [np.fft.fftfreq(n) for n in shape]
+    K = np.meshgrid(*k, indexing="ij")
+    filt = np.exp(-sum(kk ** 2 for kk in K) * 60.0)
+    s = np.real(np.fft.ifftn(np.fft.fftn(f) * filt))
+    return s > np.quantile(s, 1.0 - frac)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape,kind", [
+    ((1, 131, 257), "blobs"), ((1, 64, 64), "checker"),
+    ((1, 97, 61), "serpentine"), ((1, 40, 33), "full"),
+    ((1, 40, 33), "empty"), ((1, 1, 300), "blobs")])
+def test_fragments_match_oracle(shape, kind, precision):
+    from paper_2210_04037_amd.solver import GpuSolver
+    nz, ny, nx = shape
+    if kind == "blobs":
+        mask = _blobs(shape, 11, 0.45)
+    elif kind == "checker":
+        z, y, x = np.indices(shape)
+        mask = (x + y) % 2 == 0
+    elif kind == "serpentine":
+        z, y, x = np.indices(shape)
+        mask = (y % 2 == 0) | (x == np.where((y // 2) % 2 == 1, 0, nx - 1))
+    elif kind == "full":
+        mask = np.ones(shape, bool)
+    else:
+        mask = np.zeros(shape, bool)
+    dim = 1 if ny == 1 else 2
+    case = _masked_case(mask, 5, dim,
+                        at_cut_frac=0.0 if kind == "serpentine" else 0.01)
+    print(f"[fragments] {kind} {shape} {precision}", flush=True)
+    g = GpuSolver(case, precision=precision)
+    frags = _compare(g, case)
+    if kind == "checker":                 # every material cell is isolated
+        assert all(f[1] == 1 for f in frags)
+        assert len(frags) == int((g.state(0)[0] > 0.5).sum())
+    if kind == "serpentine":
+        assert len(frags) == 1
+    if kind == "empty":
+        assert frags == []
+    g.close()
+
+
+def test_fragment_cap_reports_count():
+    from paper_2210_04037_amd import abi
+    from paper_2210_04037_amd.solver import GpuSolver
+    shape = (1, 32, 32)
+    z, y, x = np.indices(shape)
+    case = _masked_case((x + y) % 2 == 0, 3)
+    g = GpuSolver(case)
+    lab_full, frags = g.fragments(0, 0.5)
+    with pytest.raises(abi.FvError) as e:
+        g.fragments(0, 0.5, cap=len(frags) - 1)
+    assert e.value.code == abi.FV_ENOMEM
+    assert str(len(frags)) in str(e.value)
+    g.close()
+
+
+def test_fragments_after_spall():
+    """The 1D plate impact after the spall plane has opened: the GPU labels
+    of its own evolved state equal the oracle's."""
+    from paper_2210_04037_amd.solver import GpuSolver
+    case = F.make_case(1, n=100)
+    g = GpuSolver(case)
+    g.step(400)
+    frags = _compare(g, case)
+    print(f"[fragments] spall: {len(frags)} fragments", frags, flush=True)
+    assert len(frags) >= 1
+    g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fragments_ring_state(precision):
+    from paper_2210_04037_amd.solver import GpuSolver
+    case = F.make_case(2, n=256)
+    g = GpuSolver(case, precision=precision)
+    g.step(60)
+    frags = _compare(g, case)
+    print(f"[fragments] ring 256^2 {precision}: {len(frags)} fragments, "
+          f"largest {max(f[1] for f in frags)} cells", flush=True)
+    g.close()
+
+
+def test_fragments_full_size_ring():
+    """1024^2: labels and statistics of the initial ring state (one large
+    annulus) against the oracle's flood fill."""
+    from paper_2210_04037_amd.solver import GpuSolver
+    case = F.make_case(2)
+    g = GpuSolver(case, precision="fp32")
+    frags = _compare(g, case)
+    assert max(f[1] for f in frags) > 10000
+    g.close()
