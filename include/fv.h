@@ -91,7 +91,12 @@ typedef struct {
  * volume fractions are clamped to [phi_floor, 1] (absent materials).
  * weno_eps: WENO3 smoothness floor relative to the squared domain extent.
  * phi_fp64_cut: FP32-bulk only, cells with a volume fraction below it invert
- * the mixture EOS in double.  tile: 0 selects the default tile. */
+ * the mixture EOS in double.  tile: cells per workgroup tile in x and y
+ * (tile[2] unused); {0, 0} selects the default shape, any other value must
+ * be one of the compiled shapes (fv_autotune lists them) or fv_init fails
+ * with FV_EINVAL.  Results do not depend on the tile shape.  use_graph:
+ * nonzero makes fv_step capture its n_steps steps into a HIP graph at the
+ * first call with that step count and replay it afterwards. */
 typedef struct {
   int32_t precision;
   double cfl;
@@ -99,7 +104,7 @@ typedef struct {
   double weno_eps;
   double phi_fp64_cut;
   int32_t tile[3];
-  int32_t reserved;
+  int32_t use_graph;
 } fv_options;
 
 /* Number of state fields S for a dimension and material list (the first
@@ -174,6 +179,18 @@ int32_t fv_time(fv_ctx* ctx, double* t_host);
  * final rounding (an integer superaccumulator), so it equals the correctly
  * rounded sum of the same values.  Synchronises; FV_ENONPHYS if flagged. */
 int32_t fv_totals(fv_ctx* ctx, double* out);
+
+/* Autotuner: time every compiled tile shape of ctx's kernel set on reps
+ * timing runs of the first RK stage over the current state (these leave the
+ * state, time, dt and boundary accumulators unchanged; they overwrite only
+ * the stage buffer in the workspace), keep the fastest shape for later steps
+ * and report.  tiles: host int32[2 * max_report] out, (x, y) per shape; ms:
+ * host float[max_report] out, average launch time per shape; *n_variants:
+ * number of compiled shapes; *chosen: index of the selected one (either may
+ * be NULL).  Synchronises; drops captured step graphs.  Results of later
+ * steps are bitwise those of any other shape. */
+int32_t fv_autotune(fv_ctx* ctx, int32_t reps, int32_t max_report, int32_t* tiles, float* ms,
+                    int32_t* n_variants, int32_t* chosen);
 
 /* One fragment of fv_fragments. */
 typedef struct {

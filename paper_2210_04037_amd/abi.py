@@ -15,7 +15,8 @@ PRECISIONS = {"fp64": FV_FP64, "fp32": FV_FP32_BULK}
 
 EXPORTS = ["fv_state_fields", "fv_workspace_bytes", "fv_init",
            "fv_load_primitive", "fv_reset", "fv_primitive", "fv_cfl_dt",
-           "fv_step", "fv_time", "fv_totals", "fv_fragment_workspace_bytes",
+           "fv_step", "fv_time", "fv_totals", "fv_autotune",
+           "fv_fragment_workspace_bytes",
            "fv_fragments", "fv_last_error", "fv_destroy"]
 
 
@@ -36,7 +37,7 @@ class FvOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("cfl", ctypes.c_double),
                 ("phi_floor", ctypes.c_double), ("weno_eps", ctypes.c_double),
                 ("phi_fp64_cut", ctypes.c_double),
-                ("tile", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32)]
+                ("tile", ctypes.c_int32 * 3), ("use_graph", ctypes.c_int32)]
 
 
 class FvFragment(ctypes.Structure):
@@ -82,6 +83,8 @@ def load(path=LIB_PATH):
     lib.fv_primitive.restype = i32
     lib.fv_cfl_dt.argtypes = [vp, P(dbl)]
     lib.fv_cfl_dt.restype = i32
+    lib.fv_autotune.argtypes = [vp, i32, i32, P(i32), P(ctypes.c_float), P(i32), P(i32)]
+    lib.fv_autotune.restype = i32
     lib.fv_fragment_workspace_bytes.argtypes = [vp, i32, ctypes.c_int64]
     lib.fv_fragment_workspace_bytes.restype = ctypes.c_size_t
     lib.fv_fragments.argtypes = [vp, i32, dbl, vp, vp, ctypes.c_size_t,
@@ -127,13 +130,16 @@ def material_array(mats):
 
 
 def options_struct(precision="fp64", cfl=0.6, phi_floor=1e-8, weno_eps=1e-6,
-                   phi_fp64_cut=1e-6):
+                   phi_fp64_cut=1e-6, tile=None, use_graph=False):
     o = FvOptions()
     o.precision = PRECISIONS[precision]
     o.cfl = cfl
     o.phi_floor = phi_floor
     o.weno_eps = weno_eps
     o.phi_fp64_cut = phi_fp64_cut
+    if tile is not None:
+        o.tile[0], o.tile[1] = int(tile[0]), int(tile[1])
+    o.use_graph = 1 if use_graph else 0
     return o
 
 

@@ -27,24 +27,32 @@ def hipcc():
 # approximate transcendental functions, the FP64 form keeps IEEE arithmetic
 UNITS = [
     ("fv_api.hip", []),
+    ("fv_fp64.hip", []),
     ("fv_fp32.hip", ["-fno-hip-fp32-correctly-rounded-divide-sqrt",
                      "-freciprocal-math", "-fapprox-func", "-fno-math-errno"]),
 ]
 
 
 def build(verbose=False, extra=()):
-    objs = []
+    """Compile the units in parallel, link libfv.so."""
+    objs, procs = [], []
     for src, flags in UNITS:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
         cmd = ([hipcc()] + FLAGS + flags + list(extra)
                + ["-c", "-o", obj, os.path.join(CSRC, src)])
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            sys.stderr.write(r.stdout + r.stderr)
-            raise RuntimeError(f"hipcc failed on {src}")
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                            stderr=subprocess.STDOUT, text=True)))
         objs.append(obj)
+    failed = []
+    for src, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(out)
+            failed.append(src)
+    if failed:
+        raise RuntimeError(f"hipcc failed on {', '.join(failed)}")
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -18,10 +18,6 @@
 using namespace fv;
 using namespace fvk;
 
-namespace fvk {
-// FP32-bulk launchers, defined in fv_fp32.hip
-bool select_ops_fp32(int dim, int nm, int ns, Ops& o, hipError_t& herr, bool set_attr);
-}
 
 namespace {
 // Correctly rounded (ties to even) value of sum_k bins[k] 2^(32k) 2^-1074.
@@ -90,17 +86,21 @@ static int hip_check(fv_ctx* c, hipError_t e, const char* what) {
 }
 
 
-// set_attr: also raise the kernel's dynamic LDS limit (a HIP runtime call;
-// size-only queries skip it so that they run without a device)
-static bool select_ops(int dim, int nm, int ns, int prec, Ops& o, hipError_t& herr,
-                       bool set_attr = true) {
-  herr = hipSuccess;
-  if (prec == FV_FP32_BULK) return select_ops_fp32(dim, nm, ns, o, herr, set_attr);
-  FV_SEL(1, 1, 1, double, double, 256, 1)
-  FV_SEL(1, 2, 1, double, double, 256, 1)
-  FV_SEL(2, 1, 1, double, double, 32, 8)
-  FV_SEL(2, 2, 1, double, double, 32, 8)
-  return false;
+// Every compiled tile shape of the kernel set for this combination, the
+// default first.  set_attr: also raise each kernel's dynamic LDS limit (a HIP
+// runtime call; size-only queries skip it so that they run without a device)
+static bool select_ops(int dim, int nm, int ns, int prec, std::vector<Ops>& vars,
+                       hipError_t& herr, bool set_attr = true) {
+  if (prec == FV_FP32_BULK) return select_ops_fp32(dim, nm, ns, vars, herr, set_attr);
+  return select_ops_fp64(dim, nm, ns, vars, herr, set_attr);
+}
+
+// index of the tile shape asked for in the options (0, 0: the default)
+static int pick_variant(const std::vector<Ops>& vars, const fv_options* opt) {
+  if (opt->tile[0] == 0 && opt->tile[1] == 0) return 0;
+  for (size_t v = 0; v < vars.size(); ++v)
+    if (vars[v].TX == opt->tile[0] && vars[v].TY == opt->tile[1]) return (int)v;
+  return -1;
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -150,17 +150,27 @@ static int validate(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
 
 struct WsPlan {
   std::vector<size_t> u1, u2, bacc, dts;
-  std::vector<int> ntrans[6];
   size_t insts = 0, block_inst = 0, bins = 0, total = 0;
-  int total_blocks = 0;
-  std::vector<int> tiles[3], block_begin;
+  int max_blocks = 0;
 };
 
-static void plan_ws(int32_t n_inst, const fv_grid* grids, const Ops& o, WsPlan& W) {
+static int tiles_of(const fv_grid& g, const Ops& o, int& tx, int& ty) {
+  tx = (g.n[0] + o.TX - 1) / o.TX;
+  ty = g.dim >= 2 ? (g.n[1] + o.TY - 1) / o.TY : 1;
+  return tx * ty;
+}
+
+// Workspace layout; the block table holds the block count of the tile shape
+// with the most blocks, so that any compiled shape can be selected later.
+static void plan_ws(int32_t n_inst, const fv_grid* grids, const std::vector<Ops>& vars,
+                    WsPlan& W) {
+  const Ops& o = vars[0];
   size_t off = 0;
-  W.total_blocks = 0;
-  for (int k = 0; k < 3; ++k) W.tiles[k].resize(n_inst);
-  W.block_begin.resize(n_inst);
+  for (const Ops& v : vars) {
+    int nb = 0, tx, ty;
+    for (int i = 0; i < n_inst; ++i) nb += tiles_of(grids[i], v, tx, ty);
+    W.max_blocks = std::max(W.max_blocks, nb);
+  }
   for (int i = 0; i < n_inst; ++i) {
     const fv_grid& g = grids[i];
     const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
@@ -174,14 +184,9 @@ static void plan_ws(int32_t n_inst, const fv_grid* grids, const Ops& o, WsPlan& 
     }
     W.bacc.push_back(off); off += align256(nb * sizeof(double));
     W.dts.push_back(off); off += align256(DTS_SIZE * sizeof(double));
-    const int tx = (g.n[0] + o.TX - 1) / o.TX;
-    const int ty = g.dim >= 2 ? (g.n[1] + o.TY - 1) / o.TY : 1;
-    W.tiles[0][i] = tx; W.tiles[1][i] = ty; W.tiles[2][i] = 1;
-    W.block_begin[i] = W.total_blocks;
-    W.total_blocks += tx * ty;
   }
   W.insts = off; off += align256(sizeof(Inst) * n_inst);
-  W.block_inst = off; off += align256(sizeof(int) * W.total_blocks);
+  W.block_inst = off; off += align256(sizeof(int) * W.max_blocks);
   W.bins = off; off += align256(sizeof(unsigned long long) * NBINS * (size_t)n_inst * 2 * o.NTOT * 3);
   W.total = off;
 }
@@ -219,6 +224,49 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
   P.phi_fp64_cut = opt->phi_fp64_cut;
 }
 
+// Select tile shape v: per-instance tile counts, the block -> instance table,
+// and their device copies (synchronises the stream).  Captured step graphs
+// hold the old launch shape and are dropped.
+static void drop_graphs(fv_ctx* c) {
+  for (auto& g : c->gexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  c->graph_steps = 0;
+}
+
+static int set_tiles(fv_ctx* c, int v) {
+  const Ops& o = c->vars[v];
+  int total = 0;
+  c->h_block_inst.clear();
+  for (int i = 0; i < c->n_inst; ++i) {
+    Inst& I = c->insts[i];
+    fv_grid g{};
+    g.dim = c->dim;
+    for (int k = 0; k < 3; ++k) g.n[k] = I.n[k];
+    int tx, ty;
+    tiles_of(g, o, tx, ty);
+    I.tiles[0] = tx; I.tiles[1] = ty; I.tiles[2] = 1;
+    I.block_begin = total;
+    I.nblocks = tx * ty;
+    total += I.nblocks;
+    for (int b = 0; b < I.nblocks; ++b) c->h_block_inst.push_back(i);
+  }
+  if (total > c->max_blocks) return fail(c, FV_EINVAL, "block table overflow");
+  drop_graphs(c);
+  c->var = v;
+  c->ops = o;
+  c->total_blocks = total;
+  int rc = hip_check(c, hipMemcpyAsync(c->insts_d, c->insts.data(), sizeof(Inst) * c->n_inst,
+                                       hipMemcpyHostToDevice, c->stream), "copy instance table");
+  if (rc == FV_OK)
+    rc = hip_check(c, hipMemcpyAsync(c->block_inst_d, c->h_block_inst.data(), sizeof(int) * total,
+                                     hipMemcpyHostToDevice, c->stream), "copy block table");
+  if (rc == FV_OK) rc = hip_check(c, hipStreamSynchronize(c->stream), "tile table sync");
+  return rc;
+}
+
 extern "C" {
 
 int32_t fv_state_fields(int32_t dim, int32_t n_mat, const fv_material* mats) {
@@ -234,11 +282,12 @@ size_t fv_workspace_bytes(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
   int ns = 0;
   std::string msg;
   if (validate(n_inst, grids, n_mat, mats, opt, ns, msg) != FV_OK) return 0;
-  Ops o;
+  std::vector<Ops> vars;
   hipError_t he;
-  if (!select_ops(grids[0].dim, n_mat, ns, opt->precision, o, he, false)) return 0;
+  if (!select_ops(grids[0].dim, n_mat, ns, opt->precision, vars, he, false)) return 0;
+  if (pick_variant(vars, opt) < 0) return 0;
   WsPlan W;
-  plan_ws(n_inst, grids, o, W);
+  plan_ws(n_inst, grids, vars, W);
   return W.total;
 }
 
@@ -263,10 +312,18 @@ int32_t fv_init(fv_ctx** out, int32_t n_inst, const fv_grid* grids, int32_t n_ma
   c->precision = opt->precision;
   c->stream = (hipStream_t)stream;
   hipError_t he;
-  if (!select_ops(c->dim, n_mat, ns, opt->precision, c->ops, he)) {
+  if (!select_ops(c->dim, n_mat, ns, opt->precision, c->vars, he)) {
     delete c;
     return fail(nullptr, FV_EINVAL, "unsupported dimension/material/precision combination");
   }
+  c->var = pick_variant(c->vars, opt);
+  if (c->var < 0) {
+    delete c;
+    return fail(nullptr, FV_EINVAL, "tile shape " + std::to_string(opt->tile[0]) + "x" +
+                                         std::to_string(opt->tile[1]) + " is not compiled");
+  }
+  c->ops = c->vars[c->var];
+  c->use_graph = opt->use_graph != 0;
   if (he != hipSuccess) {
     std::string m = std::string("hipFuncSetAttribute: ") + hipGetErrorString(he);
     delete c;
@@ -274,14 +331,13 @@ int32_t fv_init(fv_ctx** out, int32_t n_inst, const fv_grid* grids, int32_t n_ma
   }
   fill_params(mats, n_mat, opt, c->P);
   WsPlan W;
-  plan_ws(n_inst, grids, c->ops, W);
+  plan_ws(n_inst, grids, c->vars, W);
   if (workspace_bytes < W.total) {
     delete c;
     return fail(nullptr, FV_ENOMEM, "workspace too small: need " + std::to_string(W.total) + " bytes");
   }
   char* ws = (char*)workspace;
   c->insts.resize(n_inst);
-  std::vector<int> block_inst(W.total_blocks);
   for (int i = 0; i < n_inst; ++i) {
     const fv_grid& g = grids[i];
     Inst& I = c->insts[i];
@@ -300,27 +356,18 @@ int32_t fv_init(fv_ctx** out, int32_t n_inst, const fv_grid* grids, int32_t n_ma
       I.bc[k][1] = g.bc[k][1];
     }
     I.ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
-    I.tiles[0] = W.tiles[0][i]; I.tiles[1] = W.tiles[1][i]; I.tiles[2] = 1;
-    I.block_begin = W.block_begin[i];
-    I.nblocks = I.tiles[0] * I.tiles[1];
     int off = 0;
     for (int a = 0; a < 3; ++a) {
       const int nt = a < g.dim ? (a == 0 ? g.n[1] * g.n[2] : g.n[0] * g.n[2]) : 0;
       I.bacc_off[2 * a] = off; off += nt * c->ops.NC;
       I.bacc_off[2 * a + 1] = off; off += nt * c->ops.NC;
     }
-    for (int b = 0; b < I.nblocks; ++b) block_inst[I.block_begin + b] = i;
   }
   c->insts_d = (Inst*)(ws + W.insts);
   c->block_inst_d = (int*)(ws + W.block_inst);
   c->bins_d = (unsigned long long*)(ws + W.bins);
-  c->total_blocks = W.total_blocks;
-  rc = hip_check(c, hipMemcpyAsync(c->insts_d, c->insts.data(), sizeof(Inst) * n_inst,
-                                   hipMemcpyHostToDevice, c->stream), "copy instance table");
-  if (rc == FV_OK)
-    rc = hip_check(c, hipMemcpyAsync(c->block_inst_d, block_inst.data(), sizeof(int) * W.total_blocks,
-                                     hipMemcpyHostToDevice, c->stream), "copy block table");
-  if (rc == FV_OK) rc = hip_check(c, hipStreamSynchronize(c->stream), "init sync");
+  c->max_blocks = W.max_blocks;
+  rc = set_tiles(c, c->var);
   if (rc != FV_OK) {
     g_init_error = c->err;
     delete c;
@@ -447,12 +494,94 @@ int32_t fv_step(fv_ctx* c, const double* dt_host, int32_t n_steps, const double*
     rc = hip_check(c, hipStreamSynchronize(c->stream), "sync after parameter write");
     if (rc != FV_OK) return rc;
   }
-  for (int s = 0; s < n_steps; ++s) {
-    const int parity = (int)((c->step + s) & 1);
-    for (int st = 1; st <= 3; ++st) c->ops.stage(c, st, parity);
+  if (n_steps == 0) return FV_OK;
+  const int p0 = (int)(c->step & 1);
+  if (!c->use_graph) {
+    for (int s = 0; s < n_steps; ++s) {
+      const int parity = (p0 + s) & 1;
+      for (int st = 1; st <= 3; ++st) c->ops.stage(c, st, parity, c->stream);
+    }
+    c->step += n_steps;
+    return hip_check(c, hipGetLastError(), "stage kernel launch");
+  }
+  // n_steps steps as one graph, captured on a private stream at the first
+  // call with this step count and starting parity, then replayed on the
+  // context's stream (launch arguments are fixed; dt, time and the CFL state
+  // live on the device)
+  if (c->graph_steps != n_steps) drop_graphs(c);
+  if (!c->gexec[p0]) {
+    int rc = FV_OK;
+    if (!c->cap_stream)
+      rc = hip_check(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking),
+                     "capture stream");
+    if (rc != FV_OK) return rc;
+    rc = hip_check(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed),
+                   "begin capture");
+    if (rc != FV_OK) return rc;
+    for (int s = 0; s < n_steps; ++s) {
+      const int parity = (p0 + s) & 1;
+      for (int st = 1; st <= 3; ++st) c->ops.stage(c, st, parity, c->cap_stream);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t le = hipGetLastError();
+    const hipError_t ee = hipStreamEndCapture(c->cap_stream, &graph);
+    rc = hip_check(c, le != hipSuccess ? le : ee, "capture step graph");
+    if (rc == FV_OK)
+      rc = hip_check(c, hipGraphInstantiate(&c->gexec[p0], graph, nullptr, nullptr, 0),
+                     "instantiate step graph");
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc != FV_OK) {
+      c->gexec[p0] = nullptr;
+      return rc;
+    }
+    c->graph_steps = n_steps;
   }
   c->step += n_steps;
-  return hip_check(c, hipGetLastError(), "stage kernel launch");
+  return hip_check(c, hipGraphLaunch(c->gexec[p0], c->stream), "step graph launch");
+}
+
+int32_t fv_autotune(fv_ctx* c, int32_t reps, int32_t max_report, int32_t* tiles, float* ms,
+                    int32_t* n_variants, int32_t* chosen) {
+  if (!c) return FV_EINVAL;
+  if (reps < 1 || max_report < 0 || (max_report > 0 && (!tiles || !ms)))
+    return fail(c, FV_EINVAL, "reps < 1 or null report arrays");
+  const int nv = (int)c->vars.size();
+  if (n_variants) *n_variants = nv;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = hip_check(c, hipEventCreate(&e0), "event");
+  if (rc == FV_OK) rc = hip_check(c, hipEventCreate(&e1), "event");
+  int best = c->var;
+  float best_ms = 0.0f;
+  const int parity = (int)(c->step & 1);
+  for (int v = 0; v < nv && rc == FV_OK; ++v) {
+    rc = set_tiles(c, v);
+    if (rc != FV_OK) break;
+    c->ops.stage(c, 0, parity, c->stream);  // warm-up (code object load)
+    rc = hip_check(c, hipEventRecord(e0, c->stream), "event record");
+    for (int r = 0; r < reps && rc == FV_OK; ++r) c->ops.stage(c, 0, parity, c->stream);
+    if (rc == FV_OK) rc = hip_check(c, hipGetLastError(), "timing launch");
+    if (rc == FV_OK) rc = hip_check(c, hipEventRecord(e1, c->stream), "event record");
+    if (rc == FV_OK) rc = hip_check(c, hipEventSynchronize(e1), "event sync");
+    float t = 0.0f;
+    if (rc == FV_OK) rc = hip_check(c, hipEventElapsedTime(&t, e0, e1), "event time");
+    if (rc != FV_OK) break;
+    t /= (float)reps;
+    if (v < max_report) {
+      tiles[2 * v] = c->vars[v].TX;
+      tiles[2 * v + 1] = c->vars[v].TY;
+      ms[v] = t;
+    }
+    if (v == 0 || t < best_ms) {
+      best_ms = t;
+      best = v;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  const int rc2 = set_tiles(c, rc == FV_OK ? best : c->var);
+  if (rc != FV_OK) return rc;
+  if (chosen) *chosen = best;
+  return rc2;
 }
 
 int32_t fv_totals(fv_ctx* c, double* out) {
@@ -670,6 +799,8 @@ const char* fv_last_error(const fv_ctx* c) {
 void fv_destroy(fv_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 

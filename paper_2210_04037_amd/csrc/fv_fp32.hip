@@ -2,17 +2,43 @@
 // double-precision islands of fv_stage.hpp (trace-fraction pressure
 // inversion, plastic return, totals).  This translation unit is compiled
 // with fast reciprocals and approximate transcendental functions; the FP64
-// form (fv_api.hip) keeps IEEE division and library functions.
+// form (fv_fp64.hip) keeps IEEE division and library functions.
 #include "fv_kernels.hpp"
 
 namespace fvk {
 
-bool select_ops_fp32(int dim, int nm, int ns, Ops& o, hipError_t& herr, bool set_attr) {
+bool select_ops_fp32(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t& herr,
+                     bool set_attr) {
   herr = hipSuccess;
-  FV_SEL(1, 1, 1, float, float, 256, 1)
-  FV_SEL(1, 2, 1, float, float, 256, 1)
-  FV_SEL(2, 1, 1, float, float, 32, 16)
-  FV_SEL(2, 2, 1, float, float, 32, 16)
+  vars.clear();
+  if (dim == 1 && nm == 1 && ns == 1) {
+    FV_VAR(1, 1, 1, float, float, 256, 1)
+    FV_VAR(1, 1, 1, float, float, 128, 1)
+    FV_VAR(1, 1, 1, float, float, 64, 1)
+    return true;
+  }
+  if (dim == 1 && nm == 2 && ns == 1) {
+    FV_VAR(1, 2, 1, float, float, 256, 1)
+    FV_VAR(1, 2, 1, float, float, 128, 1)
+    FV_VAR(1, 2, 1, float, float, 64, 1)
+    return true;
+  }
+  if (dim == 2 && nm == 1 && ns == 1) {
+    FV_VAR(2, 1, 1, float, float, 32, 16)
+    FV_VAR(2, 1, 1, float, float, 32, 8)
+    FV_VAR(2, 1, 1, float, float, 64, 8)
+    FV_VAR(2, 1, 1, float, float, 16, 16)
+    FV_VAR(2, 1, 1, float, float, 64, 4)
+    return true;
+  }
+  if (dim == 2 && nm == 2 && ns == 1) {
+    FV_VAR(2, 2, 1, float, float, 32, 16)
+    FV_VAR(2, 2, 1, float, float, 32, 8)
+    FV_VAR(2, 2, 1, float, float, 64, 8)
+    FV_VAR(2, 2, 1, float, float, 16, 16)
+    FV_VAR(2, 2, 1, float, float, 64, 4)
+    return true;
+  }
   return false;
 }
 

@@ -1,0 +1,43 @@
+// The plain FP64 form of the stage kernels (state and arithmetic in double,
+// IEEE division and library functions): the reference form the oracle
+// checks and the FP32-bulk form is measured against.
+#include "fv_kernels.hpp"
+
+namespace fvk {
+
+bool select_ops_fp64(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t& herr,
+                     bool set_attr) {
+  herr = hipSuccess;
+  vars.clear();
+  if (dim == 1 && nm == 1 && ns == 1) {
+    FV_VAR(1, 1, 1, double, double, 256, 1)
+    FV_VAR(1, 1, 1, double, double, 128, 1)
+    FV_VAR(1, 1, 1, double, double, 64, 1)
+    return true;
+  }
+  if (dim == 1 && nm == 2 && ns == 1) {
+    FV_VAR(1, 2, 1, double, double, 256, 1)
+    FV_VAR(1, 2, 1, double, double, 128, 1)
+    FV_VAR(1, 2, 1, double, double, 64, 1)
+    return true;
+  }
+  if (dim == 2 && nm == 1 && ns == 1) {
+    FV_VAR(2, 1, 1, double, double, 32, 8)
+    FV_VAR(2, 1, 1, double, double, 32, 4)
+    FV_VAR(2, 1, 1, double, double, 16, 8)
+    FV_VAR(2, 1, 1, double, double, 64, 4)
+    FV_VAR(2, 1, 1, double, double, 16, 16)
+    return true;
+  }
+  if (dim == 2 && nm == 2 && ns == 1) {
+    FV_VAR(2, 2, 1, double, double, 32, 8)
+    FV_VAR(2, 2, 1, double, double, 32, 4)
+    FV_VAR(2, 2, 1, double, double, 16, 8)
+    FV_VAR(2, 2, 1, double, double, 64, 4)
+    FV_VAR(2, 2, 1, double, double, 16, 16)
+    return true;
+  }
+  return false;
+}
+
+}  // namespace fvk

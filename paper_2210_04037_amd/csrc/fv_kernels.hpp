@@ -118,14 +118,18 @@ stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int 
   dt = fmin(dt, dts[DTS_TEND] - t);
   const int lb = b - I.block_begin;
   const int tid = threadIdx.x;
+  // stage 0: a timing run of stage 1 that leaves the time, the dt state and
+  // the boundary accumulators alone (its output goes to the stage-1 buffer)
+  const bool dry = stage == 0;
+  if (dry) stage = 1;
   if (!(dt > 0.0)) {
-    if (stage == 1 && lb == 0 && tid == 0) {
+    if (stage == 1 && !dry && lb == 0 && tid == 0) {
       dts[DTS_T + 1 - q] = t;
       dts[DTS_DTINV + 1 - q] = dtinv;
     }
     return;
   }
-  if (stage == 1 && lb == 0 && tid == 0) {
+  if (stage == 1 && !dry && lb == 0 && tid == 0) {
     dts[DTS_T + 1 - q] = t + dt;
     dts[DTS_DTINV + 1 - q] = 0.0;
   }
@@ -133,6 +137,7 @@ stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int 
   cx.I = &I;
   cx.P = P;
   cx.stage = stage;
+  cx.dry = dry;
   cx.parity = q;
   cx.bx = lb % I.tiles[0];
   cx.by = lb / I.tiles[0];
@@ -236,7 +241,7 @@ __global__ void __launch_bounds__(256) cfl_kernel(const Inst* insts, int ii, Par
 struct Ops {
   int S = 0, NC = 0, NTOT = 0, TX = 0, TY = 0, NT = 0;
   size_t smem = 0;
-  void (*stage)(fv_ctx*, int, int) = nullptr;
+  void (*stage)(fv_ctx*, int, int, hipStream_t) = nullptr;
   void (*p2c)(fv_ctx*, int, const double*) = nullptr;
   void (*c2p)(fv_ctx*, int, double*) = nullptr;
   void (*cfl)(fv_ctx*, int, int) = nullptr;
@@ -256,7 +261,16 @@ struct fv_ctx {
   unsigned long long* bins_d = nullptr;
   int total_blocks = 0;
   long long step = 0;
-  fvk::Ops ops;
+  fvk::Ops ops;                       // the selected tile shape
+  std::vector<fvk::Ops> vars;         // every compiled tile shape
+  int var = 0;
+  int max_blocks = 0;                 // capacity of the block table
+  std::vector<int> h_block_inst;
+  // multi-step graphs: one per starting step parity, for graph_steps steps
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int graph_steps = 0;
   std::vector<double> h_dt, h_tend;   // staging for async copies
   std::string err;
 };
@@ -276,9 +290,9 @@ Ops make_ops() {
   o.NT = TX * TY;
   o.elem = sizeof(T);
   o.smem = St::smem_bytes();
-  o.stage = [](fv_ctx* c, int stage, int parity) {
+  o.stage = [](fv_ctx* c, int stage, int parity, hipStream_t s) {
     hipLaunchKernelGGL((stage_kernel<DIM, NM, NS, T, C, TX, TY>), dim3(c->total_blocks),
-                       dim3(TX * TY), St::smem_bytes(), c->stream, c->insts_d,
+                       dim3(TX * TY), St::smem_bytes(), s, c->insts_d,
                        c->block_inst_d, c->P, stage, parity);
   };
   o.p2c = [](fv_ctx* c, int ii, const double* prim) {
@@ -307,12 +321,20 @@ hipError_t set_smem_attr() {
                              (int)St::smem_bytes());
 }
 
-// one selection entry per translation unit's precision
-#define FV_SEL(D, M, S_, TT, CC, X, Y)                                  \
-  if (dim == D && nm == M && ns == S_) {                               \
-    o = make_ops<D, M, S_, TT, CC, X, Y>();                            \
-    if (set_attr) herr = set_smem_attr<D, M, S_, TT, CC, X, Y>();      \
-    return true;                                                       \
+// one compiled tile shape of a kernel set (the first one listed is the
+// default); set_attr also raises the kernel's dynamic LDS limit, a runtime
+// call that size-only queries skip
+#define FV_VAR(D, M, S_, TT, CC, X, Y)                                      \
+  {                                                                        \
+    vars.push_back(make_ops<D, M, S_, TT, CC, X, Y>());                    \
+    if (set_attr && herr == hipSuccess) herr = set_smem_attr<D, M, S_, TT, CC, X, Y>(); \
   }
+
+// kernel sets of each translation unit: every tile shape compiled for a
+// (dimension, materials, solids) combination
+bool select_ops_fp64(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t& herr,
+                     bool set_attr);
+bool select_ops_fp32(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t& herr,
+                     bool set_attr);
 
 }  // namespace fvk

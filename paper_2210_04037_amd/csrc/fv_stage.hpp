@@ -82,6 +82,7 @@ struct Stage {
     const Inst* I;
     Params P;
     int stage;      // 1, 2, 3
+    bool dry;       // timing run: no boundary accumulation
     int parity;     // step & 1
     int bx, by;     // tile coordinates
     C dt;
@@ -447,7 +448,7 @@ struct Stage {
       }
     }
     // outward boundary flux accumulation, RK3 weights 1/6, 1/6, 2/3
-    if (!periodic && (lo_b || hi_b)) {
+    if (!periodic && (lo_b || hi_b) && !cx.dry) {
       const C w = cx.stage == 3 ? (C)(2.0 / 3.0) : (C)(1.0 / 6.0);
       const C sgn = lo_b ? (C)-1 : (C)1;
       double* acc = I.bacc + I.bacc_off[2 * a + (hi_b ? 1 : 0)] + (int64_t)bslot * NC;

@@ -20,7 +20,8 @@ class GpuSolver:
     materials and options)."""
 
     def __init__(self, cases, precision="fp64", device="cuda:0", cfl=None,
-                 phi_floor=1e-8, weno_eps=1e-6, phi_fp64_cut=1e-6, load=True):
+                 phi_floor=1e-8, weno_eps=1e-6, phi_fp64_cut=1e-6, load=True,
+                 tile=None, use_graph=False):
         import torch
         if not isinstance(cases, (list, tuple)):
             cases = [cases]
@@ -36,7 +37,7 @@ class GpuSolver:
             *[abi.grid_struct(c) for c in cases])
         self.mat_arr = abi.material_array(self.mats)
         self.opt = abi.options_struct(precision, cfl or c0.cfl, phi_floor,
-                                      weno_eps, phi_fp64_cut)
+                                      weno_eps, phi_fp64_cut, tile, use_graph)
         self.S = lib.fv_state_fields(self.dim, len(self.mats), self.mat_arr)
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         self.states, self.phi0s = [], []
@@ -115,6 +116,19 @@ class GpuSolver:
     def state(self, i=0):
         self.torch.cuda.synchronize(self.device)
         return self.states[i].double().cpu().numpy()
+
+    def autotune(self, reps=20):
+        """Time every compiled tile shape, keep the fastest; returns
+        (chosen (tx, ty), {(tx, ty): ms per launch})."""
+        cap = 16
+        tiles = (ctypes.c_int32 * (2 * cap))()
+        ms = (ctypes.c_float * cap)()
+        nv, ch = ctypes.c_int32(), ctypes.c_int32()
+        self._c(self.lib.fv_autotune(self.ctx, int(reps), cap, tiles, ms,
+                                     ctypes.byref(nv), ctypes.byref(ch)))
+        n = min(nv.value, cap)
+        table = {(tiles[2 * v], tiles[2 * v + 1]): ms[v] for v in range(n)}
+        return (tiles[2 * ch.value], tiles[2 * ch.value + 1]), table
 
     def fragments(self, i=0, cut=0.5, cap=None):
         """Fragment labels (nz, ny, nx) int32 (-1 outside material) and the
