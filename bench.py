@@ -5,7 +5,8 @@ after it on the same workload for the comparison (its throughput and the
 per-field L1 error of FP32-bulk against it).
 
 One step = one full time step of the whole hot path over the 1024^2
-expanding-ring workload: three SSP-RK3 stage launches (reconstruction, HLLC
+expanding-ring workload (or, with --workload ensemble, over every member of
+the seeded ensemble of uneven rings in one context): three SSP-RK3 stage launches (reconstruction, HLLC
 with the void-opening modifier, conservative update) with the source step
 (plastic return, damage, phi0 gather) and the CFL reduction fused into the
 third.  Inputs are resident in HBM when the timed region starts.
@@ -28,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2210_04037_amd", "csrc", f)
                   for f in ("fv_core.hpp", "fv_stage.hpp", "fv_kernels.hpp",
-                            "fv_api.hip", "fv_fp32.hip")]
+                            "fv_fp64.hip", "fv_fp32.hip")]
 
 
 def kernel_source_hash():
@@ -87,65 +88,97 @@ def cpu_baseline(case, seconds=15.0):
                       f"the annulus, {steps} steps, single thread"}
 
 
-def run_gpu(case, precision, steps, warmup):
-    """Time `steps` steps after `warmup` untimed ones; return the timing and
-    the primitive state and conservation totals at the end."""
+def _step_chunked(g, n, chunk):
+    """n steps as replays of captured chunk-step graphs (plus one call for
+    the remainder), or one eager call when chunk is 0."""
+    if chunk <= 0:
+        g.step(n)
+        return
+    for _ in range(n // chunk):
+        g.step(chunk)
+    if n % chunk:
+        g.step(n % chunk)
+
+
+def run_gpu(cases, precision, steps, warmup, autotune=True, chunk=10,
+            keep_state=True):
+    """Time `steps` steps after `warmup` untimed ones (the autotuner runs
+    before the warm-up); return the timing, the chosen tile, and the
+    primitive states and conservation totals at the end."""
     import torch
     from paper_2210_04037_amd.solver import GpuSolver
-    g = GpuSolver(case, precision=precision, device="cuda:0")
+    g = GpuSolver(cases, precision=precision, device="cuda:0",
+                  use_graph=chunk > 0)
     tot0, _ = g.totals()
-    g.step(warmup)
+    tile, table = (None, None)
+    if autotune:
+        tile, table = g.autotune(reps=10)
+    _step_chunked(g, warmup, chunk)
     torch.cuda.synchronize()
     s = g.stream
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(s)
-    g.step(steps)
+    _step_chunked(g, steps, chunk)
     e1.record(s)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    t = g.time()[0]
+    t = g.time()
     g.cfl_dt()          # raises if the device flagged a non-physical state
     tot1, out1 = g.totals()
-    W = g.primitive(0)
+    W = [g.primitive(i) for i in range(len(g.cases))] if keep_state else None
     S = g.S
     elem = 8 if precision == "fp64" else 4
     g.close()
-    return dict(ms=ms, S=S, elem=elem, t=t, W=W, tot0=tot0[0],
-                tot1=tot1[0] + out1[0])
+    return dict(ms=ms, S=S, elem=elem, t=t, W=W, tot0=tot0, tot1=tot1 + out1,
+                tile=tile, tiles_ms=table)
 
 
-def precision_report(case, r32, r64):
+def precision_report(cases, r32, r64):
     """Per-field L1 of the FP32-bulk run against the FP64 run after the same
-    steps (relative to the FP64 field's L1; eps_p and D over solid cells),
-    and the relative conservation drift of the FP32-bulk run."""
+    steps (relative to the FP64 field's L1, summed over every instance; eps_p
+    and D over solid cells), and the worst relative conservation drift of
+    the FP32-bulk run over the instances."""
     import numpy as np
     from paper_2210_04037_amd.abi import state_rows
-    rows = state_rows(case.dim, len(case.mats),
-                      [m["kind"] == "solid" for m in case.mats])
-    W32, W64 = r32["W"], r64["W"]
-
-    def l1(a, b, mask=None):
-        if mask is not None:
-            a, b = a[mask], b[mask]
-        den = np.sum(np.abs(b))
-        return float(np.sum(np.abs(a - b)) / den) if den > 0 else 0.0
-
+    c0 = cases[0]
+    rows = state_rows(c0.dim, len(c0.mats),
+                      [m["kind"] == "solid" for m in c0.mats])
+    num = dict(rho=0.0, u=0.0, eps_p=0.0, D=0.0)
+    den = dict(rho=0.0, u=0.0, eps_p=0.0, D=0.0)
     rho = lambda W: np.sum(W[rows["phi"]] * W[rows["mass"]], axis=0)
     spd = lambda W: np.sqrt(np.sum(W[rows["mom"]] ** 2, axis=0))
-    solid = W64[rows["phi"][0]] > 0.5
-    nm = len(case.mats)
-    c0, c1 = r32["tot0"], r32["tot1"]
+    for W32, W64 in zip(r32["W"], r64["W"]):
+        solid = W64[rows["phi"][0]] > 0.5
+        pairs = dict(rho=(rho(W32), rho(W64)), u=(spd(W32), spd(W64)),
+                     eps_p=(W32[rows["eps"][0]][solid], W64[rows["eps"][0]][solid]),
+                     D=(W32[rows["dmg"][0]][solid], W64[rows["dmg"][0]][solid]))
+        for k, (a, b) in pairs.items():
+            num[k] += float(np.sum(np.abs(a - b)))
+            den[k] += float(np.sum(np.abs(b)))
+    nm = len(c0.mats)
+    a0, a1 = r32["tot0"], r32["tot1"]
     return {
-        "l1_rel_vs_fp64": {
-            "rho": l1(rho(W32), rho(W64)), "u": l1(spd(W32), spd(W64)),
-            "eps_p": l1(W32[rows["eps"][0]], W64[rows["eps"][0]], solid),
-            "D": l1(W32[rows["dmg"][0]], W64[rows["dmg"][0]], solid)},
+        "l1_rel_vs_fp64": {k: (num[k] / den[k] if den[k] > 0 else 0.0)
+                           for k in num},
         "bars": {"rho": 1e-4, "u": 1e-3, "eps_p": 1e-3, "D": 1e-2},
-        "mass_drift": max(abs(c1[l] - c0[l]) / abs(c0[l]) for l in range(nm)),
-        "energy_drift": abs(c1[-1] - c0[-1]) / abs(c0[-1]),
-        "sim_time_fp32_fp64": [r32["t"], r64["t"]],
+        "mass_drift": max(abs(a1[i][l] - a0[i][l]) / abs(a0[i][l])
+                          for i in range(len(cases)) for l in range(nm)),
+        "energy_drift": max(abs(a1[i][-1] - a0[i][-1]) / abs(a0[i][-1])
+                            for i in range(len(cases))),
+        "sim_time_fp32_fp64": [float(r32["t"][0]), float(r64["t"][0])],
     }
+
+
+def loop_single_runs(cases, precision, steps, warmup, chunk):
+    """The same members one context at a time (each autotuned, warmed up
+    and timed alone); returns the summed timed milliseconds."""
+    total = 0.0
+    for c in cases:
+        r = run_gpu([c], precision, steps, warmup, chunk=chunk,
+                    keep_state=False)
+        total += r["ms"]
+    return total
 
 
 def calibrate_copy(nbytes=1 << 30, reps=5):
@@ -175,6 +208,16 @@ def main():
                          "per-field L1 error of FP32-bulk against FP64)")
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="ring", choices=["ring", "ensemble"],
+                    help="ring: the 1024^2 expanding ring (default); "
+                         "ensemble: seeded rings of uneven sizes in one "
+                         "context")
+    ap.add_argument("--members", type=int, default=64)
+    ap.add_argument("--no-loop", action="store_true",
+                    help="ensemble: skip timing the members one at a time")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--graph-chunk", type=int, default=10,
+                    help="steps per captured graph (0: eager launches)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device copy (counter scaling)")
     args = ap.parse_args()
@@ -187,10 +230,22 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import fvinputs as F
-    case = F.make_case(2, n=args.n)
-    ncell = case.n_cells
+    chunk = args.graph_chunk
+    if args.workload == "ring":
+        cases = [F.make_case(2, n=args.n)]
+        workload = (f"2D expanding ring {args.n}x{args.n} over a 60 mm "
+                    "square: copper-like annulus 25-26.5 mm in gas, "
+                    "150 m/s r/R, Gaussian phi0 (0.2 mm, 5%)")
+    else:
+        cases = [F.make_case(4, member=m) for m in range(args.members)]
+        workload = (f"ensemble of {args.members} seeded 2D expanding rings, "
+                    "edges drawn from {256,384,512,768}, ring speeds "
+                    "U(100, 250) m/s, one context (every member in each "
+                    "launch)")
+    ncell = sum(c.n_cells for c in cases)
     other = "fp64" if args.precision == "fp32" else "fp32"
-    r = run_gpu(case, args.precision, args.steps, args.warmup)
+    r = run_gpu(cases, args.precision, args.steps, args.warmup,
+                autotune=not args.no_autotune, chunk=chunk)
     ms, S, elem = r["ms"], r["S"], r["elem"]
     cu_s = ncell * args.steps / (ms * 1e-3)
     launches = 3 * args.steps
@@ -199,7 +254,7 @@ def main():
     # plus one phi0 read; per launch that is a third of it
     bytes_per_launch = (8 * S + 1) * elem * ncell / 3.0
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = measured_traffic(args.precision)
+    traffic = measured_traffic(args.precision) if args.workload == "ring" else None
     out = {
         "metric": "cell-updates/s",
         "value": cu_s,
@@ -214,14 +269,13 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {
-            "workload": (f"2D expanding ring {args.n}x{args.n} over a 60 mm "
-                         "square: copper-like annulus 25-26.5 mm in gas, "
-                         "150 m/s r/R, Gaussian phi0 (0.2 mm, 5%)"),
-            "cells": ncell, "state_fields": S,
+            "workload": workload,
+            "cells": ncell, "instances": len(cases), "state_fields": S,
             "precision": ("fp32-bulk (FP64 EOS island, FP64 plastic return "
                           "and damage, exact totals)"
                           if args.precision == "fp32" else "fp64"),
-            "simulated_time_s": r["t"],
+            "tile": r["tile"], "graph_chunk_steps": chunk,
+            "simulated_time_s": float(r["t"][0]),
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -231,16 +285,27 @@ def main():
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": avg_launch_s * 1e3,
         },
+        "autotune_ms_per_stage1_launch": (
+            {f"{k[0]}x{k[1]}": v for k, v in r["tiles_ms"].items()}
+            if r["tiles_ms"] else None),
     }
     if not args.no_compare:
-        r2 = run_gpu(case, other, args.steps, args.warmup)
+        r2 = run_gpu(cases, other, args.steps, args.warmup,
+                     autotune=not args.no_autotune, chunk=chunk)
         out[f"{other}_form"] = {
             "value": ncell * args.steps / (r2["ms"] * 1e-3),
-            "ms_per_step": r2["ms"] / args.steps}
+            "ms_per_step": r2["ms"] / args.steps, "tile": r2["tile"]}
         r32, r64 = (r, r2) if args.precision == "fp32" else (r2, r)
-        out["precision"] = precision_report(case, r32, r64)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(case)
+        out["precision"] = precision_report(cases, r32, r64)
+    if args.workload == "ensemble" and not args.no_loop:
+        loop_ms = loop_single_runs(cases, args.precision, args.steps,
+                                   args.warmup, chunk)
+        out["loop_of_single_runs"] = {
+            "value": ncell * args.steps / (loop_ms * 1e-3),
+            "ms_per_step": loop_ms / args.steps,
+            "ensemble_speedup": loop_ms / ms}
+    if not args.no_cpu and args.workload == "ring":
+        out["cpu_baseline"] = cpu_baseline(cases[0])
     print(json.dumps(out), flush=True)
 
 

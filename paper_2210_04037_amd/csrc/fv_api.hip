@@ -228,12 +228,12 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
 // and their device copies (synchronises the stream).  Captured step graphs
 // hold the old launch shape and are dropped.
 static void drop_graphs(fv_ctx* c) {
-  for (auto& g : c->gexec)
-    if (g) {
-      (void)hipGraphExecDestroy(g);
-      g = nullptr;
-    }
-  c->graph_steps = 0;
+  for (int k = 0; k < fv_ctx::NGRAPH; ++k) {
+    if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    c->gexec[k] = nullptr;
+    c->gkey[k] = 0;
+  }
+  c->gnext = 0;
 }
 
 static int set_tiles(fv_ctx* c, int v) {
@@ -507,9 +507,17 @@ int32_t fv_step(fv_ctx* c, const double* dt_host, int32_t n_steps, const double*
   // n_steps steps as one graph, captured on a private stream at the first
   // call with this step count and starting parity, then replayed on the
   // context's stream (launch arguments are fixed; dt, time and the CFL state
-  // live on the device)
-  if (c->graph_steps != n_steps) drop_graphs(c);
-  if (!c->gexec[p0]) {
+  // live on the device).  A few graphs are kept, the oldest replaced first.
+  const int key = 2 * n_steps + p0;
+  int slot = -1;
+  for (int k = 0; k < fv_ctx::NGRAPH; ++k)
+    if (c->gkey[k] == key) slot = k;
+  if (slot < 0) {
+    slot = c->gnext;
+    c->gnext = (c->gnext + 1) % fv_ctx::NGRAPH;
+    if (c->gexec[slot]) (void)hipGraphExecDestroy(c->gexec[slot]);
+    c->gexec[slot] = nullptr;
+    c->gkey[slot] = 0;
     int rc = FV_OK;
     if (!c->cap_stream)
       rc = hip_check(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking),
@@ -527,17 +535,17 @@ int32_t fv_step(fv_ctx* c, const double* dt_host, int32_t n_steps, const double*
     const hipError_t ee = hipStreamEndCapture(c->cap_stream, &graph);
     rc = hip_check(c, le != hipSuccess ? le : ee, "capture step graph");
     if (rc == FV_OK)
-      rc = hip_check(c, hipGraphInstantiate(&c->gexec[p0], graph, nullptr, nullptr, 0),
+      rc = hip_check(c, hipGraphInstantiate(&c->gexec[slot], graph, nullptr, nullptr, 0),
                      "instantiate step graph");
     if (graph) (void)hipGraphDestroy(graph);
     if (rc != FV_OK) {
-      c->gexec[p0] = nullptr;
+      c->gexec[slot] = nullptr;
       return rc;
     }
-    c->graph_steps = n_steps;
+    c->gkey[slot] = key;
   }
   c->step += n_steps;
-  return hip_check(c, hipGraphLaunch(c->gexec[p0], c->stream), "step graph launch");
+  return hip_check(c, hipGraphLaunch(c->gexec[slot], c->stream), "step graph launch");
 }
 
 int32_t fv_autotune(fv_ctx* c, int32_t reps, int32_t max_report, int32_t* tiles, float* ms,

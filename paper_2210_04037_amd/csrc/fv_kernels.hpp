@@ -266,11 +266,13 @@ struct fv_ctx {
   int var = 0;
   int max_blocks = 0;                 // capacity of the block table
   std::vector<int> h_block_inst;
-  // multi-step graphs: one per starting step parity, for graph_steps steps
+  // captured multi-step graphs, keyed by (step count, starting parity)
+  static constexpr int NGRAPH = 4;
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  int graph_steps = 0;
+  hipGraphExec_t gexec[NGRAPH] = {};
+  int gkey[NGRAPH] = {};              // 2 * n_steps + parity, 0 = empty
+  int gnext = 0;                      // slot replaced next
   std::vector<double> h_dt, h_tend;   // staging for async copies
   std::string err;
 };
