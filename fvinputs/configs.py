@@ -96,10 +96,14 @@ def _centres(n, lo, hi, sub=1):
     return out
 
 
-def _subsample(dim, n, lo, hi, indicator, velocity, rho_in, rho_out, sub=4):
+def _subsample(dim, n, lo, hi, indicator, velocity, rho_in, rho_out, sub=4,
+               may_hold=None):
     """Volume fraction of the solid region and the mass-weighted velocity of
     each cell from sub^dim sub-samples.  `indicator(x, y, z)` -> bool array,
-    `velocity(x, y, z)` -> list of d arrays (solid velocity)."""
+    `velocity(x, y, z)` -> list of d arrays (solid velocity).  `may_hold(x,
+    y, z, reach)`, if given, marks the cells whose centre lies within `reach`
+    (half the cell diagonal) of the solid region; the others hold no solid
+    sub-sample and are skipped (same values, computed only where needed)."""
     nx, ny, nz = n
     frac = np.zeros((nz, ny, nx))
     mom = np.zeros((dim, nz, ny, nx))
@@ -107,20 +111,47 @@ def _subsample(dim, n, lo, hi, indicator, velocity, rho_in, rho_out, sub=4):
     subs = [sub if k < dim else 1 for k in range(3)]
     d = [(hi[k] - lo[k]) / n[k] for k in range(3)]
     cnt = float(np.prod(subs))
+    if may_hold is None:
+        cells = None
+    else:
+        cx, cy, cz = _centres(n, lo, hi)
+        Zc, Yc, Xc = np.meshgrid(cz, cy, cx, indexing="ij")
+        reach = 0.5 * float(np.sqrt(sum(d[k] ** 2 for k in range(dim))))
+        cells = np.nonzero(may_hold(Xc, Yc, Zc, reach).ravel())[0]
+        del Xc, Yc, Zc
+        iz, iy, ix = np.unravel_index(cells, (nz, ny, nx))
+        mass.ravel()[:] = rho_out * cnt        # no solid sub-sample
     for sz in range(subs[2]):
-        zc = lo[2] + (np.arange(nz) + (sz + 0.5) / subs[2]) * d[2]
         for sy in range(subs[1]):
-            yc = lo[1] + (np.arange(ny) + (sy + 0.5) / subs[1]) * d[1]
             for sx in range(subs[0]):
-                xc = lo[0] + (np.arange(nx) + (sx + 0.5) / subs[0]) * d[0]
-                Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+                if cells is None:
+                    zc = lo[2] + (np.arange(nz) + (sz + 0.5) / subs[2]) * d[2]
+                    yc = lo[1] + (np.arange(ny) + (sy + 0.5) / subs[1]) * d[1]
+                    xc = lo[0] + (np.arange(nx) + (sx + 0.5) / subs[0]) * d[0]
+                    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+                    ins = indicator(X, Y, Z)
+                    frac += ins
+                    rho = np.where(ins, rho_in, rho_out)
+                    mass += rho
+                    vel = velocity(X, Y, Z)
+                    for k in range(dim):
+                        mom[k] += np.where(ins, rho * vel[k], 0.0)
+                    continue
+                Z = lo[2] + (iz + (sz + 0.5) / subs[2]) * d[2]
+                Y = lo[1] + (iy + (sy + 0.5) / subs[1]) * d[1]
+                X = lo[0] + (ix + (sx + 0.5) / subs[0]) * d[0]
                 ins = indicator(X, Y, Z)
-                frac += ins
                 rho = np.where(ins, rho_in, rho_out)
-                mass += rho
+                f = frac.ravel()
+                f[cells] = f[cells] + ins
+                if sz == 0 and sy == 0 and sx == 0:
+                    mass.ravel()[cells] = 0.0
+                mv = mass.ravel()
+                mv[cells] = mv[cells] + rho
                 vel = velocity(X, Y, Z)
                 for k in range(dim):
-                    mom[k] += np.where(ins, rho * vel[k], 0.0)
+                    mk = mom[k].ravel()
+                    mk[cells] = mk[cells] + np.where(ins, rho * vel[k], 0.0)
     frac /= cnt
     u = mom / mass[None]
     return frac, u
@@ -235,8 +266,12 @@ def make_case(config, n=None, member=None, t_end=None):
             r = np.where(r > 0, r, 1.0)
             return [200.0 * X / r, 200.0 * Y / r, np.zeros_like(X)]
 
+        def near(X, Y, Z, reach):
+            r = np.sqrt(X * X + Y * Y)
+            return (np.abs(r - 0.0155) <= 0.0005 + reach) & (np.abs(Z) <= 0.015 + reach)
+
         frac, u = _subsample(3, grid, lo, hi, ind, vel, mats[0]["rho0"],
-                             mats[1]["rho0"])
+                             mats[1]["rho0"], may_hold=near)
         prim = _assemble(3, mats, frac, u, P_ATM, grid, lo, hi)
         d = (hi[0] - lo[0]) / ne
         phi0 = lognormal_field((ne, ne, ne), (d, d, d), 0.3e-3, 0.05,

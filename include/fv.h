@@ -63,7 +63,7 @@ extern "C" {
 
 typedef struct fv_ctx fv_ctx;
 
-/* Uniform grid of one instance.  dim in {1, 2}; n[k] cells on [lo[k],hi[k]]
+/* Uniform grid of one instance.  dim in {1, 2, 3}; n[k] cells on [lo[k],hi[k]]
  * for k < dim (unused directions: n = 1, and their extent sets the cell
  * volume).  bc[k][0] / bc[k][1] are the lower / upper sides. */
 typedef struct {
@@ -113,7 +113,8 @@ int32_t fv_state_fields(int32_t dim, int32_t n_mat, const fv_material* mats);
 
 /* Bytes of device workspace fv_init needs for these instances (two stage
  * copies of every state, boundary-flux accumulators, dt state, instance
- * tables, reduction bins).  Returns 0 for invalid arguments. */
+ * tables, reduction bins; in 3D also the primitives of every cell and the
+ * face data of each direction).  Returns 0 for invalid arguments. */
 size_t fv_workspace_bytes(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
                           const fv_material* mats, const fv_options* opt);
 

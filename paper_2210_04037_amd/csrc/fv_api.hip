@@ -133,7 +133,7 @@ static int validate(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
   for (int i = 0; i < n_inst; ++i) {
     const fv_grid& g = grids[i];
     if (g.dim != dim) { msg = "all instances must share the dimension"; return FV_EINVAL; }
-    if (g.dim < 1 || g.dim > 2) { msg = "dim must be 1 or 2"; return FV_EINVAL; }
+    if (g.dim < 1 || g.dim > 3) { msg = "dim must be 1, 2 or 3"; return FV_EINVAL; }
     for (int k = 0; k < 3; ++k) {
       if (g.n[k] < 1 || (k >= g.dim && g.n[k] != 1)) { msg = "bad cell counts"; return FV_EINVAL; }
       if (!(g.hi[k] > g.lo[k])) { msg = "hi must exceed lo"; return FV_EINVAL; }
@@ -149,7 +149,7 @@ static int validate(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
 }
 
 struct WsPlan {
-  std::vector<size_t> u1, u2, bacc, dts;
+  std::vector<size_t> u1, u2, bacc, dts, wb, fb[3];
   size_t insts = 0, block_inst = 0, bins = 0, total = 0;
   int max_blocks = 0;
 };
@@ -179,11 +179,18 @@ static void plan_ws(int32_t n_inst, const fv_grid* grids, const std::vector<Ops>
     W.u2.push_back(off); off += sb;
     size_t nb = 0;
     for (int a = 0; a < 3; ++a) {
-      const int nt = a < g.dim ? (a == 0 ? g.n[1] * g.n[2] : g.n[0] * g.n[2]) : 0;
+      const int nt = a < g.dim ? (int)(((int64_t)g.n[0] * g.n[1] * g.n[2]) / g.n[a]) : 0;
       nb += 2 * (size_t)nt * o.NC;
     }
     W.bacc.push_back(off); off += align256(nb * sizeof(double));
     W.dts.push_back(off); off += align256(DTS_SIZE * sizeof(double));
+    // 3D passes: primitives of every cell and the face data of each direction
+    W.wb.push_back(off);
+    if (g.dim == 3) off += align256((size_t)o.NW * ncell * o.elem);
+    for (int a = 0; a < 3; ++a) {
+      W.fb[a].push_back(off);
+      if (g.dim == 3) off += align256((size_t)o.NQ * (ncell / g.n[a]) * (g.n[a] + 1) * o.elem);
+    }
   }
   W.insts = off; off += align256(sizeof(Inst) * n_inst);
   W.block_inst = off; off += align256(sizeof(int) * W.max_blocks);
@@ -347,6 +354,8 @@ int32_t fv_init(fv_ctx** out, int32_t n_inst, const fv_grid* grids, int32_t n_ma
     I.U2 = ws + W.u2[i];
     I.phi0 = phi0[i];
     I.bacc = (double*)(ws + W.bacc[i]);
+    I.Wb = g.dim == 3 ? (void*)(ws + W.wb[i]) : nullptr;
+    for (int a = 0; a < 3; ++a) I.Fb[a] = g.dim == 3 ? (void*)(ws + W.fb[a][i]) : nullptr;
     I.dts = (double*)(ws + W.dts[i]);
     for (int k = 0; k < 3; ++k) {
       I.n[k] = g.n[k];
@@ -358,7 +367,7 @@ int32_t fv_init(fv_ctx** out, int32_t n_inst, const fv_grid* grids, int32_t n_ma
     I.ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
     int off = 0;
     for (int a = 0; a < 3; ++a) {
-      const int nt = a < g.dim ? (a == 0 ? g.n[1] * g.n[2] : g.n[0] * g.n[2]) : 0;
+      const int nt = a < g.dim ? (int)(((int64_t)g.n[0] * g.n[1] * g.n[2]) / g.n[a]) : 0;
       I.bacc_off[2 * a] = off; off += nt * c->ops.NC;
       I.bacc_off[2 * a + 1] = off; off += nt * c->ops.NC;
     }
@@ -384,7 +393,7 @@ static int reset_inst(fv_ctx* c, int i) {
   const int q = (int)(c->step & 1);
   size_t nb = 0;
   for (int a = 0; a < c->dim; ++a) {
-    const int nt = a == 0 ? I.n[1] * I.n[2] : I.n[0] * I.n[2];
+    const int nt = (int)(I.ncell / I.n[a]);
     nb += 2 * (size_t)nt * c->ops.NC;
   }
   int rc = hip_check(c, hipMemsetAsync(I.bacc, 0, nb * sizeof(double), c->stream), "zero accumulators");
@@ -623,7 +632,7 @@ int32_t fv_totals(fv_ctx* c, double* out) {
                            c->bins_d + (size_t)slot * NBINS);
     }
     for (int a = 0; a < dim; ++a) {
-      const int nt = a == 0 ? I.n[1] * I.n[2] : I.n[0] * I.n[2];
+      const int nt = (int)(I.ncell / I.n[a]);
       for (int side = 0; side < 2; ++side) {
         for (int k = 0; k < NT; ++k, ++slot) {
           if (I.bc[a][side] == FV_BC_PERIODIC) continue;
@@ -653,7 +662,7 @@ int32_t fv_totals(fv_ctx* c, double* out) {
     // per-side values
     std::vector<std::vector<double>> per(NT);
     for (int a = 0; a < dim; ++a) {
-      const double area = a == 0 ? I.dx[1] * I.dx[2] : I.dx[0] * I.dx[2];
+      const double area = a == 0 ? I.dx[1] * I.dx[2] : (a == 1 ? I.dx[0] * I.dx[2] : I.dx[0] * I.dx[1]);
       for (int side = 0; side < 2; ++side)
         for (int k = 0; k < NT; ++k, ++slot)
           per[k].push_back(bins_to_double(&bins[(size_t)slot * NBINS]) * area);

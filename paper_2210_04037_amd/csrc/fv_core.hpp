@@ -331,6 +331,74 @@ FV_HD void sym2_exp(C a00, C a01, C a11, C& e00, C& e01, C& e11) {
   e01 = em * sh * a01;
 }
 
+// Eigen-decomposition of a symmetric 3x3 matrix by cyclic Jacobi rotations
+// (each rotation zeroes one off-diagonal pair; sweeps repeat until the
+// off-diagonal mass is below rounding).  Degenerate eigenvalues need no
+// special case, which matters for the near-identity stretches of an elastic
+// solid.  A is overwritten by its diagonal form, Q collects the rotations
+// (columns are eigenvectors).
+template <int P_, int Q_, int R_, class C>
+FV_HD void jacobi_rotate(C A[3][3], C Q[3][3]) {
+  const C apq = A[P_][Q_];
+  // An off-diagonal entry below the rounding of the diagonal pair is already
+  // zero.  The absolute floor keeps 1 / (2 apq) finite: with reciprocal
+  // division a degenerate pair (equal diagonal) and a denormal apq would
+  // otherwise give 0 * inf.
+  const C rel = sizeof(C) == 8 ? (C)1e-18 : (C)1e-9;
+  const C floor_abs = sizeof(C) == 8 ? (C)1e-280 : (C)1e-30;
+  if (m_abs(apq) <= rel * (m_abs(A[P_][P_]) + m_abs(A[Q_][Q_])) || m_abs(apq) < floor_abs) {
+    A[P_][Q_] = A[Q_][P_] = (C)0;
+    return;
+  }
+  const C theta = (A[Q_][Q_] - A[P_][P_]) / ((C)2 * apq);
+  const C at = m_abs(theta);
+  // t = tan of the rotation angle, the smaller root of t^2 + 2 theta t - 1
+  const C t0 = (C)1 / (at + m_sqrt(at * at + (C)1));
+  const C t = theta < (C)0 ? -t0 : t0;
+  const C cs = (C)1 / m_sqrt(t * t + (C)1);
+  const C sn = t * cs;
+  A[P_][P_] -= t * apq;
+  A[Q_][Q_] += t * apq;
+  A[P_][Q_] = A[Q_][P_] = (C)0;
+  const C arp = A[R_][P_], arq = A[R_][Q_];
+  A[R_][P_] = A[P_][R_] = cs * arp - sn * arq;
+  A[R_][Q_] = A[Q_][R_] = sn * arp + cs * arq;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const C qp = Q[k][P_], qq = Q[k][Q_];
+    Q[k][P_] = cs * qp - sn * qq;
+    Q[k][Q_] = sn * qp + cs * qq;
+  }
+}
+
+template <class C>
+FV_HD void sym3_eig(C A[3][3], C Q[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Q[i][j] = i == j ? (C)1 : (C)0;
+  const C eps = sizeof(C) == 8 ? (C)1e-32 : (C)1e-15;   // squared rounding
+  const int max_sweeps = sizeof(C) == 8 ? 10 : 8;
+  for (int s = 0; s < max_sweeps; ++s) {
+    const C off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const C dg = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (off <= eps * dg || off == (C)0) break;
+    jacobi_rotate<0, 1, 2>(A, Q);
+    jacobi_rotate<0, 2, 1>(A, Q);
+    jacobi_rotate<1, 2, 0>(A, Q);
+  }
+}
+
+// Q diag(f) Q^T
+template <class C>
+FV_HD void sym3_compose(const C Q[3][3], const C f[3], C M[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      M[i][j] = Q[i][0] * f[0] * Q[j][0] + Q[i][1] * f[1] * Q[j][1] + Q[i][2] * f[2] * Q[j][2];
+}
+
 // dev H (full symmetric 3x3, zeros where the dimension keeps them zero)
 template <int DIM, class C>
 FV_HD void hencky(const C V[3][3], C H[3][3]) {
@@ -342,6 +410,22 @@ FV_HD void hencky(const C V[3][3], C H[3][3]) {
     const C h0 = m_log(m_abs(V[0][0])), h1 = m_log(m_abs(V[1][1])), h2 = m_log(m_abs(V[2][2]));
     const C mm = (h0 + h1 + h2) / (C)3;
     H[0][0] = h0 - mm; H[1][1] = h1 - mm; H[2][2] = h2 - mm;
+  } else if (DIM == 3) {
+    // B = V V^T, H = 1/2 ln B through its eigen-decomposition
+    C B[3][3], Q[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        B[i][j] = V[i][0] * V[j][0] + V[i][1] * V[j][1] + V[i][2] * V[j][2];
+    sym3_eig(B, Q);
+    C h[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) h[k] = (C)0.5 * m_log(B[k][k]);
+    const C mm = (h[0] + h[1] + h[2]) / (C)3;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) h[k] -= mm;
+    sym3_compose(Q, h, H);
   } else {
     const C b00 = V[0][0] * V[0][0] + V[0][1] * V[0][1];
     const C b01 = V[0][0] * V[1][0] + V[0][1] * V[1][1];
@@ -375,6 +459,17 @@ FV_HD void stretch_from_log(const C H[3][3], C V[3][3]) {
     for (int j = 0; j < 3; ++j) V[i][j] = 0;
   if (DIM == 1) {
     V[0][0] = m_exp(H[0][0]); V[1][1] = m_exp(H[1][1]); V[2][2] = m_exp(H[2][2]);
+  } else if (DIM == 3) {
+    C A[3][3], Q[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) A[i][j] = H[i][j];
+    sym3_eig(A, Q);
+    C e[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e[k] = m_exp(A[k][k]);
+    sym3_compose(Q, e, V);
   } else {
     C e00, e01, e11;
     sym2_exp(H[0][0], H[0][1], H[1][1], e00, e01, e11);

@@ -39,6 +39,14 @@ bool select_ops_fp32(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t
     FV_VAR(2, 2, 1, float, float, 64, 4)
     return true;
   }
+  if (dim == 3 && nm == 1 && ns == 1) {
+    FV_VAR3(1, 1, float, float)
+    return true;
+  }
+  if (dim == 3 && nm == 2 && ns == 1) {
+    FV_VAR3(2, 1, float, float)
+    return true;
+  }
   return false;
 }
 

@@ -162,7 +162,7 @@ stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int 
     for (int it = tid; it < nit; it += NT) {
       int cm, c0, c1, c2, gf, fs, bs;
       if (St::face_item(cx, a, it, cm, c0, c1, c2, gf, fs, bs))
-        St::compute_face(cx, sm, a, cm, c0, c1, c2, gf, fs, bs, fb);
+        St::template compute_face<int>(cx, sm, TL::NCELL, a, cm, c0, c1, c2, gf, fs, TL::NFACE, bs, fb);
     }
     __syncthreads();
     if (own) St::gather(cx, sm, fb, a, tx, ty, acc);
@@ -236,10 +236,171 @@ __global__ void __launch_bounds__(256) cfl_kernel(const Inst* insts, int ii, Par
 
 
 // ---------------------------------------------------------------------------
+// 3D stage: three passes over full-grid buffers in HBM.  A tile with a
+// two-cell halo in three directions does not fit in LDS at the number of
+// primitive fields a 3D cell carries, so the primitives go to HBM once, every
+// face of a direction is computed once from them, and a per-cell pass
+// gathers the six faces, applies the RK combination and (third stage) the
+// source step and CFL reduction.
+// ---------------------------------------------------------------------------
+// time step of the stage from the device dt state; fills the context.
+// stage 0 is the timing run of stage 1 (see stage_kernel).
+template <class St, class T, class C>
+__device__ __forceinline__ bool setup3(const Inst& I, const Params& P, int stage, int parity,
+                                       typename St::Ctx& cx, double& t, double& dtinv,
+                                       double& dt) {
+  const int q = parity & 1;
+  const double* dts = I.dts;
+  t = dts[DTS_T + q];
+  dtinv = dts[DTS_DTINV + q];
+  dt = dts[DTS_DTFIX] > 0.0 ? dts[DTS_DTFIX] : P.cfl / dtinv;
+  dt = fmin(dt, dts[DTS_TEND] - t);
+  const bool dry = stage == 0;
+  if (dry) stage = 1;
+  cx.I = &I;
+  cx.P = P;
+  cx.stage = stage;
+  cx.dry = dry;
+  cx.parity = q;
+  cx.bx = 0;
+  cx.by = 0;
+  cx.dt = (C)dt;
+  const T* U = (const T*)I.U;
+  cx.base = U;
+  cx.src = stage == 1 ? U : (stage == 2 ? (const T*)I.U1 : (const T*)I.U2);
+  cx.out = stage == 1 ? (T*)I.U1 : (stage == 2 ? (T*)I.U2 : (T*)I.U);
+  return dt > 0.0;
+}
+
+__device__ __forceinline__ int64_t nfaces3(const Inst& I, int a) {
+  return I.ncell / I.n[a] * (I.n[a] + 1);
+}
+
+template <int NM, int NS, class T, class C>
+__global__ void __launch_bounds__(256) prim3_kernel(const Inst* insts, int ii, Params P,
+                                                    int stage, int parity) {
+  using St = Stage<3, NM, NS, T, C, 1, 1>;
+  const Inst& I = insts[ii];
+  typename St::Ctx cx;
+  double t, dtinv, dt;
+  if (!setup3<St, T, C>(I, P, stage, parity, cx, t, dtinv, dt)) return;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= I.ncell) return;
+  St::template cell_prims<int64_t>(cx, g, (C*)I.Wb, I.ncell, g);
+}
+
+template <int NM, int NS, class T, class C>
+__global__ void __launch_bounds__(256) face3_kernel(const Inst* insts, int ii, Params P,
+                                                    int stage, int parity, int a) {
+  using St = Stage<3, NM, NS, T, C, 1, 1>;
+  const Inst& I = insts[ii];
+  typename St::Ctx cx;
+  double t, dtinv, dt;
+  if (!setup3<St, T, C>(I, P, stage, parity, cx, t, dtinv, dt)) return;
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nf = nfaces3(I, a);
+  if (f >= nf) return;
+  const int nx = I.n[0], ny = I.n[1];
+  int c[3], i;
+  if (a == 0) {
+    i = (int)(f % (nx + 1));
+    const int64_t r = f / (nx + 1);
+    c[1] = (int)(r % ny);
+    c[2] = (int)(r / ny);
+    c[0] = 0;
+  } else if (a == 1) {
+    c[0] = (int)(f % nx);
+    const int64_t r = f / nx;
+    i = (int)(r % (ny + 1));
+    c[2] = (int)(r / (ny + 1));
+    c[1] = 0;
+  } else {
+    c[0] = (int)(f % nx);
+    const int64_t r = f / nx;
+    c[1] = (int)(r % ny);
+    i = (int)(r / ny);
+    c[2] = 0;
+  }
+  // the face lies between cells i - 1 and i along a; stencil i - 2 .. i + 1
+  int64_t st[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    int cc[3] = {c[0], c[1], c[2]};
+    cc[a] = St::map_index(i - 2 + s, I.n[a], I.bc[a][0], I.bc[a][1]);
+    st[s] = ((int64_t)cc[2] * ny + cc[1]) * nx + cc[0];
+  }
+  const int64_t bslot = a == 0 ? (int64_t)c[2] * ny + c[1]
+                                : (a == 1 ? (int64_t)c[2] * nx + c[0] : (int64_t)c[1] * nx + c[0]);
+  St::template compute_face<int64_t>(cx, (const C*)I.Wb, I.ncell, a, st[0], st[1], st[2], st[3],
+                                     i, f, nf, bslot, (C*)I.Fb[a]);
+}
+
+template <int NM, int NS, class T, class C>
+__global__ void __launch_bounds__(256) finish3_kernel(const Inst* insts, int ii, Params P,
+                                                      int stage, int parity) {
+  using St = Stage<3, NM, NS, T, C, 1, 1>;
+  using L = Lay<3, NM, NS>;
+  __shared__ double scratch[4];
+  const Inst& I = insts[ii];
+  typename St::Ctx cx;
+  double t, dtinv, dt;
+  const bool dry = stage == 0;
+  const bool go = setup3<St, T, C>(I, P, stage, parity, cx, t, dtinv, dt);
+  const int q = parity & 1;
+  // time of the next step and a cleared CFL slot for the third stage's
+  // reduction (a finished instance carries its time and CFL value over)
+  if (cx.stage == 1 && !dry && blockIdx.x == 0 && threadIdx.x == 0) {
+    I.dts[DTS_T + 1 - q] = go ? t + dt : t;
+    I.dts[DTS_DTINV + 1 - q] = go ? 0.0 : dtinv;
+  }
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double cflv = 0.0;
+  if (go && g < I.ncell) {
+    const C* W = (const C*)I.Wb;
+    const int64_t nc = I.ncell;
+    C Xc[3], uc[3], phic[NM];
+    C Vc[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      Xc[k] = W[(L::W_X + k) * nc + g];
+      uc[k] = W[(L::R_U + k) * nc + g];
+    }
+#pragma unroll
+    for (int l = 0; l < NM; ++l) phic[l] = W[(L::R_PHI + l) * nc + g];
+#pragma unroll
+    for (int qv = 0; qv < L::NV; ++qv) Vc[vb_i<3>(qv)][vb_j<3>(qv)] = W[(L::R_V + qv) * nc + g];
+    const int nx = I.n[0], ny = I.n[1];
+    const int x = (int)(g % nx);
+    const int64_t r = g / nx;
+    const int y = (int)(r % ny);
+    const int z = (int)(r / ny);
+    C acc[St::S];
+#pragma unroll
+    for (int f = 0; f < St::S; ++f) acc[f] = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      int64_t fm, fp;
+      if (a == 0) { fm = ((int64_t)z * ny + y) * (nx + 1) + x; fp = fm + 1; }
+      else if (a == 1) { fm = ((int64_t)z * (ny + 1) + y) * nx + x; fp = fm + nx; }
+      else { fm = g; fp = g + (int64_t)nx * ny; }
+      const int64_t nf = nfaces3(I, a);
+      typename St::FaceC m, p;
+      St::template face_contrib<int64_t>((const C*)I.Fb[a], fm, nf, a, 1, Xc, Vc, uc, m);
+      St::template face_contrib<int64_t>((const C*)I.Fb[a], fp, nf, a, 0, Xc, Vc, uc, p);
+      St::gather_dir(cx, a, m, p, Xc, uc, phic, Vc, acc);
+    }
+    bool bad = false;
+    cflv = St::finish_cell(cx, g, acc, &bad);
+    if (bad) atomicOr(reinterpret_cast<unsigned int*>(&I.dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);
+  }
+  if (cx.stage == 3 && go) block_max_to<256>(cflv, scratch, &I.dts[DTS_DTINV + 1 - q]);
+}
+
+// ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
 struct Ops {
-  int S = 0, NC = 0, NTOT = 0, TX = 0, TY = 0, NT = 0;
+  int S = 0, NC = 0, NTOT = 0, TX = 0, TY = 0, NT = 0, NW = 0, NQ = 0;
   size_t smem = 0;
   void (*stage)(fv_ctx*, int, int, hipStream_t) = nullptr;
   void (*p2c)(fv_ctx*, int, const double*) = nullptr;
@@ -279,24 +440,17 @@ struct fv_ctx {
 
 namespace fvk {
 
-template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
-Ops make_ops() {
-  using St = Stage<DIM, NM, NS, T, C, TX, TY>;
+// launchers shared by every tile shape: state conversions and the CFL
+// reduction of a state without a source step
+template <int DIM, int NM, int NS, class T, class C>
+void common_ops(Ops& o) {
   using L = Lay<DIM, NM, NS>;
-  Ops o;
   o.S = L::S;
   o.NC = L::NC;
+  o.NW = L::NW;
+  o.NQ = L::NQ;
   o.NTOT = NM + DIM + 1;
-  o.TX = TX;
-  o.TY = TY;
-  o.NT = TX * TY;
   o.elem = sizeof(T);
-  o.smem = St::smem_bytes();
-  o.stage = [](fv_ctx* c, int stage, int parity, hipStream_t s) {
-    hipLaunchKernelGGL((stage_kernel<DIM, NM, NS, T, C, TX, TY>), dim3(c->total_blocks),
-                       dim3(TX * TY), St::smem_bytes(), s, c->insts_d,
-                       c->block_inst_d, c->P, stage, parity);
-  };
   o.p2c = [](fv_ctx* c, int ii, const double* prim) {
     const int64_t n = c->insts[ii].ncell;
     hipLaunchKernelGGL((prim_to_cons_kernel<DIM, NM, NS, T>), dim3((unsigned)((n + 255) / 256)),
@@ -309,8 +463,52 @@ Ops make_ops() {
   };
   o.cfl = [](fv_ctx* c, int ii, int parity) {
     const int64_t n = c->insts[ii].ncell;
-    hipLaunchKernelGGL((cfl_kernel<DIM, NM, NS, T, C, TX, TY>), dim3((unsigned)((n + 255) / 256)),
+    hipLaunchKernelGGL((cfl_kernel<DIM, NM, NS, T, C, 1, 1>), dim3((unsigned)((n + 255) / 256)),
                        dim3(256), 0, c->stream, c->insts_d, ii, c->P, parity);
+  };
+}
+
+template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
+Ops make_ops() {
+  using St = Stage<DIM, NM, NS, T, C, TX, TY>;
+  Ops o;
+  common_ops<DIM, NM, NS, T, C>(o);
+  o.TX = TX;
+  o.TY = TY;
+  o.NT = TX * TY;
+  o.smem = St::smem_bytes();
+  o.stage = [](fv_ctx* c, int stage, int parity, hipStream_t s) {
+    hipLaunchKernelGGL((stage_kernel<DIM, NM, NS, T, C, TX, TY>), dim3(c->total_blocks),
+                       dim3(TX * TY), St::smem_bytes(), s, c->insts_d,
+                       c->block_inst_d, c->P, stage, parity);
+  };
+  return o;
+}
+
+// 3D kernel set: the three passes per stage, launched instance by instance
+// (block size 256; TX reports it, TY = 1)
+template <int NM, int NS, class T, class C>
+Ops make_ops3() {
+  Ops o;
+  common_ops<3, NM, NS, T, C>(o);
+  o.TX = 256;
+  o.TY = 1;
+  o.NT = 256;
+  o.smem = 0;
+  o.stage = [](fv_ctx* c, int stage, int parity, hipStream_t s) {
+    for (int ii = 0; ii < c->n_inst; ++ii) {
+      const Inst& I = c->insts[ii];
+      const unsigned nbc = (unsigned)((I.ncell + 255) / 256);
+      hipLaunchKernelGGL((prim3_kernel<NM, NS, T, C>), dim3(nbc), dim3(256), 0, s, c->insts_d, ii,
+                         c->P, stage, parity);
+      for (int a = 0; a < 3; ++a) {
+        const int64_t nf = I.ncell / I.n[a] * (I.n[a] + 1);
+        hipLaunchKernelGGL((face3_kernel<NM, NS, T, C>), dim3((unsigned)((nf + 255) / 256)),
+                           dim3(256), 0, s, c->insts_d, ii, c->P, stage, parity, a);
+      }
+      hipLaunchKernelGGL((finish3_kernel<NM, NS, T, C>), dim3(nbc), dim3(256), 0, s, c->insts_d,
+                         ii, c->P, stage, parity);
+    }
   };
   return o;
 }
@@ -331,6 +529,9 @@ hipError_t set_smem_attr() {
     vars.push_back(make_ops<D, M, S_, TT, CC, X, Y>());                    \
     if (set_attr && herr == hipSuccess) herr = set_smem_attr<D, M, S_, TT, CC, X, Y>(); \
   }
+
+#define FV_VAR3(M, S_, TT, CC)                                              \
+  { vars.push_back(make_ops3<M, S_, TT, CC>()); }
 
 // kernel sets of each translation unit: every tile shape compiled for a
 // (dimension, materials, solids) combination

@@ -33,6 +33,8 @@ struct Inst {
   void* U2;         // stage-2 result (workspace)
   const void* phi0; // perturbation field on the initial mesh
   double* bacc;     // outward boundary flux accumulators
+  void* Wb;         // 3D: primitives of every cell (workspace)
+  void* Fb[3];      // 3D: face data of each direction (workspace)
   double* dts;      // dt state, see DTS_* below
   int n[3];
   int tiles[3];
@@ -135,6 +137,14 @@ struct Stage {
     int gy = 0;
     if (DIM >= 2) gy = map_index(cx.by * TY + hy - 2, I.n[1], I.bc[1][0], I.bc[1][1]);
     const int64_t g = (int64_t)gy * I.n[0] + gx;
+    cell_prims<int>(cx, g, sm, TL::NCELL, tc);
+  }
+
+  // Primitive and derived values of cell g of the stage input, stored at
+  // W[v * wstride + tc] (an LDS tile, or a full-grid buffer in HBM).
+  template <class IDX>
+  FV_HD static void cell_prims(const Ctx& cx, int64_t g, C* sm, IDX wstride, IDX tc) {
+    const Inst& I = *cx.I;
     C U[S];
 #pragma unroll
     for (int f = 0; f < S; ++f) U[f] = (C)cx.src[(int64_t)f * I.ncell + g];
@@ -183,7 +193,7 @@ struct Stage {
 #pragma unroll
     for (int s = 0; s < NS; ++s)
       if (D[s] >= (C)crit_level(cx.P.mat[s])) crit = 1;
-    const int NCELL = TL::NCELL;
+    const IDX NCELL = wstride;
 #pragma unroll
     for (int l = 0; l < NM; ++l) {
       W[(L::R_PHI + l) * NCELL + tc] = phi[l];
@@ -303,12 +313,13 @@ struct Stage {
 
   // Face a of the tile: W pointers of the four stencil cells (cm, c0 | c1, c2)
   // and the face's position relative to the domain boundary.
-  FV_HD static void compute_face(const Ctx& cx, const C* sm, int a, int cm, int c0,
-                                 int c1, int c2, int gface, int fslot,
-                                 int bslot, C* fb) {
+  template <class IDX>
+  FV_HD static void compute_face(const Ctx& cx, const C* sm, IDX wstride, int a, IDX cm,
+                                 IDX c0, IDX c1, IDX c2, int gface, IDX fslot, IDX fstride,
+                                 int64_t bslot, C* fb) {
     const Inst& I = *cx.I;
     const Params& P = cx.P;
-    const int NCELL = TL::NCELL;
+    const IDX NCELL = wstride;
     const C* W = sm;
     C wl[L::NR], wr[L::NR];
 #pragma unroll
@@ -456,7 +467,7 @@ struct Stage {
       for (int q = 0; q < NC; ++q) acc[q] += (double)(w * cx.dt * (sgn * F[q]));
     }
     // store
-    const int NF = TL::NFACE;
+    const IDX NF = fstride;
 #pragma unroll
     for (int q = 0; q < NC; ++q) fb[(L::Q_F + q) * NF + fslot] = F[q];
     fb[L::Q_UF * NF + fslot] = uf;
@@ -523,10 +534,11 @@ struct Stage {
     C row[3];
   };
 
-  FV_HD static void face_contrib(const C* fb, int fslot, int a, int side,
+  template <class IDX>
+  FV_HD static void face_contrib(const C* fb, IDX fslot, IDX fstride, int a, int side,
                                  const C* Xc, const C Vc[3][3], const C* uc,
                                  FaceC& o) {
-    const int NF = TL::NFACE;
+    const IDX NF = fstride;
 #pragma unroll
     for (int q = 0; q < NC; ++q) o.F[q] = fb[(L::Q_F + q) * NF + fslot];
     const C os = fb[L::Q_OS * NF + fslot];
@@ -602,8 +614,16 @@ struct Stage {
     if (a == 0) { fm = ty * (TX + 1) + tx; fp = fm + 1; }
     else { fm = ty * TX + tx; fp = fm + TX; }
     FaceC m, p;
-    face_contrib(fb, fm, a, 1, Xc, Vc, uc, m);
-    face_contrib(fb, fp, a, 0, Xc, Vc, uc, p);
+    face_contrib<int>(fb, fm, TL::NFACE, a, 1, Xc, Vc, uc, m);
+    face_contrib<int>(fb, fp, TL::NFACE, a, 0, Xc, Vc, uc, p);
+    gather_dir(cx, a, m, p, Xc, uc, phic, Vc, acc);
+  }
+
+  // accumulate the divergence of direction a from its two faces (m: the
+  // lower face, p: the upper one) and the cell's own values
+  FV_HD static void gather_dir(const Ctx& cx, int a, const FaceC& m, const FaceC& p,
+                               const C* Xc, const C* uc, const C* phic,
+                               const C Vc[3][3], C* acc) {
     const C inv = (C)1 / (C)cx.I->dx[a];
     const C div = (p.vel - m.vel) * inv;
 #pragma unroll
