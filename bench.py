@@ -101,17 +101,17 @@ def _step_chunked(g, n, chunk):
 
 
 def run_gpu(cases, precision, steps, warmup, autotune=True, chunk=10,
-            keep_state=True):
+            keep_state=True, tile=None):
     """Time `steps` steps after `warmup` untimed ones (the autotuner runs
     before the warm-up); return the timing, the chosen tile, and the
     primitive states and conservation totals at the end."""
     import torch
     from paper_2210_04037_amd.solver import GpuSolver
     g = GpuSolver(cases, precision=precision, device="cuda:0",
-                  use_graph=chunk > 0)
+                  use_graph=chunk > 0, tile=tile)
     tot0, _ = g.totals()
-    tile, table = (None, None)
-    if autotune:
+    table = None
+    if autotune and tile is None:
         tile, table = g.autotune(reps=10)
     _step_chunked(g, warmup, chunk)
     torch.cuda.synchronize()
@@ -208,14 +208,18 @@ def main():
                          "per-field L1 error of FP32-bulk against FP64)")
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="ring", choices=["ring", "ensemble"],
+    ap.add_argument("--workload", default="ring",
+                    choices=["ring", "ensemble", "shell3d", "impact3d"],
                     help="ring: the 1024^2 expanding ring (default); "
                          "ensemble: seeded rings of uneven sizes in one "
-                         "context")
+                         "context; shell3d: the 256^3 expanding shell; "
+                         "impact3d: the 512^3 plate impact")
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--no-loop", action="store_true",
                     help="ensemble: skip timing the members one at a time")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tile", default=None,
+                    help="fixed tile 'TX,TY' (skips the autotuner)")
     ap.add_argument("--graph-chunk", type=int, default=10,
                     help="steps per captured graph (0: eager launches)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -236,16 +240,29 @@ def main():
         workload = (f"2D expanding ring {args.n}x{args.n} over a 60 mm "
                     "square: copper-like annulus 25-26.5 mm in gas, "
                     "150 m/s r/R, Gaussian phi0 (0.2 mm, 5%)")
-    else:
+    elif args.workload == "ensemble":
         cases = [F.make_case(4, member=m) for m in range(args.members)]
         workload = (f"ensemble of {args.members} seeded 2D expanding rings, "
                     "edges drawn from {256,384,512,768}, ring speeds "
                     "U(100, 250) m/s, one context (every member in each "
                     "launch)")
+    elif args.workload == "shell3d":
+        ne = args.n if args.n != 1024 else 256
+        cases = [F.make_case(3, n=ne)]
+        workload = (f"3D expanding cylindrical shell {ne}^3 over a 40 mm cube: "
+                    "copper-like shell r 15-16 mm, |z| <= 15 mm, 200 m/s "
+                    "radial, in gas; log-normal phi0 (0.3 mm, sigma 0.05)")
+    else:
+        ne = args.n if args.n != 1024 else 512
+        cases = [F.make_case(5, n=ne)]
+        workload = (f"3D plate impact {ne}^3 over a 20 mm cube: 4 mm "
+                    "copper-like flyer at 400 m/s on a 16 mm target with "
+                    "1000 spherical inclusions (phi0 0.7, r 0.1-0.3 mm)")
     ncell = sum(c.n_cells for c in cases)
     other = "fp64" if args.precision == "fp32" else "fp32"
+    tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
     r = run_gpu(cases, args.precision, args.steps, args.warmup,
-                autotune=not args.no_autotune, chunk=chunk)
+                autotune=not args.no_autotune, chunk=chunk, tile=tile)
     ms, S, elem = r["ms"], r["S"], r["elem"]
     cu_s = ncell * args.steps / (ms * 1e-3)
     launches = 3 * args.steps
@@ -281,7 +298,8 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "stage_kernel (3 launches per step)",
+            "kernel": ("stage_kernel (3 launches per step)" if cases[0].dim < 3
+                       else "3D stage: prim3 + 3 x face3 + finish3 per stage"),
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": avg_launch_s * 1e3,
         },

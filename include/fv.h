@@ -126,8 +126,8 @@ size_t fv_workspace_bytes(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
  * element type, read-only, Section 2.4).  workspace: device buffer of at
  * least fv_workspace_bytes.  stream: hipStream_t (NULL = default stream).
  * The states are not read here: load them with fv_load_primitive or write
- * conserved values and call fv_reset.  Errors: FV_EINVAL, FV_ENOMEM,
- * FV_EDEVICE. */
+ * conserved values and call fv_reset; until then fv_step, fv_cfl_dt and
+ * fv_autotune return FV_ESTATE.  Errors: FV_EINVAL, FV_ENOMEM, FV_EDEVICE. */
 int32_t fv_init(fv_ctx** out, int32_t n_inst, const fv_grid* grids,
                 int32_t n_mat, const fv_material* mats, const fv_options* opt,
                 void* const* state, const void* const* phi0, void* workspace,

@@ -298,6 +298,8 @@ size_t fv_workspace_bytes(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
   return W.total;
 }
 
+static int reset_inst(fv_ctx* c, int i, bool cfl);
+
 int32_t fv_init(fv_ctx** out, int32_t n_inst, const fv_grid* grids, int32_t n_mat,
                 const fv_material* mats, const fv_options* opt, void* const* state,
                 const void* const* phi0, void* workspace, size_t workspace_bytes,
@@ -383,12 +385,21 @@ int32_t fv_init(fv_ctx** out, int32_t n_inst, const fv_grid* grids, int32_t n_ma
     return rc;
   }
   c->h_dt.assign(n_inst * DTS_SIZE, 0.0);
+  c->loaded.assign(n_inst, 0);
+  for (int i = 0; i < n_inst && rc == FV_OK; ++i) rc = reset_inst(c, i, false);
+  if (rc == FV_OK) rc = hip_check(c, hipStreamSynchronize(c->stream), "init sync");
+  if (rc != FV_OK) {
+    g_init_error = c->err;
+    delete c;
+    return rc;
+  }
   *out = c;
-  // zero accumulators and dt state
-  return fv_reset(c) == FV_OK ? FV_OK : FV_EDEVICE;
+  return FV_OK;
 }
 
-static int reset_inst(fv_ctx* c, int i) {
+// zero accumulators and flag, time 0; with cfl, also the first CFL step of
+// the current state (a state that has not been written is never read)
+static int reset_inst(fv_ctx* c, int i, bool cfl) {
   const Inst& I = c->insts[i];
   const int q = (int)(c->step & 1);
   size_t nb = 0;
@@ -403,16 +414,26 @@ static int reset_inst(fv_ctx* c, int i) {
   h[DTS_TEND] = HUGE_VAL;
   rc = hip_check(c, hipMemcpyAsync(I.dts, h, DTS_SIZE * sizeof(double), hipMemcpyHostToDevice, c->stream),
                  "reset dt state");
-  if (rc != FV_OK) return rc;
+  if (rc != FV_OK || !cfl) return rc;
   c->ops.cfl(c, i, q);
   return hip_check(c, hipGetLastError(), "cfl kernel");
+}
+
+// every instance holds a written state
+static int check_loaded(fv_ctx* c) {
+  for (int i = 0; i < c->n_inst; ++i)
+    if (!c->loaded[i])
+      return fail(c, FV_ESTATE, "instance " + std::to_string(i) +
+                                    " has no state: call fv_load_primitive or fv_reset first");
+  return FV_OK;
 }
 
 int32_t fv_reset(fv_ctx* c) {
   if (!c) return FV_EINVAL;
   for (int i = 0; i < c->n_inst; ++i) {
-    const int rc = reset_inst(c, i);
+    const int rc = reset_inst(c, i, true);
     if (rc != FV_OK) return rc;
+    c->loaded[i] = 1;
   }
   return hip_check(c, hipStreamSynchronize(c->stream), "reset sync");
 }
@@ -423,8 +444,9 @@ int32_t fv_load_primitive(fv_ctx* c, int32_t inst, const void* prim) {
   c->ops.p2c(c, inst, (const double*)prim);
   int rc = hip_check(c, hipGetLastError(), "prim_to_cons kernel");
   if (rc != FV_OK) return rc;
-  rc = reset_inst(c, inst);
+  rc = reset_inst(c, inst, true);
   if (rc != FV_OK) return rc;
+  c->loaded[inst] = 1;
   return hip_check(c, hipStreamSynchronize(c->stream), "load sync");
 }
 
@@ -457,6 +479,7 @@ static int read_dts(fv_ctx* c, std::vector<double>& h) {
 
 int32_t fv_cfl_dt(fv_ctx* c, double* dt_host) {
   if (!c || !dt_host) return FV_EINVAL;
+  if (check_loaded(c) != FV_OK) return FV_ESTATE;
   std::vector<double> h;
   const int rc = read_dts(c, h);
   if (rc != FV_OK) return rc;
@@ -482,6 +505,7 @@ int32_t fv_time(fv_ctx* c, double* t_host) {
 int32_t fv_step(fv_ctx* c, const double* dt_host, int32_t n_steps, const double* t_end) {
   if (!c) return FV_EINVAL;
   if (n_steps < 0) return fail(c, FV_EINVAL, "n_steps < 0");
+  if (check_loaded(c) != FV_OK) return FV_ESTATE;
   if (dt_host || t_end) {
     // fixed step and end time of every instance (DTS_DTFIX, DTS_TEND)
     int rc = hip_check(c, hipStreamSynchronize(c->stream), "sync before parameter write");
@@ -562,6 +586,7 @@ int32_t fv_autotune(fv_ctx* c, int32_t reps, int32_t max_report, int32_t* tiles,
   if (!c) return FV_EINVAL;
   if (reps < 1 || max_report < 0 || (max_report > 0 && (!tiles || !ms)))
     return fail(c, FV_EINVAL, "reps < 1 or null report arrays");
+  if (check_loaded(c) != FV_OK) return FV_ESTATE;
   const int nv = (int)c->vars.size();
   if (n_variants) *n_variants = nv;
   hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -289,9 +289,13 @@ __global__ void __launch_bounds__(256) prim3_kernel(const Inst* insts, int ii, P
   St::template cell_prims<int64_t>(cx, g, (C*)I.Wb, I.ncell, g);
 }
 
-template <int NM, int NS, class T, class C>
+// the direction is a template argument: every per-direction index in the
+// face computation is then a constant (a runtime direction would put those
+// arrays in scratch memory)
+template <int NM, int NS, class T, class C, int A>
 __global__ void __launch_bounds__(256) face3_kernel(const Inst* insts, int ii, Params P,
-                                                    int stage, int parity, int a) {
+                                                    int stage, int parity) {
+  constexpr int a = A;
   using St = Stage<3, NM, NS, T, C, 1, 1>;
   const Inst& I = insts[ii];
   typename St::Ctx cx;
@@ -302,13 +306,13 @@ __global__ void __launch_bounds__(256) face3_kernel(const Inst* insts, int ii, P
   if (f >= nf) return;
   const int nx = I.n[0], ny = I.n[1];
   int c[3], i;
-  if (a == 0) {
+  if constexpr (a == 0) {
     i = (int)(f % (nx + 1));
     const int64_t r = f / (nx + 1);
     c[1] = (int)(r % ny);
     c[2] = (int)(r / ny);
     c[0] = 0;
-  } else if (a == 1) {
+  } else if constexpr (a == 1) {
     c[0] = (int)(f % nx);
     const int64_t r = f / nx;
     i = (int)(r % (ny + 1));
@@ -435,6 +439,7 @@ struct fv_ctx {
   int gkey[NGRAPH] = {};              // 2 * n_steps + parity, 0 = empty
   int gnext = 0;                      // slot replaced next
   std::vector<double> h_dt, h_tend;   // staging for async copies
+  std::vector<char> loaded;           // state written (load_primitive / reset)
   std::string err;
 };
 
@@ -501,11 +506,15 @@ Ops make_ops3() {
       const unsigned nbc = (unsigned)((I.ncell + 255) / 256);
       hipLaunchKernelGGL((prim3_kernel<NM, NS, T, C>), dim3(nbc), dim3(256), 0, s, c->insts_d, ii,
                          c->P, stage, parity);
-      for (int a = 0; a < 3; ++a) {
-        const int64_t nf = I.ncell / I.n[a] * (I.n[a] + 1);
-        hipLaunchKernelGGL((face3_kernel<NM, NS, T, C>), dim3((unsigned)((nf + 255) / 256)),
-                           dim3(256), 0, s, c->insts_d, ii, c->P, stage, parity, a);
-      }
+      const int64_t nf0 = I.ncell / I.n[0] * (I.n[0] + 1);
+      const int64_t nf1 = I.ncell / I.n[1] * (I.n[1] + 1);
+      const int64_t nf2 = I.ncell / I.n[2] * (I.n[2] + 1);
+      hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 0>), dim3((unsigned)((nf0 + 255) / 256)),
+                         dim3(256), 0, s, c->insts_d, ii, c->P, stage, parity);
+      hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 1>), dim3((unsigned)((nf1 + 255) / 256)),
+                         dim3(256), 0, s, c->insts_d, ii, c->P, stage, parity);
+      hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 2>), dim3((unsigned)((nf2 + 255) / 256)),
+                         dim3(256), 0, s, c->insts_d, ii, c->P, stage, parity);
       hipLaunchKernelGGL((finish3_kernel<NM, NS, T, C>), dim3(nbc), dim3(256), 0, s, c->insts_d,
                          ii, c->P, stage, parity);
     }

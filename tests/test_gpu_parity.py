@@ -270,3 +270,27 @@ def test_full_size_ring_long_run_stays_physical(precision):
     print(f"[long] median eps {np.median(eps):.4f} critical cells "
           f"{crit.sum()} of {solid.sum()}", flush=True)
     assert crit.mean() < 0.01
+
+
+def test_unloaded_state_is_a_call_order_error():
+    """fv_init does not read the state buffers; stepping before a state is
+    loaded (or written and reset) is refused, after fv_reset it works."""
+    import torch
+    from paper_2210_04037_amd import abi
+    case = F.make_case(2, n=48)
+    g = _gpu(case, load=False)
+    with pytest.raises(abi.FvError) as ei:
+        g.step(1)
+    assert ei.value.code == abi.FV_ESTATE
+    with pytest.raises(abi.FvError) as ei:
+        g.cfl_dt()
+    assert ei.value.code == abi.FV_ESTATE
+    ref = _gpu(case)
+    g.states[0].copy_(ref.states[0])
+    torch.cuda.synchronize()
+    g.reset()
+    g.step(3)
+    ref.step(3)
+    assert np.array_equal(g.state(0), ref.state(0))
+    g.close()
+    ref.close()
