@@ -65,6 +65,12 @@ def load(path=LIB_PATH):
         raise FileNotFoundError(
             f"{path} is missing: build it with "
             "`python -m paper_2210_04037_amd.build` (no CPU fallback exists)")
+    try:
+        # one HIP runtime per process: a ROCm build of torch brings its own,
+        # which must be the one libfv binds to when both are used
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     P = ctypes.POINTER

@@ -65,9 +65,9 @@ struct MatP {
   double rho0, K0, alpha, G0, beta, Gamma0;
   double yield, Dcrit, D0, eps_th, eps_c, balpha, nhard, pgate;
   // host-derived constants
-  double Dcrit_eff;    // D_crit (1 - 1e-9): critical test up to the rounding of
-                       // the advected ratio (phi rho D)/(phi rho), FP64 state
-  double Dcrit_eff32;  // D_crit (1 - 1e-6): the same for an FP32 state
+  double Dcrit_eff;    // D_crit (1 - 1e-6): critical test up to the rounding of
+                       // the advected ratio (phi rho D)/(phi rho) in FP32
+                       // storage, the same in both precision forms
   double invGamma;   // 1 / Gamma0
   double nu;         // Poisson ratio of the undamaged moduli
   double bonA;       // alpha_B (Dc - D0)^(1/alpha_B) / ln(eps_c / eps_th)

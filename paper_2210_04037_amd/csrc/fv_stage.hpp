@@ -93,11 +93,10 @@ struct Stage {
     T* out;         // stage output
   };
 
-  // critical-damage level for the stored precision (the advected ratio
-  // (phi rho D)/(phi rho) returns D_crit only to the storage rounding)
-  FV_HD static double crit_level(const MatP& m) {
-    return sizeof(T) == 8 ? m.Dcrit_eff : m.Dcrit_eff32;
-  }
+  // critical-damage level: the advected ratio (phi rho D)/(phi rho)
+  // returns D_crit only to the storage rounding; one level for both
+  // precision forms, so that they take this discontinuous decision alike
+  FV_HD static double crit_level(const MatP& m) { return m.Dcrit_eff; }
 
   // FP64 island of the FP32-bulk policy: the mixture pressure inversion of a
   // cell holding a trace volume fraction, with the phasic masses, energy and

@@ -60,7 +60,7 @@ def test_spall_1d_parity_through_fracture():
     g, o = _run_pair(case, 400)
     U = g.state(0)
     L = Layout(1, case.mats)
-    assert np.max(o.U[L.dmg[0]] / o.U[L.mass[0]]) >= 0.9 * (1 - 1e-9)
+    assert np.max(o.U[L.dmg[0]] / o.U[L.mass[0]]) >= 0.9 * (1 - 1e-6)
     err = _field_errors(U, o.U)
     assert err.max() < 1e-7, err
     # same cells opened to void
