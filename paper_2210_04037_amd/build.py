@@ -10,6 +10,11 @@ LIB = os.path.join(HERE, "libfv.so")
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
+    # multiply-adds fused per source expression: every inlined copy of a
+    # function rounds alike, so a value (a tile cell's primitives, a face
+    # flux computed by two neighbouring tiles) does not depend on which code
+    # path formed it
+    "-ffp-contract=on",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",

@@ -147,15 +147,28 @@ stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int 
   cx.src = stage == 1 ? U : (stage == 2 ? (const T*)I.U1 : (const T*)I.U2);
   cx.out = stage == 1 ? (T*)I.U1 : (stage == 2 ? (T*)I.U2 : (T*)I.U);
 
-  for (int tc = tid; tc < TL::NCELL; tc += NT) St::load_cell(cx, sm, tc);
-  __syncthreads();
-
-  C acc[St::S];
-#pragma unroll
-  for (int f = 0; f < St::S; ++f) acc[f] = 0;
+  // Every global load of the thread goes out at once: its own cell's stage
+  // input (kept for the update), the cell's U^n (stages 2 and 3) and its
+  // first halo cell; the primitives are formed after they arrive.
+  constexpr int S = St::S;
+  const int tcA = TL::own(tid);
+  C UA[S], UN[S], UH[S];
+  St::load_state(cx, cx.src, St::tile_global(cx, tcA), UA);
   int tx, ty;
   int64_t g = 0;
   const bool own = St::own_cell(cx, tid, tx, ty, g);
+  if (stage != 1 && own) St::load_state(cx, cx.base, g, UN);
+  const bool has_h = tid < TL::NHALO;
+  const int tcH = has_h ? TL::halo_cell(tid) : 0;
+  if (has_h) St::load_state(cx, cx.src, St::tile_global(cx, tcH), UH);
+  St::template prims_of<int>(cx, UA, sm, TL::NCELL, tcA);
+  if (has_h) St::template prims_of<int>(cx, UH, sm, TL::NCELL, tcH);
+  for (int h = tid + NT; h < TL::NHALO; h += NT) St::load_cell(cx, sm, TL::halo_cell(h));
+  __syncthreads();
+
+  C acc[S];
+#pragma unroll
+  for (int f = 0; f < S; ++f) acc[f] = 0;
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     const int nit = St::face_items(a);
@@ -171,7 +184,7 @@ stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int 
   double cflv = 0.0;
   if (own) {
     bool bad = false;
-    cflv = St::finish_cell(cx, g, acc, &bad);
+    cflv = St::finish_cell(cx, g, acc, UA, UN, &bad);
     if (bad) atomicOr(reinterpret_cast<unsigned int*>(&dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);
   }
   if (stage == 3) block_max_to<NT>(cflv, reinterpret_cast<double*>(smem_d), &dts[DTS_DTINV + 1 - q]);

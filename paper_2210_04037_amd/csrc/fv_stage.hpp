@@ -62,7 +62,22 @@ struct Tile {
   static constexpr int NFX = (TX + 1) * TY;
   static constexpr int NFY = DIM >= 2 ? TX * (TY + 1) : 0;
   static constexpr int NFACE = NFX > NFY ? NFX : NFY;
+  // halo ring: tile cells outside the TX x TY interior
+  static constexpr int NHALO = NCELL - NT;
   FV_HD static int cell(int hx, int hy) { return hy * HX + hx; }
+  // tile cell of halo index h (rows below and above the interior first, then
+  // the two columns on each side of every interior row)
+  FV_HD static int halo_cell(int h) {
+    if (DIM == 1) return h < 2 ? h : TX + h;
+    if (h < 2 * HX) return h;
+    if (h < 4 * HX) return cell(h % HX, TY + 2 + (h - 2 * HX) / HX);
+    const int r = h - 4 * HX, c = r % 4;
+    return cell(c < 2 ? c : TX + c, 2 + r / 4);
+  }
+  // tile cell of the interior cell owned by thread tid
+  FV_HD static int own(int tid) {
+    return DIM >= 2 ? cell(tid % TX + 2, tid / TX + 2) : tid + 2;
+  }
 };
 
 template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
@@ -128,25 +143,39 @@ struct Stage {
   }
 
   // ---------------------------------------------------------------- phase 1
-  FV_HD static void load_cell(const Ctx& cx, C* sm, int tc) {
+  // global cell of tile cell tc (ghost cells mapped by the boundary kind)
+  FV_HD static int64_t tile_global(const Ctx& cx, int tc) {
     const Inst& I = *cx.I;
     const int hx = tc % TL::HX;
     const int hy = tc / TL::HX;
     const int gx = map_index(cx.bx * TX + hx - 2, I.n[0], I.bc[0][0], I.bc[0][1]);
     int gy = 0;
     if (DIM >= 2) gy = map_index(cx.by * TY + hy - 2, I.n[1], I.bc[1][0], I.bc[1][1]);
-    const int64_t g = (int64_t)gy * I.n[0] + gx;
-    cell_prims<int>(cx, g, sm, TL::NCELL, tc);
+    return (int64_t)gy * I.n[0] + gx;
+  }
+
+  FV_HD static void load_state(const Ctx& cx, const T* src, int64_t g, C* U) {
+    const Inst& I = *cx.I;
+#pragma unroll
+    for (int f = 0; f < S; ++f) U[f] = (C)src[(int64_t)f * I.ncell + g];
+  }
+
+  FV_HD static void load_cell(const Ctx& cx, C* sm, int tc) {
+    cell_prims<int>(cx, tile_global(cx, tc), sm, TL::NCELL, tc);
   }
 
   // Primitive and derived values of cell g of the stage input, stored at
   // W[v * wstride + tc] (an LDS tile, or a full-grid buffer in HBM).
   template <class IDX>
   FV_HD static void cell_prims(const Ctx& cx, int64_t g, C* sm, IDX wstride, IDX tc) {
-    const Inst& I = *cx.I;
     C U[S];
-#pragma unroll
-    for (int f = 0; f < S; ++f) U[f] = (C)cx.src[(int64_t)f * I.ncell + g];
+    load_state(cx, cx.src, g, U);
+    prims_of<IDX>(cx, U, sm, wstride, tc);
+  }
+
+  // the same from the cell's stage-input values already in registers
+  template <class IDX>
+  FV_HD static void prims_of(const Ctx& cx, const C* U, C* sm, IDX wstride, IDX tc) {
     C* W = sm;
     C phi[NM], rho_l[NM], mass[NM], D[NS > 0 ? NS : 1], eps[NS > 0 ? NS : 1];
     C rho = 0;
@@ -832,18 +861,25 @@ struct Stage {
   // Returns the CFL sum (stage 3) or 0, and sets *bad for a non-physical
   // state.
   FV_HD static double finish_cell(const Ctx& cx, int64_t g, const C* acc, bool* bad) {
+    C us[S], ub[S];
+    load_state(cx, cx.src, g, us);
+    if (cx.stage != 1) load_state(cx, cx.base, g, ub);
+    return finish_cell(cx, g, acc, us, ub, bad);
+  }
+
+  // us: the cell's stage input, ub: its U^n (stages 2 and 3)
+  FV_HD static double finish_cell(const Ctx& cx, int64_t g, const C* acc, const C* us,
+                                  const C* ub, bool* bad) {
     const Inst& I = *cx.I;
     double Un[S];
 #pragma unroll
     for (int f = 0; f < S; ++f) {
-      const C us = (C)cx.src[(int64_t)f * I.ncell + g];
-      const C v = us + cx.dt * acc[f];
+      const C v = us[f] + cx.dt * acc[f];
       C o;
       if (cx.stage == 1) {
         o = v;
       } else {
-        const C ub = (C)cx.base[(int64_t)f * I.ncell + g];
-        o = cx.stage == 2 ? (C)0.75 * ub + (C)0.25 * v : ub / (C)3 + (C)(2.0 / 3.0) * v;
+        o = cx.stage == 2 ? (C)0.75 * ub[f] + (C)0.25 * v : ub[f] / (C)3 + (C)(2.0 / 3.0) * v;
       }
       Un[f] = (double)o;
     }
