@@ -90,6 +90,16 @@ __global__ void __launch_bounds__(256) exact_sum_kernel(const T* data, int64_t n
     if (bins[k]) atomicAdd(&out[k], bins[k]);
 }
 
+// Blocks are dispatched round-robin over the 8 XCDs, each with its own L2:
+// this renumbering gives every XCD one contiguous run of block numbers, so
+// neighbouring work (tiles sharing halos, bricks sharing stencil planes)
+// meets in one L2.
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t nb = gridDim.x;
+  const int64_t xcd = blockIdx.x & 7, qb = nb >> 3, rb = nb & 7;
+  return xcd * qb + (xcd < rb ? xcd : rb) + (blockIdx.x >> 3);
+}
+
 // ---------------------------------------------------------------------------
 // stage kernel
 // ---------------------------------------------------------------------------
@@ -102,12 +112,7 @@ stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int 
   extern __shared__ double smem_d[];
   C* sm = reinterpret_cast<C*>(smem_d);
   C* fb = sm + (size_t)St::NW * TL::NCELL;
-  // Blocks are dispatched round-robin over the 8 XCDs, each with its own L2:
-  // renumber so that every XCD works through one contiguous run of tiles
-  // (rows of neighbouring tiles share their halos in that XCD's L2).
-  const int nb = gridDim.x;
-  const int xcd = blockIdx.x & 7, qb = nb >> 3, rb = nb & 7;
-  const int b = xcd * qb + (xcd < rb ? xcd : rb) + (blockIdx.x >> 3);
+  const int b = (int)xcd_block();
   const int ii = block_inst[b];
   const Inst& I = insts[ii];
   double* dts = I.dts;
@@ -289,6 +294,29 @@ __device__ __forceinline__ int64_t nfaces3(const Inst& I, int a) {
   return I.ncell / I.n[a] * (I.n[a] + 1);
 }
 
+// Brick traversal of the y- and z-face passes: a block of 256 threads covers
+// 64 faces along x by 4 along the other transverse direction, and consecutive
+// block numbers step along the face direction first, so the cell planes a
+// brick's stencil reaches are still in the XCD's L2 for the next block (a
+// 256^2 plane of primitives is larger than one XCD's L2).
+constexpr int BRX = 64, BRY = 4;
+__host__ __device__ inline int64_t brick_blocks(int n_t, int n_u, int n_s) {
+  // n_t: cells along x, n_u: along the other transverse direction,
+  // n_s: positions along the stepping direction
+  return (int64_t)((n_t + BRX - 1) / BRX) * ((n_u + BRY - 1) / BRY) * n_s;
+}
+// position of thread tid of brick block b: x, transverse u, step s;
+// false past the domain
+__device__ __forceinline__ bool brick_pos(int64_t b, int n_t, int n_u, int n_s, int& x, int& u,
+                                          int& s) {
+  s = (int)(b % n_s);
+  const int64_t br = b / n_s;
+  const int nbx = (n_t + BRX - 1) / BRX;
+  x = (int)(br % nbx) * BRX + (int)(threadIdx.x % BRX);
+  u = (int)(br / nbx) * BRY + (int)(threadIdx.x / BRX);
+  return x < n_t && u < n_u;
+}
+
 template <int NM, int NS, class T, class C>
 __global__ void __launch_bounds__(256) prim3_kernel(const Inst* insts, int ii, Params P,
                                                     int stage, int parity) {
@@ -297,7 +325,7 @@ __global__ void __launch_bounds__(256) prim3_kernel(const Inst* insts, int ii, P
   typename St::Ctx cx;
   double t, dtinv, dt;
   if (!setup3<St, T, C>(I, P, stage, parity, cx, t, dtinv, dt)) return;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = xcd_block() * blockDim.x + threadIdx.x;
   if (g >= I.ncell) return;
   St::template cell_prims<int64_t>(cx, g, (C*)I.Wb, I.ncell, g);
 }
@@ -314,29 +342,29 @@ __global__ void __launch_bounds__(256) face3_kernel(const Inst* insts, int ii, P
   typename St::Ctx cx;
   double t, dtinv, dt;
   if (!setup3<St, T, C>(I, P, stage, parity, cx, t, dtinv, dt)) return;
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nf = nfaces3(I, a);
-  if (f >= nf) return;
-  const int nx = I.n[0], ny = I.n[1];
+  const int nx = I.n[0], ny = I.n[1], nz = I.n[2];
   int c[3], i;
+  int64_t f;
   if constexpr (a == 0) {
+    // x-faces: rows of consecutive faces
+    f = xcd_block() * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
     i = (int)(f % (nx + 1));
     const int64_t r = f / (nx + 1);
     c[1] = (int)(r % ny);
     c[2] = (int)(r / ny);
     c[0] = 0;
   } else if constexpr (a == 1) {
-    c[0] = (int)(f % nx);
-    const int64_t r = f / nx;
-    i = (int)(r % (ny + 1));
-    c[2] = (int)(r / (ny + 1));
+    // y-faces: bricks over (x, z), stepping along y
+    if (!brick_pos(xcd_block(), nx, nz, ny + 1, c[0], c[2], i)) return;
     c[1] = 0;
+    f = ((int64_t)c[2] * (ny + 1) + i) * nx + c[0];
   } else {
-    c[0] = (int)(f % nx);
-    const int64_t r = f / nx;
-    c[1] = (int)(r % ny);
-    i = (int)(r / ny);
+    // z-faces: bricks over (x, y), stepping along z
+    if (!brick_pos(xcd_block(), nx, ny, nz + 1, c[0], c[1], i)) return;
     c[2] = 0;
+    f = ((int64_t)i * ny + c[1]) * nx + c[0];
   }
   // the face lies between cells i - 1 and i along a; stencil i - 2 .. i + 1
   int64_t st[4];
@@ -519,15 +547,16 @@ Ops make_ops3() {
       const unsigned nbc = (unsigned)((I.ncell + 255) / 256);
       hipLaunchKernelGGL((prim3_kernel<NM, NS, T, C>), dim3(nbc), dim3(256), 0, s, c->insts_d, ii,
                          c->P, stage, parity);
-      const int64_t nf0 = I.ncell / I.n[0] * (I.n[0] + 1);
-      const int64_t nf1 = I.ncell / I.n[1] * (I.n[1] + 1);
-      const int64_t nf2 = I.ncell / I.n[2] * (I.n[2] + 1);
+      const int nx = I.n[0], ny = I.n[1], nz = I.n[2];
+      const int64_t nf0 = I.ncell / nx * (nx + 1);
       hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 0>), dim3((unsigned)((nf0 + 255) / 256)),
                          dim3(256), 0, s, c->insts_d, ii, c->P, stage, parity);
-      hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 1>), dim3((unsigned)((nf1 + 255) / 256)),
-                         dim3(256), 0, s, c->insts_d, ii, c->P, stage, parity);
-      hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 2>), dim3((unsigned)((nf2 + 255) / 256)),
-                         dim3(256), 0, s, c->insts_d, ii, c->P, stage, parity);
+      hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 1>),
+                         dim3((unsigned)brick_blocks(nx, nz, ny + 1)), dim3(256), 0, s,
+                         c->insts_d, ii, c->P, stage, parity);
+      hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 2>),
+                         dim3((unsigned)brick_blocks(nx, ny, nz + 1)), dim3(256), 0, s,
+                         c->insts_d, ii, c->P, stage, parity);
       hipLaunchKernelGGL((finish3_kernel<NM, NS, T, C>), dim3(nbc), dim3(256), 0, s, c->insts_d,
                          ii, c->P, stage, parity);
     }

@@ -737,7 +737,26 @@ struct Stage {
 #pragma unroll
     for (int q = 0; q < L::NV; ++q) V[vb_i<DIM>(q)][vb_j<DIM>(q)] = U[L::VB + q];
     double H[3][3];
-    hencky<DIM, double>(V, H);
+    // 3D: the eigen-decomposition of V V^T is kept, so that the return (a
+    // scaling of dev H) rebuilds the stretch from the same eigenvectors
+    double Qe[3][3], he[3];
+    if constexpr (DIM == 3) {
+      double B[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          B[i][j] = V[i][0] * V[j][0] + V[i][1] * V[j][1] + V[i][2] * V[j][2];
+      sym3_eig(B, Qe);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) he[k] = 0.5 * log(B[k][k]);
+      const double mm = (he[0] + he[1] + he[2]) / 3.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) he[k] -= mm;
+      sym3_compose(Qe, he, H);
+    } else {
+      hencky<DIM, double>(V, H);
+    }
     const double J2 = J2_of<DIM, double>(H);
     Mix<NM, NS, double> mx;
     mix_terms<NM, NS, double>(P, phi, rho_l, D, J2, mx);
@@ -757,7 +776,7 @@ struct Stage {
       Ymix += phi[s] * w * sy;
     }
     const double Jmax = Gm > 0.0 ? Ymix / (sqrt(6.0) * Gm) : 0.0;
-    const double J = sqrt(J2);
+    const double J = DIM == 3 ? sqrt(he[0] * he[0] + he[1] * he[1] + he[2] * he[2]) : sqrt(J2);
     double scale = 1.0, deps = 0.0;
     if (J > Jmax) { scale = Jmax / J; deps = sqrt(2.0 / 3.0) * (J - Jmax); }
 #pragma unroll
@@ -765,7 +784,14 @@ struct Stage {
 #pragma unroll
       for (int j = 0; j < 3; ++j) H[i][j] *= scale;
     double Vn[3][3];
-    stretch_from_log<DIM, double>(H, Vn);
+    if constexpr (DIM == 3) {
+      double e[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) e[k] = exp(scale * he[k]);
+      sym3_compose(Qe, e, Vn);
+    } else {
+      stretch_from_log<DIM, double>(H, Vn);
+    }
 #pragma unroll
     for (int q = 0; q < L::NV; ++q) U[L::VB + q] = Vn[vb_i<DIM>(q)][vb_j<DIM>(q)];
     double Dn[NS > 0 ? NS : 1];
@@ -844,7 +870,26 @@ struct Stage {
 #pragma unroll
     for (int q = 0; q < L::NV; ++q) V[vb_i<DIM>(q)][vb_j<DIM>(q)] = U[L::VB + q];
     double H[3][3];
-    hencky<DIM, double>(V, H);
+    // 3D: the eigen-decomposition of V V^T is kept, so that the return (a
+    // scaling of dev H) rebuilds the stretch from the same eigenvectors
+    double Qe[3][3], he[3];
+    if constexpr (DIM == 3) {
+      double B[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          B[i][j] = V[i][0] * V[j][0] + V[i][1] * V[j][1] + V[i][2] * V[j][2];
+      sym3_eig(B, Qe);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) he[k] = 0.5 * log(B[k][k]);
+      const double mm = (he[0] + he[1] + he[2]) / 3.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) he[k] -= mm;
+      sym3_compose(Qe, he, H);
+    } else {
+      hencky<DIM, double>(V, H);
+    }
     const double J2 = J2_of<DIM, double>(H);
     Mix<NM, NS, double> mx;
     mix_terms<NM, NS, double>(P, phi, rho_l, D, J2, mx);
@@ -958,7 +1003,26 @@ struct Cell {
     double V[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     for (int q = 0; q < L::NV; ++q) V[vb_i<DIM>(q)][vb_j<DIM>(q)] = U[L::VB + q];
     double H[3][3];
-    hencky<DIM, double>(V, H);
+    // 3D: the eigen-decomposition of V V^T is kept, so that the return (a
+    // scaling of dev H) rebuilds the stretch from the same eigenvectors
+    double Qe[3][3], he[3];
+    if constexpr (DIM == 3) {
+      double B[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          B[i][j] = V[i][0] * V[j][0] + V[i][1] * V[j][1] + V[i][2] * V[j][2];
+      sym3_eig(B, Qe);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) he[k] = 0.5 * log(B[k][k]);
+      const double mm = (he[0] + he[1] + he[2]) / 3.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) he[k] -= mm;
+      sym3_compose(Qe, he, H);
+    } else {
+      hencky<DIM, double>(V, H);
+    }
     const double J2 = J2_of<DIM, double>(H);
     Mix<NM, NS, double> mx;
     mix_terms<NM, NS, double>(P, phi, rho_l, D, J2, mx);
