@@ -181,6 +181,20 @@ int32_t fv_time(fv_ctx* ctx, double* t_host);
  * rounded sum of the same values.  Synchronises; FV_ENONPHYS if flagged. */
 int32_t fv_totals(fv_ctx* ctx, double* out);
 
+/* Checkpoint of the context's own state: the step count, each instance's
+ * time, CFL state, end time, fixed dt and flag, and its cumulative boundary
+ * outflow.  With copies of the state buffers this is a complete checkpoint: a
+ * context created with the same grids, materials and options whose state
+ * buffers hold the saved states and that calls fv_restore continues bit for
+ * bit.  fv_checkpoint_bytes: size of the blob (0 for a NULL ctx).
+ * fv_checkpoint: writes the blob to dst (device, caller-owned); synchronises;
+ * FV_ESTATE before a state is loaded.  fv_restore: reads it from src (device);
+ * synchronises; FV_EINVAL if the blob is not a checkpoint of a context with
+ * the same number of instances and cells. */
+size_t fv_checkpoint_bytes(const fv_ctx* ctx);
+int32_t fv_checkpoint(fv_ctx* ctx, void* dst);
+int32_t fv_restore(fv_ctx* ctx, const void* src);
+
 /* Autotuner: time every compiled tile shape of ctx's kernel set on reps
  * timing runs of the first RK stage over the current state (these leave the
  * state, time, dt and boundary accumulators unchanged; they overwrite only

@@ -15,7 +15,8 @@ PRECISIONS = {"fp64": FV_FP64, "fp32": FV_FP32_BULK}
 
 EXPORTS = ["fv_state_fields", "fv_workspace_bytes", "fv_init",
            "fv_load_primitive", "fv_reset", "fv_primitive", "fv_cfl_dt",
-           "fv_step", "fv_time", "fv_totals", "fv_autotune",
+           "fv_step", "fv_time", "fv_totals", "fv_checkpoint_bytes",
+           "fv_checkpoint", "fv_restore", "fv_autotune",
            "fv_fragment_workspace_bytes",
            "fv_fragments", "fv_last_error", "fv_destroy"]
 
@@ -89,6 +90,12 @@ def load(path=LIB_PATH):
     lib.fv_primitive.restype = i32
     lib.fv_cfl_dt.argtypes = [vp, P(dbl)]
     lib.fv_cfl_dt.restype = i32
+    lib.fv_checkpoint_bytes.argtypes = [vp]
+    lib.fv_checkpoint_bytes.restype = ctypes.c_size_t
+    lib.fv_checkpoint.argtypes = [vp, vp]
+    lib.fv_checkpoint.restype = i32
+    lib.fv_restore.argtypes = [vp, vp]
+    lib.fv_restore.restype = i32
     lib.fv_autotune.argtypes = [vp, i32, i32, P(i32), P(ctypes.c_float), P(i32), P(i32)]
     lib.fv_autotune.restype = i32
     lib.fv_fragment_workspace_bytes.argtypes = [vp, i32, ctypes.c_int64]

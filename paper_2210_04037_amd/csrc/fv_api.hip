@@ -501,6 +501,92 @@ int32_t fv_time(fv_ctx* c, double* t_host) {
   return FV_OK;
 }
 
+// ---------------------------------------------------------------------------
+// checkpoint / restore of the context's own state
+// ---------------------------------------------------------------------------
+namespace {
+constexpr double CK_MAGIC = 4.6e15;  // tag of a checkpoint blob
+
+size_t bacc_doubles(const fv_ctx* c, int i) {
+  const Inst& I = c->insts[i];
+  size_t nb = 0;
+  for (int a = 0; a < c->dim; ++a) nb += 2 * (size_t)(I.ncell / I.n[a]) * c->ops.NC;
+  return nb;
+}
+
+// header: magic, n_inst, step count, 0, then ncell of every instance;
+// then per instance its dt state and boundary accumulators
+size_t ck_doubles(const fv_ctx* c) {
+  size_t n = 4 + (size_t)c->n_inst;
+  for (int i = 0; i < c->n_inst; ++i) n += DTS_SIZE + bacc_doubles(c, i);
+  return n;
+}
+}  // namespace
+
+size_t fv_checkpoint_bytes(const fv_ctx* c) { return c ? ck_doubles(c) * sizeof(double) : 0; }
+
+int32_t fv_checkpoint(fv_ctx* c, void* dst) {
+  if (!c) return FV_EINVAL;
+  if (!dst) return fail(c, FV_EINVAL, "null checkpoint buffer");
+  if (check_loaded(c) != FV_OK) return FV_ESTATE;
+  c->h_ck.assign(4 + c->n_inst, 0.0);
+  c->h_ck[0] = CK_MAGIC;
+  c->h_ck[1] = c->n_inst;
+  c->h_ck[2] = (double)c->step;
+  for (int i = 0; i < c->n_inst; ++i) c->h_ck[4 + i] = (double)c->insts[i].ncell;
+  double* d = static_cast<double*>(dst);
+  int rc = hip_check(c, hipMemcpyAsync(d, c->h_ck.data(), sizeof(double) * c->h_ck.size(),
+                                       hipMemcpyHostToDevice, c->stream), "write checkpoint header");
+  size_t off = c->h_ck.size();
+  for (int i = 0; i < c->n_inst && rc == FV_OK; ++i) {
+    const Inst& I = c->insts[i];
+    rc = hip_check(c, hipMemcpyAsync(d + off, I.dts, sizeof(double) * DTS_SIZE,
+                                     hipMemcpyDeviceToDevice, c->stream), "save dt state");
+    off += DTS_SIZE;
+    const size_t nb = bacc_doubles(c, i);
+    if (rc == FV_OK && nb)
+      rc = hip_check(c, hipMemcpyAsync(d + off, I.bacc, sizeof(double) * nb, hipMemcpyDeviceToDevice,
+                                       c->stream), "save boundary accumulators");
+    off += nb;
+  }
+  // the header staging buffer must outlive the copy
+  if (rc == FV_OK) rc = hip_check(c, hipStreamSynchronize(c->stream), "checkpoint sync");
+  return rc;
+}
+
+int32_t fv_restore(fv_ctx* c, const void* src) {
+  if (!c) return FV_EINVAL;
+  if (!src) return fail(c, FV_EINVAL, "null checkpoint buffer");
+  const double* s = static_cast<const double*>(src);
+  std::vector<double> hdr(4 + c->n_inst);
+  int rc = hip_check(c, hipMemcpyAsync(hdr.data(), s, sizeof(double) * hdr.size(),
+                                       hipMemcpyDeviceToHost, c->stream), "read checkpoint header");
+  if (rc == FV_OK) rc = hip_check(c, hipStreamSynchronize(c->stream), "restore sync");
+  if (rc != FV_OK) return rc;
+  if (hdr[0] != CK_MAGIC || hdr[1] != c->n_inst)
+    return fail(c, FV_EINVAL, "not a checkpoint of a context with these instances");
+  for (int i = 0; i < c->n_inst; ++i)
+    if (hdr[4 + i] != (double)c->insts[i].ncell)
+      return fail(c, FV_EINVAL, "checkpoint grid of instance " + std::to_string(i) + " differs");
+  size_t off = hdr.size();
+  for (int i = 0; i < c->n_inst && rc == FV_OK; ++i) {
+    const Inst& I = c->insts[i];
+    rc = hip_check(c, hipMemcpyAsync(I.dts, s + off, sizeof(double) * DTS_SIZE,
+                                     hipMemcpyDeviceToDevice, c->stream), "restore dt state");
+    off += DTS_SIZE;
+    const size_t nb = bacc_doubles(c, i);
+    if (rc == FV_OK && nb)
+      rc = hip_check(c, hipMemcpyAsync(I.bacc, s + off, sizeof(double) * nb, hipMemcpyDeviceToDevice,
+                                       c->stream), "restore boundary accumulators");
+    off += nb;
+  }
+  if (rc == FV_OK) rc = hip_check(c, hipStreamSynchronize(c->stream), "restore sync");
+  if (rc != FV_OK) return rc;
+  c->step = (long long)hdr[2];
+  for (int i = 0; i < c->n_inst; ++i) c->loaded[i] = 1;
+  return FV_OK;
+}
+
 int32_t fv_step(fv_ctx* c, const double* dt_host, int32_t n_steps, const double* t_end) {
   if (!c) return FV_EINVAL;
   if (n_steps < 0) return fail(c, FV_EINVAL, "n_steps < 0");

@@ -481,6 +481,7 @@ struct fv_ctx {
   int gnext = 0;                      // slot replaced next
   std::vector<double> h_dt, h_tend;   // staging for async copies
   std::vector<char> loaded;           // state written (load_primitive / reset)
+  std::vector<double> h_ck;           // checkpoint header staging
   std::string err;
 };
 

@@ -117,6 +117,23 @@ class GpuSolver:
         self.torch.cuda.synchronize(self.device)
         return self.states[i].double().cpu().numpy()
 
+    def checkpoint(self):
+        """Copies of the state buffers and the context's own state (time,
+        CFL state, boundary outflow, step count), all on the device."""
+        n = self.lib.fv_checkpoint_bytes(self.ctx)
+        blob = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+        self._c(self.lib.fv_checkpoint(self.ctx, ctypes.c_void_p(blob.data_ptr())))
+        return [t.clone() for t in self.states], blob
+
+    def restore(self, ck):
+        """Continue from a checkpoint of a context with the same grids,
+        materials and options (bit for bit)."""
+        states, blob = ck
+        for t, s in zip(self.states, states):
+            t.copy_(s)
+        self.torch.cuda.synchronize(self.device)
+        self._c(self.lib.fv_restore(self.ctx, ctypes.c_void_p(blob.data_ptr())))
+
     def autotune(self, reps=20):
         """Time every compiled tile shape, keep the fastest; returns
         (chosen (tx, ty), {(tx, ty): ms per launch})."""
