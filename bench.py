@@ -40,6 +40,29 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def profile_value(key):
+    """A figure from the committed rocprofv3 summary, if it was taken on the
+    current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals[key]) if key in vals else None
+    except ValueError:
+        return None
+
+
+# VALU issue rate without packed FP32: 256 CUs x 4 SIMDs, one wave64
+# instruction per SIMD every 4 cycles at 2.4 GHz
+VALU_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
+
+
 def measured_traffic(precision):
     """HBM bytes per stage launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source; else None."""
@@ -132,6 +155,22 @@ def run_gpu(cases, precision, steps, warmup, autotune=True, chunk=10,
     g.close()
     return dict(ms=ms, S=S, elem=elem, t=t, W=W, tot0=tot0, tot1=tot1 + out1,
                 tile=tile, tiles_ms=table)
+
+
+def valu_report(args, r, avg_launch_s):
+    """Instruction-issue bound of the stage kernel (1024^2 ring, FP32-bulk,
+    64x8 tile, the configuration the counters were taken in): the VALU
+    wave-instructions one launch executes (rocprofv3 SQ_INSTS_VALU) at the
+    chip's issue rate, against the measured launch time."""
+    if args.workload != "ring" or args.precision != "fp32" or r["tile"] not in (None, (64, 8), [64, 8]):
+        return None
+    n = profile_value("SQ_INSTS_VALU")
+    if n is None:
+        return None
+    floor = n / VALU_WAVE_INSTR_PER_S
+    return {"wave_instructions_per_launch": n, "issue_floor_ms": floor * 1e3,
+            "measured_launch_ms": avg_launch_s * 1e3,
+            "frac": floor / avg_launch_s}
 
 
 def precision_report(cases, r32, r64):
@@ -303,6 +342,7 @@ def main():
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": avg_launch_s * 1e3,
         },
+        "valu": valu_report(args, r, avg_launch_s),
         "autotune_ms_per_stage1_launch": (
             {f"{k[0]}x{k[1]}": v for k, v in r["tiles_ms"].items()}
             if r["tiles_ms"] else None),

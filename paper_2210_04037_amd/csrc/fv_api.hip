@@ -1,8 +1,7 @@
-// libfv: kernels and the C ABI declared in include/fv.h.
-//
-// One HIP translation unit.  Templates are instantiated for the supported
-// (dimension, materials, precision) combinations; fv_init picks one set of
-// launchers and every later call goes through it.
+// libfv host API: the C ABI declared in include/fv.h (argument checks,
+// workspace plan, context set-up, stepping and step graphs, autotuner,
+// totals, fragments, checkpoints).  The kernel sets of the two precision
+// forms are compiled in fv_fp64.hip and fv_fp32.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -12,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "fv_kernels.hpp"
+#include "fv_launch.hpp"
 #include "fv_ccl.hpp"
 
 using namespace fv;

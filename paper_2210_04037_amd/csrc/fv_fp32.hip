@@ -3,7 +3,7 @@
 // inversion, plastic return, totals).  This translation unit is compiled
 // with fast reciprocals and approximate transcendental functions; the FP64
 // form (fv_fp64.hip) keeps IEEE division and library functions.
-#include "fv_kernels.hpp"
+#include "fv_launch.hpp"
 
 namespace fvk {
 

@@ -1,7 +1,7 @@
 // The plain FP64 form of the stage kernels (state and arithmetic in double,
 // IEEE division and library functions): the reference form the oracle
 // checks and the FP32-bulk form is measured against.
-#include "fv_kernels.hpp"
+#include "fv_launch.hpp"
 
 namespace fvk {
 

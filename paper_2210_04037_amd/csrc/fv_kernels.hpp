@@ -1,6 +1,6 @@
-// Kernels of libfv and their launchers, shared by the two translation units
-// (fv_api.hip: host API and the FP64 form; fv_fp32.hip: the FP32-bulk form,
-// compiled with fast reciprocal and approximate transcendental functions).
+// Device kernels of libfv: the stage kernel (1D, 2D), the three 3D passes,
+// state conversions, the CFL reduction and the exact sums.  Their launchers
+// and the host context are in fv_launch.hpp.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -440,156 +440,5 @@ __global__ void __launch_bounds__(256) finish3_kernel(const Inst* insts, int ii,
   }
   if (cx.stage == 3 && go) block_max_to<256>(cflv, scratch, &I.dts[DTS_DTINV + 1 - q]);
 }
-
-// ---------------------------------------------------------------------------
-// context
-// ---------------------------------------------------------------------------
-struct Ops {
-  int S = 0, NC = 0, NTOT = 0, TX = 0, TY = 0, NT = 0, NW = 0, NQ = 0;
-  size_t smem = 0;
-  void (*stage)(fv_ctx*, int, int, hipStream_t) = nullptr;
-  void (*p2c)(fv_ctx*, int, const double*) = nullptr;
-  void (*c2p)(fv_ctx*, int, double*) = nullptr;
-  void (*cfl)(fv_ctx*, int, int) = nullptr;
-  size_t elem = 8;
-};
-
-}  // namespace fvk
-
-// Context behind the opaque fv_ctx handle of the C ABI.
-struct fv_ctx {
-  int n_inst = 0, dim = 0, nm = 0, ns = 0, precision = 0;
-  fv::Params P{};
-  hipStream_t stream = nullptr;
-  std::vector<fv::Inst> insts;
-  fv::Inst* insts_d = nullptr;
-  int* block_inst_d = nullptr;
-  unsigned long long* bins_d = nullptr;
-  int total_blocks = 0;
-  long long step = 0;
-  fvk::Ops ops;                       // the selected tile shape
-  std::vector<fvk::Ops> vars;         // every compiled tile shape
-  int var = 0;
-  int max_blocks = 0;                 // capacity of the block table
-  std::vector<int> h_block_inst;
-  // captured multi-step graphs, keyed by (step count, starting parity)
-  static constexpr int NGRAPH = 4;
-  bool use_graph = false;
-  hipStream_t cap_stream = nullptr;
-  hipGraphExec_t gexec[NGRAPH] = {};
-  int gkey[NGRAPH] = {};              // 2 * n_steps + parity, 0 = empty
-  int gnext = 0;                      // slot replaced next
-  std::vector<double> h_dt, h_tend;   // staging for async copies
-  std::vector<char> loaded;           // state written (load_primitive / reset)
-  std::vector<double> h_ck;           // checkpoint header staging
-  std::string err;
-};
-
-namespace fvk {
-
-// launchers shared by every tile shape: state conversions and the CFL
-// reduction of a state without a source step
-template <int DIM, int NM, int NS, class T, class C>
-void common_ops(Ops& o) {
-  using L = Lay<DIM, NM, NS>;
-  o.S = L::S;
-  o.NC = L::NC;
-  o.NW = L::NW;
-  o.NQ = L::NQ;
-  o.NTOT = NM + DIM + 1;
-  o.elem = sizeof(T);
-  o.p2c = [](fv_ctx* c, int ii, const double* prim) {
-    const int64_t n = c->insts[ii].ncell;
-    hipLaunchKernelGGL((prim_to_cons_kernel<DIM, NM, NS, T>), dim3((unsigned)((n + 255) / 256)),
-                       dim3(256), 0, c->stream, c->insts_d, ii, c->P, prim);
-  };
-  o.c2p = [](fv_ctx* c, int ii, double* prim) {
-    const int64_t n = c->insts[ii].ncell;
-    hipLaunchKernelGGL((cons_to_prim_kernel<DIM, NM, NS, T>), dim3((unsigned)((n + 255) / 256)),
-                       dim3(256), 0, c->stream, c->insts_d, ii, c->P, prim);
-  };
-  o.cfl = [](fv_ctx* c, int ii, int parity) {
-    const int64_t n = c->insts[ii].ncell;
-    hipLaunchKernelGGL((cfl_kernel<DIM, NM, NS, T, C, 1, 1>), dim3((unsigned)((n + 255) / 256)),
-                       dim3(256), 0, c->stream, c->insts_d, ii, c->P, parity);
-  };
-}
-
-template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
-Ops make_ops() {
-  using St = Stage<DIM, NM, NS, T, C, TX, TY>;
-  Ops o;
-  common_ops<DIM, NM, NS, T, C>(o);
-  o.TX = TX;
-  o.TY = TY;
-  o.NT = TX * TY;
-  o.smem = St::smem_bytes();
-  o.stage = [](fv_ctx* c, int stage, int parity, hipStream_t s) {
-    hipLaunchKernelGGL((stage_kernel<DIM, NM, NS, T, C, TX, TY>), dim3(c->total_blocks),
-                       dim3(TX * TY), St::smem_bytes(), s, c->insts_d,
-                       c->block_inst_d, c->P, stage, parity);
-  };
-  return o;
-}
-
-// 3D kernel set: the three passes per stage, launched instance by instance
-// (block size 256; TX reports it, TY = 1)
-template <int NM, int NS, class T, class C>
-Ops make_ops3() {
-  Ops o;
-  common_ops<3, NM, NS, T, C>(o);
-  o.TX = 256;
-  o.TY = 1;
-  o.NT = 256;
-  o.smem = 0;
-  o.stage = [](fv_ctx* c, int stage, int parity, hipStream_t s) {
-    for (int ii = 0; ii < c->n_inst; ++ii) {
-      const Inst& I = c->insts[ii];
-      const unsigned nbc = (unsigned)((I.ncell + 255) / 256);
-      hipLaunchKernelGGL((prim3_kernel<NM, NS, T, C>), dim3(nbc), dim3(256), 0, s, c->insts_d, ii,
-                         c->P, stage, parity);
-      const int nx = I.n[0], ny = I.n[1], nz = I.n[2];
-      const int64_t nf0 = I.ncell / nx * (nx + 1);
-      hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 0>), dim3((unsigned)((nf0 + 255) / 256)),
-                         dim3(256), 0, s, c->insts_d, ii, c->P, stage, parity);
-      hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 1>),
-                         dim3((unsigned)brick_blocks(nx, nz, ny + 1)), dim3(256), 0, s,
-                         c->insts_d, ii, c->P, stage, parity);
-      hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 2>),
-                         dim3((unsigned)brick_blocks(nx, ny, nz + 1)), dim3(256), 0, s,
-                         c->insts_d, ii, c->P, stage, parity);
-      hipLaunchKernelGGL((finish3_kernel<NM, NS, T, C>), dim3(nbc), dim3(256), 0, s, c->insts_d,
-                         ii, c->P, stage, parity);
-    }
-  };
-  return o;
-}
-
-template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
-hipError_t set_smem_attr() {
-  using St = Stage<DIM, NM, NS, T, C, TX, TY>;
-  return hipFuncSetAttribute((const void*)&stage_kernel<DIM, NM, NS, T, C, TX, TY>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)St::smem_bytes());
-}
-
-// one compiled tile shape of a kernel set (the first one listed is the
-// default); set_attr also raises the kernel's dynamic LDS limit, a runtime
-// call that size-only queries skip
-#define FV_VAR(D, M, S_, TT, CC, X, Y)                                      \
-  {                                                                        \
-    vars.push_back(make_ops<D, M, S_, TT, CC, X, Y>());                    \
-    if (set_attr && herr == hipSuccess) herr = set_smem_attr<D, M, S_, TT, CC, X, Y>(); \
-  }
-
-#define FV_VAR3(M, S_, TT, CC)                                              \
-  { vars.push_back(make_ops3<M, S_, TT, CC>()); }
-
-// kernel sets of each translation unit: every tile shape compiled for a
-// (dimension, materials, solids) combination
-bool select_ops_fp64(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t& herr,
-                     bool set_attr);
-bool select_ops_fp32(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t& herr,
-                     bool set_attr);
 
 }  // namespace fvk
