@@ -268,8 +268,8 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is "
-              "not supported (the multi-GPU sharding is a design note only)",
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not "
+              "supported (sharding over several GPUs is not implemented)",
               file=sys.stderr)
         sys.exit(2)
     import fvinputs as F

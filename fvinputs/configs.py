@@ -3,9 +3,9 @@
 The five workloads follow the inert problems of the paper's validation
 section (plate-impact spallation, expanding ring, expanding shell), built on a
 copper-like solid whose constants are stated below.  Where the workloads leave
-a detail open the reading is the one recorded in the design notes (free
-surface ends for the plate impacts, gas at atmospheric pressure around rings
-and shells, gate pressure -1.5 GPa for plate impacts and 0 otherwise).
+a detail open these readings fill it: free-surface ends for the plate
+impacts, gas at atmospheric pressure around rings and shells, gate pressure
+-1.5 GPa for plate impacts and 0 otherwise.
 """
 from dataclasses import dataclass, field
 import numpy as np

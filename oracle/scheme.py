@@ -1,7 +1,7 @@
 """Hyperbolic update -- oracle, FP64, vectorised over cells and faces.
 
 The base finite-volume scheme is deferred by the paper to earlier work
-(Section 3, first paragraph).  Readings (each listed in the design notes):
+(Section 3, first paragraph).  Readings:
 
   * reconstruction: piecewise-linear MUSCL of the primitives
     (phi_l, rho_l, eps_p, D, u, p, dev H, Vbar) with the van Leer limiter,
@@ -25,8 +25,9 @@ The base finite-volume scheme is deferred by the paper to earlier work
     neighbour, otherwise void enters it; X and Vbar use each side's own
     centre values, so opening does not change them.  (The paper's modifier
     also separates material interfaces in tension; judged along the sweep
-    direction that cuts tensile solids along their surface, so it is left to
-    an interface-normal criterion, not built here.)
+    direction that would cut tensile solids along their surface, so this
+    rule does not open interfaces: that needs an interface-normal
+    criterion.)
   * free-surface boundaries behave like an opened face towards void; the
     material leaves through it when u* points outward.
   * time integration: SSP-RK3 (Shu-Osher) for all transported fields,
