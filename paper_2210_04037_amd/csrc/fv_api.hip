@@ -193,7 +193,11 @@ static void plan_ws(int32_t n_inst, const fv_grid* grids, const std::vector<Ops>
   }
   W.insts = off; off += align256(sizeof(Inst) * n_inst);
   W.block_inst = off; off += align256(sizeof(int) * W.max_blocks);
-  W.bins = off; off += align256(sizeof(unsigned long long) * NBINS * (size_t)n_inst * 2 * o.NTOT * 3);
+  // totals bins: per instance and total, the interior sum and one per
+  // boundary side (2 per direction)
+  W.bins = off;
+  off += align256(sizeof(unsigned long long) * NBINS * (size_t)n_inst * o.NTOT *
+                  (1 + 2 * (size_t)grids[0].dim));
   W.total = off;
 }
 
@@ -676,7 +680,8 @@ int32_t fv_autotune(fv_ctx* c, int32_t reps, int32_t max_report, int32_t* tiles,
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = hip_check(c, hipEventCreate(&e0), "event");
   if (rc == FV_OK) rc = hip_check(c, hipEventCreate(&e1), "event");
-  int best = c->var;
+  const int orig = c->var;
+  int best = orig;
   float best_ms = 0.0f;
   const int parity = (int)(c->step & 1);
   for (int v = 0; v < nv && rc == FV_OK; ++v) {
@@ -704,7 +709,7 @@ int32_t fv_autotune(fv_ctx* c, int32_t reps, int32_t max_report, int32_t* tiles,
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  const int rc2 = set_tiles(c, rc == FV_OK ? best : c->var);
+  const int rc2 = set_tiles(c, rc == FV_OK ? best : orig);
   if (rc != FV_OK) return rc;
   if (chosen) *chosen = best;
   return rc2;
