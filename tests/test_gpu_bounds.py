@@ -1,7 +1,8 @@
 """No entry point writes outside the buffers it is given: the workspace and
 every state buffer are followed by canary bytes, and after loading,
-stepping (eager and graph), the autotuner, totals, a checkpoint and a
-restore, in 1D, 2D, 3D and an ensemble, every canary byte is unchanged."""
+stepping (eager and graph), the autotuner, totals, a checkpoint, a restore
+and fragment labelling, in 1D, 2D, 3D and an ensemble, every canary byte is
+unchanged."""
 import ctypes
 
 import numpy as np
@@ -64,12 +65,27 @@ def _run(cases, precision):
     ok(lib.fv_step(ctx, None, 2, None))
     dts = (ctypes.c_double * n)()
     ok(lib.fv_cfl_dt(ctx, dts))
+    frag = []
+    for i, c in enumerate(cases):
+        ncell = int(np.prod(c.n))
+        cap = ncell // 2 + 1
+        fb = lib.fv_fragment_workspace_bytes(ctx, i, cap)
+        fws = torch.full((fb + PAD,), CANARY, dtype=torch.uint8, device=dev)
+        lab = torch.full((ncell * 4 + PAD,), CANARY, dtype=torch.uint8, device=dev)
+        res = (abi.FvFragment * cap)()
+        nf = ctypes.c_int64()
+        ok(lib.fv_fragments(ctx, i, 0.5, ctypes.c_void_p(lab.data_ptr()),
+                            ctypes.c_void_p(fws.data_ptr()), fb, cap, ctypes.byref(nf), res))
+        frag.append((fws, fb, lab, ncell * 4))
     lib.fv_destroy(ctx)
     torch.cuda.synchronize()
     assert bool((ws[nbytes:] == CANARY).all()), "workspace overrun"
     assert bool((ck[ck_n:] == CANARY).all()), "checkpoint overrun"
     for i, (b, used) in enumerate(raw):
         assert bool((b[used:] == CANARY).all()), f"state {i} overrun"
+    for i, (fws, fb, lab, lb) in enumerate(frag):
+        assert bool((fws[fb:] == CANARY).all()), f"fragment workspace {i} overrun"
+        assert bool((lab[lb:] == CANARY).all()), f"labels {i} overrun"
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
