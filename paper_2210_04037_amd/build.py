@@ -30,11 +30,17 @@ def hipcc():
 
 # per translation unit: the FP32-bulk kernels take fast reciprocals and
 # approximate transcendental functions, the FP64 form keeps IEEE arithmetic
+# The stage kernels walk tiles in a loop whose body holds the whole cell
+# update; hoisting its constants (EOS and log/exp coefficients) out of that
+# loop would keep them in registers across it and spill, so machine-level
+# loop-invariant code motion is off for the two kernel units.
+KERNEL_UNIT = ["-mllvm", "-disable-machine-licm"]
 UNITS = [
     ("fv_api.hip", []),
-    ("fv_fp64.hip", []),
-    ("fv_fp32.hip", ["-fno-hip-fp32-correctly-rounded-divide-sqrt",
-                     "-freciprocal-math", "-fapprox-func", "-fno-math-errno"]),
+    ("fv_fp64.hip", KERNEL_UNIT),
+    ("fv_fp32.hip", KERNEL_UNIT + ["-fno-hip-fp32-correctly-rounded-divide-sqrt",
+                                   "-freciprocal-math", "-fapprox-func",
+                                   "-fno-math-errno"]),
 ]
 
 

@@ -103,12 +103,12 @@ __device__ __forceinline__ int64_t xcd_block() {
 // ---------------------------------------------------------------------------
 // stage kernel
 // ---------------------------------------------------------------------------
-template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY)
+template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH>
+__global__ void __launch_bounds__(NTH)
 stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int parity) {
-  using St = Stage<DIM, NM, NS, T, C, TX, TY>;
+  using St = Stage<DIM, NM, NS, T, C, TX, TY, NTH>;
   using TL = typename St::TL;
-  constexpr int NT = TX * TY;
+  constexpr int NT = NTH;
   extern __shared__ double smem_d[];
   C* sm = reinterpret_cast<C*>(smem_d);
   C* fb = sm + (size_t)St::NW * TL::NCELL;
@@ -156,9 +156,10 @@ stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int 
   // input (kept for the update), the cell's U^n (stages 2 and 3) and its
   // first halo cell; the primitives are formed after they arrive.
   constexpr int S = St::S;
-  const int tcA = TL::own(tid);
+  const bool has_a = NT == TL::NOWN || tid < TL::NOWN;
+  const int tcA = has_a ? TL::own(tid) : 0;
   C UA[S], UN[S], UH[S];
-  St::load_state(cx, cx.src, St::tile_global(cx, tcA), UA);
+  if (has_a) St::load_state(cx, cx.src, St::tile_global(cx, tcA), UA);
   int tx, ty;
   int64_t g = 0;
   const bool own = St::own_cell(cx, tid, tx, ty, g);
@@ -166,7 +167,7 @@ stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int 
   const bool has_h = tid < TL::NHALO;
   const int tcH = has_h ? TL::halo_cell(tid) : 0;
   if (has_h) St::load_state(cx, cx.src, St::tile_global(cx, tcH), UH);
-  St::template prims_of<int>(cx, UA, sm, TL::NCELL, tcA);
+  if (has_a) St::template prims_of<int>(cx, UA, sm, TL::NCELL, tcA);
   if (has_h) St::template prims_of<int>(cx, UH, sm, TL::NCELL, tcH);
   for (int h = tid + NT; h < TL::NHALO; h += NT) St::load_cell(cx, sm, TL::halo_cell(h));
   __syncthreads();

@@ -86,18 +86,18 @@ void common_ops(Ops& o) {
   };
 }
 
-template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
+template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH>
 Ops make_ops() {
-  using St = Stage<DIM, NM, NS, T, C, TX, TY>;
+  using St = Stage<DIM, NM, NS, T, C, TX, TY, NTH>;
   Ops o;
   common_ops<DIM, NM, NS, T, C>(o);
   o.TX = TX;
   o.TY = TY;
-  o.NT = TX * TY;
+  o.NT = NTH;
   o.smem = St::smem_bytes();
   o.stage = [](fv_ctx* c, int stage, int parity, hipStream_t s) {
-    hipLaunchKernelGGL((stage_kernel<DIM, NM, NS, T, C, TX, TY>), dim3(c->total_blocks),
-                       dim3(TX * TY), St::smem_bytes(), s, c->insts_d,
+    hipLaunchKernelGGL((stage_kernel<DIM, NM, NS, T, C, TX, TY, NTH>), dim3(c->total_blocks),
+                       dim3(NTH), St::smem_bytes(), s, c->insts_d,
                        c->block_inst_d, c->P, stage, parity);
   };
   return o;
@@ -136,10 +136,10 @@ Ops make_ops3() {
   return o;
 }
 
-template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
+template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH>
 hipError_t set_smem_attr() {
-  using St = Stage<DIM, NM, NS, T, C, TX, TY>;
-  return hipFuncSetAttribute((const void*)&stage_kernel<DIM, NM, NS, T, C, TX, TY>,
+  using St = Stage<DIM, NM, NS, T, C, TX, TY, NTH>;
+  return hipFuncSetAttribute((const void*)&stage_kernel<DIM, NM, NS, T, C, TX, TY, NTH>,
                              hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)St::smem_bytes());
 }
@@ -147,11 +147,13 @@ hipError_t set_smem_attr() {
 // one compiled tile shape of a kernel set (the first one listed is the
 // default); set_attr also raises the kernel's dynamic LDS limit, a runtime
 // call that size-only queries skip
-#define FV_VAR(D, M, S_, TT, CC, X, Y)                                      \
+#define FV_VARN(D, M, S_, TT, CC, X, Y, N)                                 \
   {                                                                        \
-    vars.push_back(make_ops<D, M, S_, TT, CC, X, Y>());                    \
-    if (set_attr && herr == hipSuccess) herr = set_smem_attr<D, M, S_, TT, CC, X, Y>(); \
+    vars.push_back(make_ops<D, M, S_, TT, CC, X, Y, N>());                 \
+    if (set_attr && herr == hipSuccess) herr = set_smem_attr<D, M, S_, TT, CC, X, Y, N>(); \
   }
+// a tile shape with one thread per interior cell
+#define FV_VAR(D, M, S_, TT, CC, X, Y) FV_VARN(D, M, S_, TT, CC, X, Y, (X) * (Y))
 
 #define FV_VAR3(M, S_, TT, CC)                                              \
   { vars.push_back(make_ops3<M, S_, TT, CC>()); }

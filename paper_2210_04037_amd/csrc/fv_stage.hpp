@@ -53,17 +53,23 @@ enum { DTS_DTINV = 0, DTS_T = 2, DTS_TEND = 4, DTS_DTFIX = 5, DTS_FLAG = 6,
        DTS_SIZE = 8 };
 enum { FLAG_NONPHYS = 1 };
 
-template <int DIM, int TX, int TY>
+// A tile of TX x TY cells worked on by NTH threads (NTH >= TX * TY): thread
+// tid < TX * TY owns interior cell tid; every thread takes face items, so a
+// thread count at or above the face count of each direction computes a
+// direction's faces in one pass.
+template <int DIM, int TX, int TY, int NTH = TX * TY>
 struct Tile {
+  static_assert(NTH >= TX * TY, "a tile needs a thread per interior cell");
   static constexpr int HX = TX + 4;
   static constexpr int HY = DIM >= 2 ? TY + 4 : 1;
   static constexpr int NCELL = HX * HY;
-  static constexpr int NT = TX * TY;
+  static constexpr int NT = NTH;
+  static constexpr int NOWN = TX * TY;
   static constexpr int NFX = (TX + 1) * TY;
   static constexpr int NFY = DIM >= 2 ? TX * (TY + 1) : 0;
   static constexpr int NFACE = NFX > NFY ? NFX : NFY;
   // halo ring: tile cells outside the TX x TY interior
-  static constexpr int NHALO = NCELL - NT;
+  static constexpr int NHALO = NCELL - NOWN;
   FV_HD static int cell(int hx, int hy) { return hy * HX + hx; }
   // tile cell of halo index h (rows below and above the interior first, then
   // the two columns on each side of every interior row)
@@ -80,10 +86,10 @@ struct Tile {
   }
 };
 
-template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
+template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH = TX * TY>
 struct Stage {
   using L = Lay<DIM, NM, NS>;
-  using TL = Tile<DIM, TX, TY>;
+  using TL = Tile<DIM, TX, TY, NTH>;
   static constexpr int S = L::S;
   static constexpr int NW = L::NW;
   static constexpr int NQ = L::NQ;
@@ -614,6 +620,7 @@ struct Stage {
   // own cell of this thread inside the tile
   FV_HD static bool own_cell(const Ctx& cx, int tid, int& tx, int& ty, int64_t& g) {
     const Inst& I = *cx.I;
+    if (NTH > TL::NOWN && tid >= TL::NOWN) return false;
     tx = tid % TX;
     ty = tid / TX;
     const int gx = cx.bx * TX + tx;

@@ -149,10 +149,10 @@ static void init_ctx(Ctx& cx, Run& r, int stage, int q, double dt) {
   cx.out = stage == 1 ? r.U1.data() : (stage == 2 ? r.U2.data() : r.U.data());
 }
 
-template <int DIM, int NM, int NS, int TX, int TY>
+template <int DIM, int NM, int NS, int TX, int TY, int NTH = TX * TY>
 static void step_tiles(Run& r, int nsteps) {
-  using St = Stage<DIM, NM, NS, double, double, TX, TY>;
-  using TL = Tile<DIM, TX, TY>;
+  using St = Stage<DIM, NM, NS, double, double, TX, TY, NTH>;
+  using TL = typename St::TL;
   std::vector<double> sm(St::smem_elems());
   r.I.tiles[0] = (r.I.n[0] + TX - 1) / TX;
   r.I.tiles[1] = DIM >= 2 ? (r.I.n[1] + TY - 1) / TY : 1;
@@ -351,6 +351,10 @@ int main(int argc, char** argv) {
   } else if (g.dim == 2 && tx == 32) {
     setup<2, 2, 1>(r, &g, m, &o, P, Z);
     step_tiles<2, 2, 1, 32, 8>(r, nsteps);
+  } else if (g.dim == 2 && tx == 16) {
+    // more threads than interior cells: 16 x 15 cells, 256 threads
+    setup<2, 2, 1>(r, &g, m, &o, P, Z);
+    step_tiles<2, 2, 1, 16, 15, 256>(r, nsteps);
   } else if (g.dim == 2) {
     setup<2, 2, 1>(r, &g, m, &o, P, Z);
     step_tiles<2, 2, 1, 8, 4>(r, nsteps);

@@ -89,7 +89,8 @@ def _assert_matches_oracle(case, steps, t, flag, U, L):
 
 
 @pytest.mark.parametrize("which,steps", [
-    ("spall1d", 12), ("ring2d", 4), ("ring2d_wide", 3), ("shell3d", 2),
+    ("spall1d", 12), ("ring2d", 4), ("ring2d_wide", 3), ("ring2d_spare", 3),
+    ("shell3d", 2),
     ("impact3d", 2)])
 def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
     tile_x = 0
@@ -100,6 +101,9 @@ def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
     elif which == "ring2d_wide":
         case = F.make_case(2, n=40)            # 32 x 8 tiles
         tile_x = 32
+    elif which == "ring2d_spare":
+        case = F.make_case(2, n=37)            # 16 x 15 tiles on 256 threads
+        tile_x = 16
     elif which == "shell3d":
         case = F.make_case(3, n=10)
     else:
