@@ -40,8 +40,8 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def profile_value(key):
-    """A figure from the committed rocprofv3 summary, if it was taken on the
+def _profile_fields():
+    """Fields of the committed rocprofv3 summary, if it was taken on the
     current kernel source; else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -52,8 +52,22 @@ def profile_value(key):
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_hash") != kernel_source_hash():
         return None
+    return vals
+
+
+def profile_value(key, precision=None, tile=None):
+    """A figure from the committed rocprofv3 summary, if it was taken on the
+    current kernel source (and, given a precision and tile, in that tile
+    shape); else None."""
+    vals = _profile_fields()
+    if vals is None or key not in vals:
+        return None
+    if precision is not None:
+        want = vals.get(f"tile_{precision}")
+        if tile is None or want != "%dx%d" % (tile[0], tile[1]):
+            return None
     try:
-        return float(vals[key]) if key in vals else None
+        return float(vals[key])
     except ValueError:
         return None
 
@@ -63,20 +77,11 @@ def profile_value(key):
 VALU_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 
 
-def measured_traffic(precision):
+def measured_traffic(precision, tile):
     """HBM bytes per stage launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    vals = {}
-    for line in open(TRAFFIC_FILE):
-        if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
-            vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    key = f"bytes_per_launch_{precision}"
-    return float(vals[key]) if key in vals else None
+    summary, if it was taken on the current kernel source in this tile
+    shape; else None."""
+    return profile_value(f"bytes_per_launch_{precision}", precision, tile)
 
 
 def cpu_baseline(case, seconds=15.0):
@@ -159,12 +164,12 @@ def run_gpu(cases, precision, steps, warmup, autotune=True, chunk=10,
 
 def valu_report(args, r, avg_launch_s):
     """Instruction-issue bound of the stage kernel (1024^2 ring, FP32-bulk,
-    64x8 tile, the configuration the counters were taken in): the VALU
+    in the tile shape the counters were taken in): the VALU
     wave-instructions one launch executes (rocprofv3 SQ_INSTS_VALU) at the
     chip's issue rate, against the measured launch time."""
-    if args.workload != "ring" or args.precision != "fp32" or r["tile"] not in (None, (64, 8), [64, 8]):
+    if args.workload != "ring" or args.precision != "fp32":
         return None
-    n = profile_value("SQ_INSTS_VALU")
+    n = profile_value("SQ_INSTS_VALU", "fp32", r["tile"])
     if n is None:
         return None
     floor = n / VALU_WAVE_INSTR_PER_S
@@ -310,7 +315,8 @@ def main():
     # plus one phi0 read; per launch that is a third of it
     bytes_per_launch = (8 * S + 1) * elem * ncell / 3.0
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = measured_traffic(args.precision) if args.workload == "ring" else None
+    traffic = (measured_traffic(args.precision, r["tile"])
+               if args.workload == "ring" else None)
     out = {
         "metric": "cell-updates/s",
         "value": cu_s,

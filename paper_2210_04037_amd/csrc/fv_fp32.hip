@@ -13,30 +13,36 @@ bool select_ops_fp32(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t
   vars.clear();
   if (dim == 1 && nm == 1 && ns == 1) {
     FV_VAR(1, 1, 1, float, float, 256, 1)
+    FV_VARN(1, 1, 1, float, float, 255, 1, 256)
     FV_VAR(1, 1, 1, float, float, 128, 1)
+    FV_VARN(1, 1, 1, float, float, 127, 1, 128)
     FV_VAR(1, 1, 1, float, float, 64, 1)
     return true;
   }
   if (dim == 1 && nm == 2 && ns == 1) {
     FV_VAR(1, 2, 1, float, float, 256, 1)
+    FV_VARN(1, 2, 1, float, float, 255, 1, 256)
     FV_VAR(1, 2, 1, float, float, 128, 1)
+    FV_VARN(1, 2, 1, float, float, 127, 1, 128)
     FV_VAR(1, 2, 1, float, float, 64, 1)
     return true;
   }
   if (dim == 2 && nm == 1 && ns == 1) {
-    FV_VAR(2, 1, 1, float, float, 32, 16)
-    FV_VAR(2, 1, 1, float, float, 32, 8)
+    FV_VARN(2, 1, 1, float, float, 16, 15, 256)
+    FV_VARN(2, 1, 1, float, float, 32, 7, 256)
+    FV_VARN(2, 1, 1, float, float, 15, 16, 256)
+    FV_VARN(2, 1, 1, float, float, 32, 15, 512)
     FV_VAR(2, 1, 1, float, float, 64, 8)
-    FV_VAR(2, 1, 1, float, float, 16, 16)
-    FV_VAR(2, 1, 1, float, float, 64, 4)
+    FV_VAR(2, 1, 1, float, float, 32, 8)
     return true;
   }
   if (dim == 2 && nm == 2 && ns == 1) {
-    FV_VAR(2, 2, 1, float, float, 32, 16)
-    FV_VAR(2, 2, 1, float, float, 32, 8)
+    FV_VARN(2, 2, 1, float, float, 16, 15, 256)
+    FV_VARN(2, 2, 1, float, float, 32, 7, 256)
+    FV_VARN(2, 2, 1, float, float, 15, 16, 256)
+    FV_VARN(2, 2, 1, float, float, 32, 15, 512)
     FV_VAR(2, 2, 1, float, float, 64, 8)
-    FV_VAR(2, 2, 1, float, float, 16, 16)
-    FV_VAR(2, 2, 1, float, float, 64, 4)
+    FV_VAR(2, 2, 1, float, float, 32, 8)
     return true;
   }
   if (dim == 3 && nm == 1 && ns == 1) {

@@ -11,30 +11,34 @@ bool select_ops_fp64(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t
   vars.clear();
   if (dim == 1 && nm == 1 && ns == 1) {
     FV_VAR(1, 1, 1, double, double, 256, 1)
+    FV_VARN(1, 1, 1, double, double, 255, 1, 256)
     FV_VAR(1, 1, 1, double, double, 128, 1)
+    FV_VARN(1, 1, 1, double, double, 127, 1, 128)
     FV_VAR(1, 1, 1, double, double, 64, 1)
     return true;
   }
   if (dim == 1 && nm == 2 && ns == 1) {
     FV_VAR(1, 2, 1, double, double, 256, 1)
+    FV_VARN(1, 2, 1, double, double, 255, 1, 256)
     FV_VAR(1, 2, 1, double, double, 128, 1)
+    FV_VARN(1, 2, 1, double, double, 127, 1, 128)
     FV_VAR(1, 2, 1, double, double, 64, 1)
     return true;
   }
   if (dim == 2 && nm == 1 && ns == 1) {
-    FV_VAR(2, 1, 1, double, double, 32, 8)
-    FV_VAR(2, 1, 1, double, double, 32, 4)
+    FV_VARN(2, 1, 1, double, double, 16, 15, 256)
+    FV_VARN(2, 1, 1, double, double, 32, 7, 256)
+    FV_VARN(2, 1, 1, double, double, 16, 7, 128)
     FV_VAR(2, 1, 1, double, double, 16, 8)
-    FV_VAR(2, 1, 1, double, double, 64, 4)
-    FV_VAR(2, 1, 1, double, double, 16, 16)
+    FV_VAR(2, 1, 1, double, double, 32, 8)
     return true;
   }
   if (dim == 2 && nm == 2 && ns == 1) {
-    FV_VAR(2, 2, 1, double, double, 32, 8)
-    FV_VAR(2, 2, 1, double, double, 32, 4)
+    FV_VARN(2, 2, 1, double, double, 16, 15, 256)
+    FV_VARN(2, 2, 1, double, double, 32, 7, 256)
+    FV_VARN(2, 2, 1, double, double, 16, 7, 128)
     FV_VAR(2, 2, 1, double, double, 16, 8)
-    FV_VAR(2, 2, 1, double, double, 64, 4)
-    FV_VAR(2, 2, 1, double, double, 16, 16)
+    FV_VAR(2, 2, 1, double, double, 32, 8)
     return true;
   }
   if (dim == 3 && nm == 1 && ns == 1) {
