@@ -199,7 +199,8 @@ int32_t fv_restore(fv_ctx* ctx, const void* src);
  * timing runs of the first RK stage over the current state (these leave the
  * state, time, dt and boundary accumulators unchanged; they overwrite only
  * the stage buffer in the workspace), keep the fastest shape for later steps
- * and report.  tiles: host int32[2 * max_report] out, (x, y) per shape; ms:
+ * (a shape displaces one listed before it only when at least 2 % faster) and
+ * report.  tiles: host int32[2 * max_report] out, (x, y) per shape; ms:
  * host float[max_report] out, average launch time per shape; *n_variants:
  * number of compiled shapes; *chosen: index of the selected one (either may
  * be NULL).  Synchronises; drops captured step graphs.  Results of later
