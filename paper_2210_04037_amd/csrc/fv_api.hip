@@ -488,7 +488,7 @@ int32_t fv_cfl_dt(fv_ctx* c, double* dt_host) {
   const int q = (int)(c->step & 1);
   for (int i = 0; i < c->n_inst; ++i) {
     const double* d = &h[(size_t)i * DTS_SIZE];
-    double dt = d[DTS_DTFIX] > 0 ? d[DTS_DTFIX] : c->P.cfl / d[DTS_DTINV + q];
+    double dt = d[DTS_DTFIX] > 0 ? d[DTS_DTFIX] : c->P.cfl / dts_dtinv(d, q);
     dt_host[i] = std::fmin(dt, d[DTS_TEND] - d[DTS_T + q]);
   }
   return FV_OK;
@@ -508,7 +508,7 @@ int32_t fv_time(fv_ctx* c, double* t_host) {
 // checkpoint / restore of the context's own state
 // ---------------------------------------------------------------------------
 namespace {
-constexpr double CK_MAGIC = 4.6e15;  // tag of a checkpoint blob
+constexpr double CK_MAGIC = 4.7e15;  // tag of a checkpoint blob (this dt-state layout)
 
 size_t bacc_doubles(const fv_ctx* c, int i) {
   const Inst& I = c->insts[i];

@@ -118,7 +118,7 @@ stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int 
   double* dts = I.dts;
   const int q = parity & 1;
   const double t = dts[DTS_T + q];
-  const double dtinv = dts[DTS_DTINV + q];
+  const double dtinv = dts_dtinv(dts, q);
   double dt = dts[DTS_DTFIX] > 0.0 ? dts[DTS_DTFIX] : P.cfl / dtinv;
   dt = fmin(dt, dts[DTS_TEND] - t);
   const int lb = b - I.block_begin;
@@ -130,13 +130,13 @@ stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int 
   if (!(dt > 0.0)) {
     if (stage == 1 && !dry && lb == 0 && tid == 0) {
       dts[DTS_T + 1 - q] = t;
-      dts[DTS_DTINV + 1 - q] = dtinv;
+      dts_set_dtinv(dts, 1 - q, dtinv);
     }
     return;
   }
   if (stage == 1 && !dry && lb == 0 && tid == 0) {
     dts[DTS_T + 1 - q] = t + dt;
-    dts[DTS_DTINV + 1 - q] = 0.0;
+    dts_set_dtinv(dts, 1 - q, 0.0);
   }
   typename St::Ctx cx;
   cx.I = &I;
@@ -193,7 +193,11 @@ stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int 
     cflv = St::finish_cell(cx, g, acc, UA, UN, &bad);
     if (bad) atomicOr(reinterpret_cast<unsigned int*>(&dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);
   }
-  if (stage == 3) block_max_to<NT>(cflv, reinterpret_cast<double*>(smem_d), &dts[DTS_DTINV + 1 - q]);
+  // blocks are dispatched round-robin over the XCDs: blockIdx.x & 7 is the
+  // block's XCD and picks its CFL slot
+  if (stage == 3)
+    block_max_to<NT>(cflv, reinterpret_cast<double*>(smem_d),
+                     &dts[dts_slot(1 - q, blockIdx.x & (DTS_NSLOT - 1))]);
 }
 
 // ---------------------------------------------------------------------------
@@ -250,7 +254,7 @@ __global__ void __launch_bounds__(256) cfl_kernel(const Inst* insts, int ii, Par
       v = 0.0;
     }
   }
-  block_max_to<256>(v, scratch, &I.dts[DTS_DTINV + (parity & 1)]);
+  block_max_to<256>(v, scratch, &I.dts[dts_slot(parity & 1, blockIdx.x & (DTS_NSLOT - 1))]);
 }
 
 
@@ -271,7 +275,7 @@ __device__ __forceinline__ bool setup3(const Inst& I, const Params& P, int stage
   const int q = parity & 1;
   const double* dts = I.dts;
   t = dts[DTS_T + q];
-  dtinv = dts[DTS_DTINV + q];
+  dtinv = dts_dtinv(dts, q);
   dt = dts[DTS_DTFIX] > 0.0 ? dts[DTS_DTFIX] : P.cfl / dtinv;
   dt = fmin(dt, dts[DTS_TEND] - t);
   const bool dry = stage == 0;
@@ -397,7 +401,7 @@ __global__ void __launch_bounds__(256) finish3_kernel(const Inst* insts, int ii,
   // reduction (a finished instance carries its time and CFL value over)
   if (cx.stage == 1 && !dry && blockIdx.x == 0 && threadIdx.x == 0) {
     I.dts[DTS_T + 1 - q] = go ? t + dt : t;
-    I.dts[DTS_DTINV + 1 - q] = go ? 0.0 : dtinv;
+    dts_set_dtinv(I.dts, 1 - q, go ? 0.0 : dtinv);
   }
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double cflv = 0.0;
@@ -439,7 +443,8 @@ __global__ void __launch_bounds__(256) finish3_kernel(const Inst* insts, int ii,
     cflv = St::finish_cell(cx, g, acc, &bad);
     if (bad) atomicOr(reinterpret_cast<unsigned int*>(&I.dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);
   }
-  if (cx.stage == 3 && go) block_max_to<256>(cflv, scratch, &I.dts[DTS_DTINV + 1 - q]);
+  if (cx.stage == 3 && go)
+    block_max_to<256>(cflv, scratch, &I.dts[dts_slot(1 - q, blockIdx.x & (DTS_NSLOT - 1))]);
 }
 
 }  // namespace fvk

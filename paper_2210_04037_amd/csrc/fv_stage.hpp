@@ -47,10 +47,27 @@ struct Inst {
   int64_t ncell;
 };
 
-// dt state layout (doubles): dtinv[2] (bits of non-negative doubles, so an
-// unsigned integer max is the floating max), t[2], t_end, dt_fixed, flags.
-enum { DTS_DTINV = 0, DTS_T = 2, DTS_TEND = 4, DTS_DTFIX = 5, DTS_FLAG = 6,
-       DTS_SIZE = 8 };
+// dt state of an instance (doubles).  First line: t[2] (DTS_T), t_end,
+// dt_fixed, flags.  The CFL inverse of each parity is the maximum of
+// DTS_NSLOT partial maxima, each on a 128-byte line of its own: a block
+// folds its maximum into the slot of the XCD it runs on with an integer
+// atomicMax on the bits (an unsigned max of non-negative doubles is their
+// floating max).  A single address would take the atomics of every block of
+// a launch one after another.
+enum { DTS_T = 2, DTS_TEND = 4, DTS_DTFIX = 5, DTS_FLAG = 6, DTS_NSLOT = 8,
+       DTS_LINE = 16, DTS_SIZE = DTS_LINE * (1 + 2 * DTS_NSLOT) };
+// slot k of parity q
+FV_HD int dts_slot(int q, int k) { return DTS_LINE * (1 + q * DTS_NSLOT + k); }
+// CFL inverse of parity q
+FV_HD double dts_dtinv(const double* dts, int q) {
+  double m = dts[dts_slot(q, 0)];
+  for (int k = 1; k < DTS_NSLOT; ++k) m = m > dts[dts_slot(q, k)] ? m : dts[dts_slot(q, k)];
+  return m;
+}
+// the slots of parity q hold v (first slot) and nothing else
+FV_HD void dts_set_dtinv(double* dts, int q, double v) {
+  for (int k = 0; k < DTS_NSLOT; ++k) dts[dts_slot(q, k)] = k == 0 ? v : 0.0;
+}
 enum { FLAG_NONPHYS = 1 };
 
 // A tile of TX x TY cells worked on by NTH threads (NTH >= TX * TY): thread

@@ -119,17 +119,17 @@ static void setup(Run& r, const fv_grid* g, const fv_material* mats, const fv_op
     m = std::max(m, St::cfl_sum(r.P, r.I, Uc));
   }
   r.dts[DTS_TEND] = HUGE_VAL;
-  r.dts[DTS_DTINV] = m;
+  dts_set_dtinv(r.dts.data(), 0, m);
 }
 
 // time step of a stage; the first stage advances the other parity's time slot
 // and clears its CFL slot, as the device does
 static double stage_dt(Run& r, int stage, int q) {
   const double t = r.dts[DTS_T + q];
-  const double dt = std::min(r.P.cfl / r.dts[DTS_DTINV + q], r.dts[DTS_TEND] - t);
+  const double dt = std::min(r.P.cfl / dts_dtinv(r.dts.data(), q), r.dts[DTS_TEND] - t);
   if (stage == 1) {
     r.dts[DTS_T + 1 - q] = t + dt;
-    r.dts[DTS_DTINV + 1 - q] = 0.0;
+    dts_set_dtinv(r.dts.data(), 1 - q, 0.0);
   }
   return dt;
 }
@@ -201,7 +201,7 @@ static void step_tiles(Run& r, int nsteps) {
             if (bad) r.dts[DTS_FLAG] = 1.0;
           }
         }
-      if (stage == 3) r.dts[DTS_DTINV + 1 - q] = bmax;
+      if (stage == 3) r.dts[dts_slot(1 - q, 0)] = bmax;
     }
   }
 }
@@ -298,7 +298,7 @@ static void step_3d(Run& r, int nsteps) {
         bmax = std::max(bmax, St::finish_cell(cx, g, acc, &bad));
         if (bad) r.dts[DTS_FLAG] = 1.0;
       }
-      if (stage == 3) r.dts[DTS_DTINV + 1 - q] = bmax;
+      if (stage == 3) r.dts[dts_slot(1 - q, 0)] = bmax;
     }
   }
 }
