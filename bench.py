@@ -225,6 +225,56 @@ def loop_single_runs(cases, precision, steps, warmup, chunk):
     return total
 
 
+def fragment_report(cases, chunk):
+    """Members run to their end time in one ensemble, FP64 and FP32-bulk;
+    per member: fragment count of each form, the cumulative fragment-mass
+    histogram of each (fragments of mass >= edge, fv_fragment_histogram),
+    and the number of borderline cells (solid fraction within 0.05 of the
+    0.5 cut in the FP64 state).  A form that raises the non-physical flag is
+    reported at its last checkpoint before the flag, with the time reached."""
+    import numpy as np
+    import fvinputs as F
+    from paper_2210_04037_amd import abi
+    from paper_2210_04037_amd.solver import GpuSolver
+    edges = F.mass_edges()
+    t_end = np.array([c.t_end for c in cases])
+    rep = {"edges_kg_per_m": edges, "members": [
+        {"member": c.meta.get("member", i), "n": c.n[0]} for i, c in enumerate(cases)]}
+    for prec in ("fp64", "fp32"):
+        g = GpuSolver(cases, precision=prec, use_graph=chunk > 0)
+        g.step(0, t_end=t_end)
+        n = max(chunk, 1) * 10
+        steps, flag = 0, None
+        while np.any(g.time() < t_end):
+            ck = g.checkpoint()
+            try:
+                g.step(n)
+                g.cfl_dt()
+            except abi.FvError as e:
+                flag = str(e)
+                g.restore(ck)
+                break
+            steps += n
+            if steps % 1000 == 0:
+                print(f"[fragments] {prec} step {steps} t/t_end "
+                      f"{float(np.min(g.time() / t_end)):.3f}",
+                      file=sys.stderr, flush=True)
+        t = g.time()
+        for i, c in enumerate(cases):
+            _, frags = g.fragments(i, 0.5)
+            m = rep["members"][i]
+            if prec == "fp64":
+                U = g.state(i)
+                m["borderline_cells"] = int(np.sum(np.abs(U[0] - 0.5) < 0.05))
+            m[f"t_reached_{prec}"] = float(t[i])
+            m[f"fragments_{prec}"] = len(frags)
+            m[f"cumulative_{prec}"] = g.mass_histogram(frags, edges)
+        rep[f"steps_{prec}"] = steps
+        rep[f"nonphysical_flag_{prec}"] = flag
+        g.close()
+    return rep
+
+
 def calibrate_copy(nbytes=1 << 30, reps=5):
     """A plain device copy of known size, for scaling the FETCH_SIZE and
     WRITE_SIZE counters of rocprofv3 to bytes."""
@@ -261,6 +311,10 @@ def main():
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--no-loop", action="store_true",
                     help="ensemble: skip timing the members one at a time")
+    ap.add_argument("--fragments", action="store_true",
+                    help="ensemble: also run members 0-7 at full size to "
+                         "their end time in both forms and report fragment "
+                         "counts and cumulative mass histograms")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", default=None,
                     help="fixed tile 'TX,TY' (skips the autotuner)")
@@ -368,6 +422,8 @@ def main():
             "value": ncell * args.steps / (loop_ms * 1e-3),
             "ms_per_step": loop_ms / args.steps,
             "ensemble_speedup": loop_ms / ms}
+    if args.workload == "ensemble" and args.fragments:
+        out["fragments_members_0_7"] = fragment_report(cases[:8], chunk)
     if not args.no_cpu and args.workload == "ring":
         out["cpu_baseline"] = cpu_baseline(cases[0])
     print(json.dumps(out), flush=True)

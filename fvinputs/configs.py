@@ -340,3 +340,10 @@ def uniform_case(dim, n, mats, phi, rho, u, p, bc="periodic", vbar=None,
                 for k in range(3))
     return Case("uniform", dim, tuple(n), lo, hi, bcs, mats, prim,
                 np.full(shp, float(phi0)), t_end)
+
+
+def mass_edges(lo=1.0e-6, hi=10.0, per_decade=4):
+    """Log-spaced fragment-mass edges (kg per metre of depth in 2D) for the
+    cumulative fragment-mass histograms of the ring workloads."""
+    n = int(round(np.log10(hi / lo) * per_decade)) + 1
+    return [float(v) for v in np.geomspace(lo, hi, n)]

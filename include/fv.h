@@ -237,6 +237,16 @@ size_t fv_fragment_workspace_bytes(const fv_ctx* ctx, int32_t inst, int64_t cap)
 int32_t fv_fragments(fv_ctx* ctx, int32_t inst, double cut, int32_t* labels, void* frag_ws,
                      size_t frag_ws_bytes, int64_t cap, int64_t* n_frag, fv_fragment* out);
 
+/* Cumulative fragment-mass histogram, the form in which Sections 4.2 and 4.3
+ * present fragment distributions (fragment mass against cumulative fragment
+ * number): counts[k] = number of fragments among frags[0..n) whose mass is at
+ * least edges[k].  Host arrays, caller-owned: frags (n entries, as
+ * fv_fragments returns them), edges (n_edges doubles, any order), counts
+ * (n_edges int64, out).  No device work and no context.  FV_EINVAL for a
+ * negative count or a null array that is needed. */
+int32_t fv_fragment_histogram(const fv_fragment* frags, int64_t n, const double* edges,
+                              int32_t n_edges, int64_t* counts);
+
 /* Text of the last error of ctx (or of the last failed fv_init when ctx is
  * NULL).  Valid until the next call on ctx. */
 const char* fv_last_error(const fv_ctx* ctx);

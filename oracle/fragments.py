@@ -59,3 +59,12 @@ def fragments(solid_phi, solid_mass, cell_volume, cut=0.5):
         out.append((int(root), int(cells.sum()),
                     math.fsum(vals) * cell_volume, touch))
     return out
+
+
+def mass_histogram(frags, edges):
+    """Cumulative fragment count against fragment mass, the form in which
+    Sections 4.2 and 4.3 present fragment distributions (fragment mass
+    against cumulative fragment number): entry k is the number of fragments
+    whose mass is at least edges[k]."""
+    masses = [f[2] for f in frags]
+    return [sum(1 for m in masses if m >= e) for e in edges]

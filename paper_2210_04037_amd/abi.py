@@ -18,7 +18,8 @@ EXPORTS = ["fv_state_fields", "fv_workspace_bytes", "fv_init",
            "fv_step", "fv_time", "fv_totals", "fv_checkpoint_bytes",
            "fv_checkpoint", "fv_restore", "fv_autotune",
            "fv_fragment_workspace_bytes",
-           "fv_fragments", "fv_last_error", "fv_destroy"]
+           "fv_fragments", "fv_fragment_histogram", "fv_last_error",
+           "fv_destroy"]
 
 
 class FvGrid(ctypes.Structure):
@@ -103,6 +104,9 @@ def load(path=LIB_PATH):
     lib.fv_fragments.argtypes = [vp, i32, dbl, vp, vp, ctypes.c_size_t,
                                  ctypes.c_int64, P(ctypes.c_int64), P(FvFragment)]
     lib.fv_fragments.restype = i32
+    lib.fv_fragment_histogram.argtypes = [vp, ctypes.c_int64, P(dbl), i32,
+                                          P(ctypes.c_int64)]
+    lib.fv_fragment_histogram.restype = i32
     lib.fv_step.argtypes = [vp, P(dbl), i32, P(dbl)]
     lib.fv_step.restype = i32
     lib.fv_time.argtypes = [vp, P(dbl)]

@@ -840,6 +840,19 @@ size_t fv_fragment_workspace_bytes(const fv_ctx* c, int32_t inst, int64_t cap) {
   return plan_frag(c->insts[inst].ncell, cap).total;
 }
 
+int32_t fv_fragment_histogram(const fv_fragment* frags, int64_t n, const double* edges,
+                              int32_t n_edges, int64_t* counts) {
+  if (n < 0 || n_edges < 0 || (n > 0 && !frags) || (n_edges > 0 && (!edges || !counts)))
+    return FV_EINVAL;
+  std::vector<double> m((size_t)n);
+  for (int64_t i = 0; i < n; ++i) m[(size_t)i] = frags[i].mass;
+  std::sort(m.begin(), m.end());
+  // fragments at or above an edge: those past the first mass not below it
+  for (int32_t k = 0; k < n_edges; ++k)
+    counts[k] = (int64_t)(m.end() - std::lower_bound(m.begin(), m.end(), edges[k]));
+  return FV_OK;
+}
+
 int32_t fv_fragments(fv_ctx* c, int32_t inst, double cut, int32_t* labels, void* frag_ws,
                      size_t frag_ws_bytes, int64_t cap, int64_t* n_frag, fv_fragment* out) {
   if (!c) return FV_EINVAL;

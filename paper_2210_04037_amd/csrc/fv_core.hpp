@@ -34,8 +34,6 @@ FV_HD double m_exp(double x) { return exp(x); }
 FV_HD float m_exp(float x) { return expf(x); }
 FV_HD double m_pow(double x, double y) { return pow(x, y); }
 FV_HD float m_pow(float x, float y) { return powf(x, y); }
-FV_HD double m_atanh(double x) { return atanh(x); }
-FV_HD float m_atanh(float x) { return atanhf(x); }
 FV_HD double m_abs(double x) { return fabs(x); }
 FV_HD float m_abs(float x) { return fabsf(x); }
 template <class C> FV_HD C m_min(C a, C b) { return a < b ? a : b; }
@@ -284,15 +282,19 @@ FV_HD C mix_sound(const Params& P, const C* phi, const Mix<NM, NS, C>& mx, C p,
 // kinematics: deviatoric Hencky strain of Vbar (Section 2.2, dev H = ln Vbar)
 // taken as 1/2 ln(Vbar Vbar^T) with the trace removed.
 // ----------------------------------------------------------------------------
-// log of a symmetric positive-definite 2x2 matrix [[b00, b01], [b01, b11]]:
-// log M = 1/2 ln(det M) I + g (M - m I), m = tr/2, r = eigen half-gap,
-// g = (ln l1 - ln l2)/(l1 - l2) = atanh(r/m)/r (series for small r/m).
+// log of a symmetric positive-definite 2x2 matrix M = [[b00, b01], [b01, b11]]
+// given ld = ln(det M) / 2:
+// log M = ld I + g (M - m I), m = tr/2, r = eigen half-gap,
+// g = (ln l1 - ln l2)/(l1 - l2) = (ln l1 - ld)/r with l1 = m + r the larger
+// eigenvalue (series in r/m for a small gap).  With M = V V^T the caller
+// passes ld = ln|det V|: det M formed from M's entries cancels to nothing
+// for a strongly sheared V (eigenvalue ratio near the rounding unit), and
+// atanh(r/m) = g r would then see r/m round to 1.
 template <class C>
-FV_HD void sym2_log(C b00, C b01, C b11, C& l00, C& l01, C& l11) {
+FV_HD void sym2_log(C b00, C b01, C b11, C ld, C& l00, C& l01, C& l11) {
   const C m = (C)0.5 * (b00 + b11);
   const C d = (C)0.5 * (b00 - b11);
   const C r = m_sqrt(d * d + b01 * b01);
-  const C hld = (C)0.5 * m_log(b00 * b11 - b01 * b01);
   const C x = r / m;
   const C xs = sizeof(C) == 8 ? (C)1e-3 : (C)5e-2;
   C g;
@@ -300,10 +302,10 @@ FV_HD void sym2_log(C b00, C b01, C b11, C& l00, C& l01, C& l11) {
     const C x2 = x * x;
     g = ((C)1 + x2 * ((C)(1.0 / 3.0) + x2 * ((C)0.2 + x2 * (C)(1.0 / 7.0)))) / m;
   } else {
-    g = m_atanh(x) / r;
+    g = (m_log(m + r) - ld) / r;
   }
-  l00 = hld + g * d;
-  l11 = hld - g * d;
+  l00 = ld + g * d;
+  l11 = ld - g * d;
   l01 = g * b01;
 }
 
@@ -399,6 +401,22 @@ FV_HD void sym3_compose(const C Q[3][3], const C f[3], C M[3][3]) {
       M[i][j] = Q[i][0] * f[0] * Q[j][0] + Q[i][1] * f[1] * Q[j][1] + Q[i][2] * f[2] * Q[j][2];
 }
 
+// Half logs of the eigenvalues of B = V V^T from its diagonalised form
+// (B[k][k] after sym3_eig): the two larger ones directly, the smallest from
+// det B = det(V)^2, since an eigenvalue far below the rounding of the largest
+// is lost in B itself (a strongly sheared V).
+template <class C>
+FV_HD void half_log_eigs3(const C V[3][3], const C B[3][3], C h[3]) {
+  const C detv = V[0][0] * (V[1][1] * V[2][2] - V[1][2] * V[2][1]) -
+                 V[0][1] * (V[1][0] * V[2][2] - V[1][2] * V[2][0]) +
+                 V[0][2] * (V[1][0] * V[2][1] - V[1][1] * V[2][0]);
+  const int k0 = B[0][0] <= B[1][1] ? (B[0][0] <= B[2][2] ? 0 : 2) : (B[1][1] <= B[2][2] ? 1 : 2);
+  const int k1 = (k0 + 1) % 3, k2 = (k0 + 2) % 3;
+  h[k1] = (C)0.5 * m_log(B[k1][k1]);
+  h[k2] = (C)0.5 * m_log(B[k2][k2]);
+  h[k0] = m_log(m_abs(detv)) - h[k1] - h[k2];
+}
+
 // dev H (full symmetric 3x3, zeros where the dimension keeps them zero)
 template <int DIM, class C>
 FV_HD void hencky(const C V[3][3], C H[3][3]) {
@@ -420,8 +438,7 @@ FV_HD void hencky(const C V[3][3], C H[3][3]) {
         B[i][j] = V[i][0] * V[j][0] + V[i][1] * V[j][1] + V[i][2] * V[j][2];
     sym3_eig(B, Q);
     C h[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) h[k] = (C)0.5 * m_log(B[k][k]);
+    half_log_eigs3(V, B, h);
     const C mm = (h[0] + h[1] + h[2]) / (C)3;
 #pragma unroll
     for (int k = 0; k < 3; ++k) h[k] -= mm;
@@ -431,7 +448,8 @@ FV_HD void hencky(const C V[3][3], C H[3][3]) {
     const C b01 = V[0][0] * V[1][0] + V[0][1] * V[1][1];
     const C b11 = V[1][0] * V[1][0] + V[1][1] * V[1][1];
     C l00, l01, l11;
-    sym2_log(b00, b01, b11, l00, l01, l11);
+    const C ld = m_log(m_abs(V[0][0] * V[1][1] - V[0][1] * V[1][0]));
+    sym2_log(b00, b01, b11, ld, l00, l01, l11);
     const C h00 = (C)0.5 * l00, h11 = (C)0.5 * l11, h01 = (C)0.5 * l01;
     const C h22 = m_log(m_abs(V[2][2]));
     const C mm = (h00 + h11 + h22) / (C)3;

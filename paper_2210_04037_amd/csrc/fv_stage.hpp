@@ -772,8 +772,7 @@ struct Stage {
         for (int j = 0; j < 3; ++j)
           B[i][j] = V[i][0] * V[j][0] + V[i][1] * V[j][1] + V[i][2] * V[j][2];
       sym3_eig(B, Qe);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) he[k] = 0.5 * log(B[k][k]);
+      half_log_eigs3<double>(V, B, he);
       const double mm = (he[0] + he[1] + he[2]) / 3.0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) he[k] -= mm;
@@ -905,8 +904,7 @@ struct Stage {
         for (int j = 0; j < 3; ++j)
           B[i][j] = V[i][0] * V[j][0] + V[i][1] * V[j][1] + V[i][2] * V[j][2];
       sym3_eig(B, Qe);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) he[k] = 0.5 * log(B[k][k]);
+      half_log_eigs3<double>(V, B, he);
       const double mm = (he[0] + he[1] + he[2]) / 3.0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) he[k] -= mm;
@@ -1038,8 +1036,7 @@ struct Cell {
         for (int j = 0; j < 3; ++j)
           B[i][j] = V[i][0] * V[j][0] + V[i][1] * V[j][1] + V[i][2] * V[j][2];
       sym3_eig(B, Qe);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) he[k] = 0.5 * log(B[k][k]);
+      half_log_eigs3<double>(V, B, he);
       const double mm = (he[0] + he[1] + he[2]) / 3.0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) he[k] -= mm;

@@ -171,6 +171,19 @@ class GpuSolver:
                   bool(f.touches_boundary)) for f in out[:nf.value]]
         return lab, frags
 
+    def mass_histogram(self, frags, edges):
+        """Cumulative fragment count at each mass edge (entry k: fragments of
+        mass >= edges[k]) from the library's fv_fragment_histogram."""
+        n = len(frags)
+        arr = (abi.FvFragment * max(n, 1))()
+        for k, (lab, nc, m, t) in enumerate(frags):
+            arr[k].label, arr[k].n_cells, arr[k].mass = lab, nc, m
+            arr[k].touches_boundary = int(t)
+        e = (ctypes.c_double * len(edges))(*[float(v) for v in edges])
+        out = (ctypes.c_int64 * len(edges))()
+        self._c(self.lib.fv_fragment_histogram(arr, n, e, len(edges), out))
+        return list(out)
+
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:
             self.lib.fv_destroy(self.ctx)

@@ -90,3 +90,26 @@ def test_state_rows_match_library_and_oracle_layout(cfg):
     assert rows["dmg"] == [L.dmg[l] for l in L.solids]
     assert rows["mom"] == L.mom and rows["energy"] == L.energy
     assert rows["vbar"] == L.vbar and rows["X"] == L.X
+
+
+def test_fragment_histogram_matches_oracle_definition():
+    """fv_fragment_histogram is host code: checked here against the oracle's
+    cumulative count on seeded lists (ties at an edge, unsorted edges)."""
+    import numpy as np
+    from oracle import fragments as Fr
+    lib = _lib()
+    rng = np.random.default_rng(11)
+    for n in (0, 1, 7, 300):
+        masses = np.round(rng.lognormal(-3, 2, n), 3)
+        frags = [(i, 1, float(m), i % 2 == 0) for i, m in enumerate(masses)]
+        arr = (abi.FvFragment * max(n, 1))()
+        for i, (lab, nc, m, t) in enumerate(frags):
+            arr[i].label, arr[i].n_cells, arr[i].mass = lab, nc, m
+            arr[i].touches_boundary = int(t)
+        edges = list(rng.permutation(np.concatenate(
+            [masses[:5], np.geomspace(1e-6, 10.0, 15)])))
+        e = (ctypes.c_double * len(edges))(*edges)
+        out = (ctypes.c_int64 * len(edges))()
+        assert lib.fv_fragment_histogram(arr, n, e, len(edges), out) == 0
+        assert list(out) == Fr.mass_histogram(frags, edges)
+    assert lib.fv_fragment_histogram(None, -1, None, 0, None) == abi.FV_EINVAL

@@ -85,9 +85,11 @@ def _tiles(case, precision):
     return list(table)
 
 
+@pytest.mark.parametrize("dim", [1, 2])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_tile_shapes_give_identical_bits(precision):
-    case = F.make_case(2, n=200)          # ragged against every tile shape
+def test_tile_shapes_give_identical_bits(precision, dim):
+    # ragged against every tile shape, including those with spare threads
+    case = F.make_case(2, n=200) if dim == 2 else F.make_case(1, n=1021)
     shapes = _tiles(case, precision)
     assert len(shapes) >= 3
     ref = None

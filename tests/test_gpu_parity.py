@@ -294,3 +294,28 @@ def test_unloaded_state_is_a_call_order_error():
     assert np.array_equal(g.state(0), ref.state(0))
     g.close()
     ref.close()
+
+
+@pytest.mark.parametrize("which", ["ring", "member1"])
+def test_fp64_runs_reach_their_end_time(which):
+    """The FP64 form carries the 1024^2 ring (about 11300 steps) and ensemble
+    member 1 (768^2, about 27000 steps) through fracture to their 40 us end
+    time without the non-physical flag.  Late in these runs the rarefied gas
+    behind the fragments holds stretches with principal ratios beyond 1e8,
+    whose Hencky strain the kernels form from det V (a strain formed from
+    the entries of V V^T alone gave NaN there)."""
+    from paper_2210_04037_amd.solver import GpuSolver
+    case = F.make_case(2) if which == "ring" else F.make_case(4, member=1)
+    print(f"[end time] {which} {case.n[0]}^2 fp64 to {case.t_end:.1e} s", flush=True)
+    g = GpuSolver(case, precision="fp64", use_graph=True)
+    g.step(0, t_end=[case.t_end])
+    steps = 0
+    while g.time()[0] < case.t_end:
+        g.step(500)
+        steps += 500
+        assert steps < 40000
+    assert g.cfl_dt()[0] >= 0.0              # raises on the device flag
+    lab, frags = g.fragments(0, 0.5)
+    g.close()
+    print(f"[end time] {which}: {steps} steps, {len(frags)} fragments", flush=True)
+    assert len(frags) >= 10

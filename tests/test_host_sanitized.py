@@ -110,3 +110,54 @@ def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
         case = F.make_case(5, n=9)
     t, flag, U, L = _run(exe, tmp_path, case, steps, tile_x)
     _assert_matches_oracle(case, steps, t, flag, U, L)
+
+
+@pytest.fixture(scope="module")
+def hencky_exe(tmp_path_factory):
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    out = str(tmp_path_factory.mktemp("hk") / "hencky_check")
+    cmd = [cxx, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-Wall", "-Wno-unknown-pragmas",
+           "-Werror", "-o", out, os.path.join(HERE, "host", "hencky_check.cpp")]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-4000:]
+    return out
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_hencky_of_strongly_sheared_stretch(hencky_exe, dim):
+    """dev H = dev 1/2 ln(V V^T) of unimodular stretches with principal
+    ratios up to 1e12 (the state of rarefied gas cells late in the ring
+    runs): finite, and equal to the same strain from the singular values of
+    V (which are the square roots of the eigenvalues of V V^T) to the
+    rounding that the conditioning allows.  Formed from the entries of V V^T
+    alone, the smallest eigenvalue is lost below about 1e8."""
+    def stretch(s, th, c):
+        R = np.array([[np.cos(th), -np.sin(th), 0.0],
+                      [np.sin(th), np.cos(th), 0.0], [0.0, 0.0, 1.0]])
+        return R @ np.diag([s, 1.0 / (s * c), c]) @ R.T
+
+    cases = [(1.0001, 0.7, 1.0), (1e3, 0.3, 1.0), (3e3, 0.9, 0.02),
+             (1e5, 2.0, 25.7), (1e6, 1.1, 0.5)]
+    Vs = [stretch(*c) for c in cases]
+    inp = f"{dim}\n" + "\n".join(" ".join(repr(float(x)) for x in V.ravel())
+                                 for V in Vs) + "\n"
+    r = subprocess.run([hencky_exe], input=inp, capture_output=True, text=True,
+                       timeout=60)
+    assert r.returncode == 0, r.stderr[-4000:]
+    rows = r.stdout.strip().split("\n")
+    assert len(rows) == len(Vs)
+    for (s, _, _), V, row in zip(cases, Vs, rows):
+        H = np.array([float(t) for t in row.split()]).reshape(3, 3)
+        U, sig, _ = np.linalg.svd(V)
+        h = np.log(sig)
+        h -= h.mean()
+        ref = (U * h) @ U.T
+        assert np.isfinite(H).all(), s
+        # the rounding of V itself moves the smallest singular value by
+        # about eps * sigma_max, i.e. its log by eps * kappa
+        kappa = sig.max() / sig.min()
+        bound = (1e-11 + 4 * np.finfo(float).eps * kappa) * np.max(np.abs(ref))
+        assert np.max(np.abs(H - ref)) <= bound, (s, np.max(np.abs(H - ref)), bound)

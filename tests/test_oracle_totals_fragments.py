@@ -64,6 +64,23 @@ def test_fragment_masses_and_boundary_flags():
     assert m1 == math.fsum([0.8 * 8930.0] * 6) * 2.0
 
 
+def test_mass_histogram_counts_fragments_at_or_above_each_edge():
+    """Cumulative count against mass (Sections 4.2, 4.3), on a list whose
+    counts follow by inspection: ties count at their own edge."""
+    frags = [(0, 1, 1.0, False), (5, 2, 2.0, True), (9, 2, 2.0, False),
+             (12, 5, 5.0, False)]
+    edges = [0.5, 1.0, 2.0, math.nextafter(2.0, 3.0), 5.0, 6.0]
+    assert Fr.mass_histogram(frags, edges) == [4, 4, 3, 1, 1, 0]
+    assert Fr.mass_histogram([], edges) == [0] * len(edges)
+    # the first edge at or below the lightest fragment counts them all, and
+    # the count never rises with the edge
+    rng = np.random.default_rng(3)
+    frags = [(i, 1, float(m), False) for i, m in enumerate(rng.lognormal(0, 2, 50))]
+    edges = sorted(rng.lognormal(0, 2, 20).tolist())
+    h = Fr.mass_histogram(frags, [0.0] + edges)
+    assert h[0] == 50 and all(a >= b for a, b in zip(h, h[1:]))
+
+
 def test_workload_constants_from_paper_tables():
     g = json.load(open(os.path.join(HERE, "golden", "paper_tables.json")))
     cu = F.COPPER
