@@ -26,6 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+SCHEDULES = {0: "by-instance", 1: "largest-first", 2: "interleaved"}  # fv_options.tile[2]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2210_04037_amd", "csrc", f)
                   for f in ("fv_core.hpp", "fv_stage.hpp", "fv_kernels.hpp",
@@ -317,7 +318,9 @@ def main():
                          "counts and cumulative mass histograms")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", default=None,
-                    help="fixed tile 'TX,TY' (skips the autotuner)")
+                    help="fixed tile 'TX,TY' or 'TX,TY,SCHEDULE' (0: by "
+                         "instance, 1: largest first, 2: interleaved); skips "
+                         "the autotuner")
     ap.add_argument("--graph-chunk", type=int, default=10,
                     help="steps per captured graph (0: eager launches)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -404,7 +407,8 @@ def main():
         },
         "valu": valu_report(args, r, avg_launch_s),
         "autotune_ms_per_stage1_launch": (
-            {f"{k[0]}x{k[1]}": v for k, v in r["tiles_ms"].items()}
+            {"%dx%d/%s" % (k[0], k[1], SCHEDULES.get(k[2], k[2])): v
+             for k, v in r["tiles_ms"].items()}
             if r["tiles_ms"] else None),
     }
     if not args.no_compare:

@@ -61,6 +61,13 @@ extern "C" {
 #define FV_FP64 0        /* state and arithmetic in double */
 #define FV_FP32_BULK 1   /* float state; double islands (see fv_options) */
 
+/* Block schedules of the stage launch over an ensemble (fv_options.tile[2]):
+ * the order in which the blocks of all instances are listed.  Results do
+ * not depend on it. */
+#define FV_SCHED_BY_INSTANCE 0    /* instance after instance (default) */
+#define FV_SCHED_LARGEST_FIRST 1  /* instances by decreasing tile count */
+#define FV_SCHED_INTERLEAVED 2    /* tile k of every instance before tile k+1 */
+
 typedef struct fv_ctx fv_ctx;
 
 /* Uniform grid of one instance.  dim in {1, 2, 3}; n[k] cells on [lo[k],hi[k]]
@@ -91,10 +98,11 @@ typedef struct {
  * volume fractions are clamped to [phi_floor, 1] (absent materials).
  * weno_eps: WENO3 smoothness floor relative to the squared domain extent.
  * phi_fp64_cut: FP32-bulk only, cells with a volume fraction below it invert
- * the mixture EOS in double.  tile: cells per workgroup tile in x and y
- * (tile[2] unused); {0, 0} selects the default shape, any other value must
- * be one of the compiled shapes (fv_autotune lists them) or fv_init fails
- * with FV_EINVAL.  Results do not depend on the tile shape.  use_graph:
+ * the mixture EOS in double.  tile: cells per workgroup tile in x and y,
+ * then the block schedule (FV_SCHED_*); {0, 0} selects the default shape,
+ * any other value must be one of the compiled shapes (fv_autotune lists
+ * them) or fv_init fails with FV_EINVAL, as does a schedule outside 0..2.
+ * Results depend on neither.  use_graph:
  * nonzero makes fv_step capture its n_steps steps into a HIP graph at the
  * first call with that step count and replay it afterwards. */
 typedef struct {
@@ -195,16 +203,18 @@ size_t fv_checkpoint_bytes(const fv_ctx* ctx);
 int32_t fv_checkpoint(fv_ctx* ctx, void* dst);
 int32_t fv_restore(fv_ctx* ctx, const void* src);
 
-/* Autotuner: time every compiled tile shape of ctx's kernel set on reps
- * timing runs of the first RK stage over the current state (these leave the
- * state, time, dt and boundary accumulators unchanged; they overwrite only
- * the stage buffer in the workspace), keep the fastest shape for later steps
- * (a shape displaces one listed before it only when at least 2 % faster) and
- * report.  tiles: host int32[2 * max_report] out, (x, y) per shape; ms:
- * host float[max_report] out, average launch time per shape; *n_variants:
- * number of compiled shapes; *chosen: index of the selected one (either may
- * be NULL).  Synchronises; drops captured step graphs.  Results of later
- * steps are bitwise those of any other shape. */
+/* Autotuner: time every configuration of ctx's kernel set -- each compiled
+ * tile shape under each block schedule (FV_SCHED_*; one schedule for a
+ * single instance) -- on reps timing runs of the first RK stage over the
+ * current state (these leave the state, time, dt and boundary accumulators
+ * unchanged; they overwrite only the stage buffer in the workspace), keep
+ * the fastest for later steps (a configuration displaces one listed before
+ * it only when at least 2 % faster) and report.  tiles: host
+ * int32[3 * max_report] out, (x, y, schedule) per configuration; ms: host
+ * float[max_report] out, average launch time per configuration;
+ * *n_variants: number of configurations; *chosen: index of the selected one
+ * (either may be NULL).  Synchronises; drops captured step graphs.  Results
+ * of later steps are bitwise those of any other configuration. */
 int32_t fv_autotune(fv_ctx* ctx, int32_t reps, int32_t max_report, int32_t* tiles, float* ms,
                     int32_t* n_variants, int32_t* chosen);
 

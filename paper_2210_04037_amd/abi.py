@@ -155,7 +155,9 @@ def options_struct(precision="fp64", cfl=0.6, phi_floor=1e-8, weno_eps=1e-6,
     o.weno_eps = weno_eps
     o.phi_fp64_cut = phi_fp64_cut
     if tile is not None:
-        o.tile[0], o.tile[1] = int(tile[0]), int(tile[1])
+        # (x, y) or (x, y, block schedule)
+        for k, v in enumerate(tile):
+            o.tile[k] = int(v)
     o.use_graph = 1 if use_graph else 0
     return o
 

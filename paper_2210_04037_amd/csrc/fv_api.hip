@@ -128,6 +128,9 @@ static int validate(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
   if (!(opt->cfl > 0 && opt->cfl <= 1)) { msg = "cfl must be in (0, 1]"; return FV_EINVAL; }
   if (!(opt->phi_floor > 0 && opt->phi_floor < 0.5)) { msg = "phi_floor must be in (0, 0.5)"; return FV_EINVAL; }
   if (!(opt->weno_eps > 0)) { msg = "weno_eps must be > 0"; return FV_EINVAL; }
+  if (opt->tile[2] < FV_SCHED_BY_INSTANCE || opt->tile[2] > FV_SCHED_INTERLEAVED) {
+    msg = "tile[2] must be a block schedule (0, 1 or 2)"; return FV_EINVAL;
+  }
   const int dim = grids[0].dim;
   for (int i = 0; i < n_inst; ++i) {
     const fv_grid& g = grids[i];
@@ -149,7 +152,7 @@ static int validate(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
 
 struct WsPlan {
   std::vector<size_t> u1, u2, bacc, dts, wb, fb[3];
-  size_t insts = 0, block_inst = 0, bins = 0, total = 0;
+  size_t insts = 0, block_tab = 0, bins = 0, total = 0;
   int max_blocks = 0;
 };
 
@@ -192,7 +195,7 @@ static void plan_ws(int32_t n_inst, const fv_grid* grids, const std::vector<Ops>
     }
   }
   W.insts = off; off += align256(sizeof(Inst) * n_inst);
-  W.block_inst = off; off += align256(sizeof(int) * W.max_blocks);
+  W.block_tab = off; off += align256(sizeof(int2) * W.max_blocks);
   // totals bins: per instance and total, the interior sum and one per
   // boundary side (2 per direction)
   W.bins = off;
@@ -245,10 +248,13 @@ static void drop_graphs(fv_ctx* c) {
   c->gnext = 0;
 }
 
-static int set_tiles(fv_ctx* c, int v) {
+// Tile shape v and block schedule sched: the block table lists (instance,
+// tile) for every block of a stage launch, in the order the schedule gives
+// (blocks start roughly in table order, so it decides which instances share
+// the device at a time and which tiles meet in an XCD's L2).
+static int set_tiles(fv_ctx* c, int v, int sched) {
   const Ops& o = c->vars[v];
   int total = 0;
-  c->h_block_inst.clear();
   for (int i = 0; i < c->n_inst; ++i) {
     Inst& I = c->insts[i];
     fv_grid g{};
@@ -257,20 +263,36 @@ static int set_tiles(fv_ctx* c, int v) {
     int tx, ty;
     tiles_of(g, o, tx, ty);
     I.tiles[0] = tx; I.tiles[1] = ty; I.tiles[2] = 1;
-    I.block_begin = total;
     I.nblocks = tx * ty;
     total += I.nblocks;
-    for (int b = 0; b < I.nblocks; ++b) c->h_block_inst.push_back(i);
   }
   if (total > c->max_blocks) return fail(c, FV_EINVAL, "block table overflow");
+  std::vector<int> order(c->n_inst);
+  for (int i = 0; i < c->n_inst; ++i) order[i] = i;
+  if (sched == FV_SCHED_LARGEST_FIRST)
+    std::stable_sort(order.begin(), order.end(), [c](int a, int b) {
+      return c->insts[a].nblocks > c->insts[b].nblocks;
+    });
+  c->h_block_tab.clear();
+  if (sched == FV_SCHED_INTERLEAVED) {
+    int most = 0;
+    for (int i = 0; i < c->n_inst; ++i) most = std::max(most, c->insts[i].nblocks);
+    for (int t = 0; t < most; ++t)
+      for (int i = 0; i < c->n_inst; ++i)
+        if (t < c->insts[i].nblocks) c->h_block_tab.push_back(make_int2(i, t));
+  } else {
+    for (int i : order)
+      for (int t = 0; t < c->insts[i].nblocks; ++t) c->h_block_tab.push_back(make_int2(i, t));
+  }
   drop_graphs(c);
   c->var = v;
+  c->sched = sched;
   c->ops = o;
   c->total_blocks = total;
   int rc = hip_check(c, hipMemcpyAsync(c->insts_d, c->insts.data(), sizeof(Inst) * c->n_inst,
                                        hipMemcpyHostToDevice, c->stream), "copy instance table");
   if (rc == FV_OK)
-    rc = hip_check(c, hipMemcpyAsync(c->block_inst_d, c->h_block_inst.data(), sizeof(int) * total,
+    rc = hip_check(c, hipMemcpyAsync(c->block_tab_d, c->h_block_tab.data(), sizeof(int2) * total,
                                      hipMemcpyHostToDevice, c->stream), "copy block table");
   if (rc == FV_OK) rc = hip_check(c, hipStreamSynchronize(c->stream), "tile table sync");
   return rc;
@@ -377,10 +399,10 @@ int32_t fv_init(fv_ctx** out, int32_t n_inst, const fv_grid* grids, int32_t n_ma
     }
   }
   c->insts_d = (Inst*)(ws + W.insts);
-  c->block_inst_d = (int*)(ws + W.block_inst);
+  c->block_tab_d = (int2*)(ws + W.block_tab);
   c->bins_d = (unsigned long long*)(ws + W.bins);
   c->max_blocks = W.max_blocks;
-  rc = set_tiles(c, c->var);
+  rc = set_tiles(c, c->var, opt->tile[2]);
   if (rc != FV_OK) {
     g_init_error = c->err;
     delete c;
@@ -675,17 +697,21 @@ int32_t fv_autotune(fv_ctx* c, int32_t reps, int32_t max_report, int32_t* tiles,
   if (reps < 1 || max_report < 0 || (max_report > 0 && (!tiles || !ms)))
     return fail(c, FV_EINVAL, "reps < 1 or null report arrays");
   if (check_loaded(c) != FV_OK) return FV_ESTATE;
-  const int nv = (int)c->vars.size();
+  // configurations: every compiled tile shape under every block schedule
+  // (one schedule for a single instance, where they coincide)
+  const int nsched = c->n_inst > 1 ? FV_SCHED_INTERLEAVED + 1 : 1;
+  const int nv = (int)c->vars.size() * nsched;
   if (n_variants) *n_variants = nv;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = hip_check(c, hipEventCreate(&e0), "event");
   if (rc == FV_OK) rc = hip_check(c, hipEventCreate(&e1), "event");
-  const int orig = c->var;
-  int best = orig;
+  const int orig = c->var, orig_sched = c->sched;
+  int best = 0;
   float best_ms = 0.0f;
   const int parity = (int)(c->step & 1);
-  for (int v = 0; v < nv && rc == FV_OK; ++v) {
-    rc = set_tiles(c, v);
+  for (int k = 0; k < nv && rc == FV_OK; ++k) {
+    const int v = k / nsched, sc = k % nsched;
+    rc = set_tiles(c, v, sc);
     if (rc != FV_OK) break;
     c->ops.stage(c, 0, parity, c->stream);  // warm-up (code object load)
     rc = hip_check(c, hipEventRecord(e0, c->stream), "event record");
@@ -697,22 +723,24 @@ int32_t fv_autotune(fv_ctx* c, int32_t reps, int32_t max_report, int32_t* tiles,
     if (rc == FV_OK) rc = hip_check(c, hipEventElapsedTime(&t, e0, e1), "event time");
     if (rc != FV_OK) break;
     t /= (float)reps;
-    if (v < max_report) {
-      tiles[2 * v] = c->vars[v].TX;
-      tiles[2 * v + 1] = c->vars[v].TY;
-      ms[v] = t;
+    if (k < max_report) {
+      tiles[3 * k] = c->vars[v].TX;
+      tiles[3 * k + 1] = c->vars[v].TY;
+      tiles[3 * k + 2] = sc;
+      ms[k] = t;
     }
-    // a shape displaces the best one listed before it only when it is at
-    // least 2 % faster, so that timing noise between shapes of equal speed
-    // does not change the choice from run to run
-    if (v == 0 || t < 0.98f * best_ms) {
+    // a configuration displaces the best one listed before it only when it
+    // is at least 2 % faster, so that timing noise between configurations of
+    // equal speed does not change the choice from run to run
+    if (k == 0 || t < 0.98f * best_ms) {
       best_ms = t;
-      best = v;
+      best = k;
     }
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  const int rc2 = set_tiles(c, rc == FV_OK ? best : orig);
+  const int rc2 = rc == FV_OK ? set_tiles(c, best / nsched, best % nsched)
+                              : set_tiles(c, orig, orig_sched);
   if (rc != FV_OK) return rc;
   if (chosen) *chosen = best;
   return rc2;

@@ -105,7 +105,7 @@ __device__ __forceinline__ int64_t xcd_block() {
 // ---------------------------------------------------------------------------
 template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH>
 __global__ void __launch_bounds__(NTH)
-stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int parity) {
+stage_kernel(const Inst* insts, const int2* block_tab, Params P, int stage, int parity) {
   using St = Stage<DIM, NM, NS, T, C, TX, TY, NTH>;
   using TL = typename St::TL;
   constexpr int NT = NTH;
@@ -113,7 +113,8 @@ stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int 
   C* sm = reinterpret_cast<C*>(smem_d);
   C* fb = sm + (size_t)St::NW * TL::NCELL;
   const int b = (int)xcd_block();
-  const int ii = block_inst[b];
+  const int2 e = block_tab[b];  // (instance, tile of that instance)
+  const int ii = e.x;
   const Inst& I = insts[ii];
   double* dts = I.dts;
   const int q = parity & 1;
@@ -121,7 +122,7 @@ stage_kernel(const Inst* insts, const int* block_inst, Params P, int stage, int 
   const double dtinv = dts_dtinv(dts, q);
   double dt = dts[DTS_DTFIX] > 0.0 ? dts[DTS_DTFIX] : P.cfl / dtinv;
   dt = fmin(dt, dts[DTS_TEND] - t);
-  const int lb = b - I.block_begin;
+  const int lb = e.y;
   const int tid = threadIdx.x;
   // stage 0: a timing run of stage 1 that leaves the time, the dt state and
   // the boundary accumulators alone (its output goes to the stage-1 buffer)

@@ -34,7 +34,7 @@ struct fv_ctx {
   hipStream_t stream = nullptr;
   std::vector<fv::Inst> insts;
   fv::Inst* insts_d = nullptr;
-  int* block_inst_d = nullptr;
+  int2* block_tab_d = nullptr;       // (instance, tile) of every stage block
   unsigned long long* bins_d = nullptr;
   int total_blocks = 0;
   long long step = 0;
@@ -42,7 +42,8 @@ struct fv_ctx {
   std::vector<fvk::Ops> vars;         // every compiled tile shape
   int var = 0;
   int max_blocks = 0;                 // capacity of the block table
-  std::vector<int> h_block_inst;
+  std::vector<int2> h_block_tab;
+  int sched = 0;                      // block order (FV_SCHED_*)
   // captured multi-step graphs, keyed by (step count, starting parity)
   static constexpr int NGRAPH = 4;
   bool use_graph = false;
@@ -98,7 +99,7 @@ Ops make_ops() {
   o.stage = [](fv_ctx* c, int stage, int parity, hipStream_t s) {
     hipLaunchKernelGGL((stage_kernel<DIM, NM, NS, T, C, TX, TY, NTH>), dim3(c->total_blocks),
                        dim3(NTH), St::smem_bytes(), s, c->insts_d,
-                       c->block_inst_d, c->P, stage, parity);
+                       c->block_tab_d, c->P, stage, parity);
   };
   return o;
 }

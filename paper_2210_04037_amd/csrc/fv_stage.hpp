@@ -39,7 +39,6 @@ struct Inst {
   int n[3];
   int tiles[3];
   int bc[3][2];
-  int block_begin;
   int nblocks;
   int bacc_off[6];  // offset (in doubles) of each boundary side's slots
   double lo[3];

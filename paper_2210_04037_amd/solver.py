@@ -135,17 +135,18 @@ class GpuSolver:
         self._c(self.lib.fv_restore(self.ctx, ctypes.c_void_p(blob.data_ptr())))
 
     def autotune(self, reps=20):
-        """Time every compiled tile shape, keep the fastest; returns
-        (chosen (tx, ty), {(tx, ty): ms per launch})."""
-        cap = 16
-        tiles = (ctypes.c_int32 * (2 * cap))()
+        """Time every compiled tile shape under every block schedule, keep
+        the fastest; returns (chosen (tx, ty, schedule),
+        {(tx, ty, schedule): ms per launch})."""
+        cap = 64
+        tiles = (ctypes.c_int32 * (3 * cap))()
         ms = (ctypes.c_float * cap)()
         nv, ch = ctypes.c_int32(), ctypes.c_int32()
         self._c(self.lib.fv_autotune(self.ctx, int(reps), cap, tiles, ms,
                                      ctypes.byref(nv), ctypes.byref(ch)))
         n = min(nv.value, cap)
-        table = {(tiles[2 * v], tiles[2 * v + 1]): ms[v] for v in range(n)}
-        return (tiles[2 * ch.value], tiles[2 * ch.value + 1]), table
+        key = lambda v: tuple(tiles[3 * v:3 * v + 3])
+        return key(ch.value), {key(v): ms[v] for v in range(n)}
 
     def fragments(self, i=0, cut=0.5, cap=None):
         """Fragment labels (nz, ny, nx) int32 (-1 outside material) and the

@@ -51,9 +51,9 @@ def _run(cases, precision):
         prim = torch.as_tensor(np.ascontiguousarray(c.prim), dtype=torch.float64).to(dev)
         ok(lib.fv_load_primitive(ctx, i, ctypes.c_void_p(prim.data_ptr())))
     ok(lib.fv_step(ctx, None, 3, None))
-    tiles = (ctypes.c_int32 * 32)()
-    ms = (ctypes.c_float * 16)()
-    ok(lib.fv_autotune(ctx, 2, 16, tiles, ms, None, None))
+    tiles = (ctypes.c_int32 * 96)()
+    ms = (ctypes.c_float * 32)()
+    ok(lib.fv_autotune(ctx, 2, 32, tiles, ms, None, None))
     ok(lib.fv_step(ctx, None, 2, None))
     nt = len(c0.mats) + c0.dim + 1
     out = (ctypes.c_double * (n * 2 * nt))()

@@ -105,10 +105,35 @@ def test_tile_shapes_give_identical_bits(precision, dim):
             assert np.array_equal(U, ref), tile
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_block_schedules_give_identical_bits(precision):
+    """Every configuration the autotuner tries on a ragged ensemble (tile
+    shape x block schedule) gives bitwise the same members."""
+    cases = [F.make_case(4, member=m, n=n) for m, n in ((0, 70), (1, 45), (2, 96))]
+    g = _solver(cases, precision=precision)
+    _, table = g.autotune(reps=2)
+    g.close()
+    assert {k[2] for k in table} == {0, 1, 2}
+    ref = None
+    for cfg in table:
+        g = _solver(cases, precision=precision, tile=cfg)
+        g.step(12)
+        U = [g.state(i) for i in range(len(cases))]
+        g.close()
+        if ref is None:
+            ref = U
+        else:
+            for i in range(len(cases)):
+                assert np.array_equal(U[i], ref[i]), (cfg, i)
+
+
 def test_unknown_tile_is_rejected():
     from paper_2210_04037_amd import abi
     with pytest.raises(abi.FvError) as e:
         _solver(F.make_case(2, n=64), tile=(24, 24))
+    assert e.value.code == abi.FV_EINVAL
+    with pytest.raises(abi.FvError) as e:
+        _solver(F.make_case(2, n=64), tile=(16, 15, 3))     # no such schedule
     assert e.value.code == abi.FV_EINVAL
 
 
