@@ -347,3 +347,25 @@ def mass_edges(lo=1.0e-6, hi=10.0, per_decade=4):
     cumulative fragment-mass histograms of the ring workloads."""
     n = int(round(np.log10(hi / lo) * per_decade)) + 1
     return [float(v) for v in np.geomspace(lo, hi, n)]
+
+
+# tiny and one-cell-wide grids: (dim, cells, boundary kind)
+DEGENERATE_GRIDS = [(2, (1, 9, 1), "transmissive"), (2, (9, 1, 1), "free"),
+                    (2, (3, 3, 1), "transmissive"), (2, (2, 5, 1), "periodic"),
+                    (1, (1, 1, 1), "transmissive"), (1, (3, 1, 1), "free"),
+                    (3, (1, 1, 6), "transmissive"), (3, (2, 3, 2), "periodic")]
+
+
+def degenerate_case(dim, n, bc, seed=5):
+    """Copper/gas mixture on a tiny grid with a seeded velocity and
+    volume-fraction field."""
+    c = uniform_case(dim, n, [COPPER, GAS], [0.7, 0.3], [8930.0, 1.0],
+                     [0.0] * dim, 1e5, bc=bc)
+    rng = np.random.default_rng(seed)
+    nm = len(c.mats)
+    shape = c.prim[0].shape
+    mom0 = 2 * nm + 2                       # first velocity row (one solid)
+    c.prim[mom0] = 50.0 * rng.standard_normal(shape)
+    c.prim[0] = 0.7 + 0.2 * rng.random(shape)
+    c.prim[1] = 1.0 - c.prim[0]
+    return c

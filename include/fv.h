@@ -51,7 +51,7 @@ extern "C" {
 /* boundary kinds, per side of each direction */
 #define FV_BC_TRANSMISSIVE 0  /* zero-gradient ghost cells */
 #define FV_BC_FREE 1          /* free surface: void outside (Section 3.1) */
-#define FV_BC_PERIODIC 2      /* both sides of the direction */
+#define FV_BC_PERIODIC 2      /* both sides of the direction; needs n >= 2 */
 
 /* material kinds */
 #define FV_MAT_SOLID 0   /* Romenskii EOS + shear modulus, Bonora damage */
@@ -72,7 +72,9 @@ typedef struct fv_ctx fv_ctx;
 
 /* Uniform grid of one instance.  dim in {1, 2, 3}; n[k] cells on [lo[k],hi[k]]
  * for k < dim (unused directions: n = 1, and their extent sets the cell
- * volume).  bc[k][0] / bc[k][1] are the lower / upper sides. */
+ * volume).  bc[k][0] / bc[k][1] are the lower / upper sides; periodic sides
+ * come in pairs, on a direction of at least 2 cells (the two-cell halo wraps
+ * once). */
 typedef struct {
   int32_t dim;
   int32_t n[3];

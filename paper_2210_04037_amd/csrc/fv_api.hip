@@ -143,6 +143,8 @@ static int validate(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
         for (int s = 0; s < 2; ++s)
           if (g.bc[k][s] < FV_BC_TRANSMISSIVE || g.bc[k][s] > FV_BC_PERIODIC) { msg = "bad boundary kind"; return FV_EINVAL; }
         if ((g.bc[k][0] == FV_BC_PERIODIC) != (g.bc[k][1] == FV_BC_PERIODIC)) { msg = "periodic sides must be paired"; return FV_EINVAL; }
+        // the two-cell halo wraps once: a periodic direction needs two cells
+        if (g.bc[k][0] == FV_BC_PERIODIC && g.n[k] < 2) { msg = "a periodic direction needs at least 2 cells"; return FV_EINVAL; }
       }
     }
     if ((int64_t)g.n[0] * g.n[1] * g.n[2] > ((int64_t)1 << 31)) { msg = "too many cells"; return FV_EINVAL; }

@@ -158,9 +158,12 @@ struct Stage {
     return (C)((m_max(th, 0.0) + cold) / xi);
   }
 
+  // Cell index along a direction of n cells for any g: the face stencils
+  // reach two cells past each side, and a tile wider than a small grid
+  // reaches further, so a periodic direction wraps modulo n.
   FV_HD static int map_index(int g, int n, int bclo, int bchi) {
-    if (g < 0) return bclo == BC_PERIODIC ? g + n : 0;
-    if (g >= n) return bchi == BC_PERIODIC ? g - n : n - 1;
+    if (g < 0) return bclo == BC_PERIODIC ? (n - 1) - (-g - 1) % n : 0;
+    if (g >= n) return bchi == BC_PERIODIC ? g % n : n - 1;
     return g;
   }
 

@@ -113,3 +113,19 @@ def test_fragment_histogram_matches_oracle_definition():
         assert lib.fv_fragment_histogram(arr, n, e, len(edges), out) == 0
         assert list(out) == Fr.mass_histogram(frags, edges)
     assert lib.fv_fragment_histogram(None, -1, None, 0, None) == abi.FV_EINVAL
+
+
+def test_periodic_direction_needs_two_cells():
+    """The two-cell halo wraps a periodic direction once, so a periodic
+    direction of one cell is rejected before any device work (it would
+    index outside the grid)."""
+    lib = _lib()
+    mats = [F.COPPER, F.GAS]
+    o = abi.options_struct("fp64")
+    for n, ok in (((1, 8, 1), False), ((2, 8, 1), True), ((8, 1, 1), False)):
+        c = F.uniform_case(2, n, mats, [0.5, 0.5], [8930.0, 1.0], [0.0, 0.0],
+                           1e5, bc="periodic")
+        g = (abi.FvGrid * 1)(abi.grid_struct(c))
+        nb = lib.fv_workspace_bytes(1, g, 2, abi.material_array(mats),
+                                    ctypes.byref(o))
+        assert (nb > 0) == ok, n

@@ -112,6 +112,16 @@ def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
     _assert_matches_oracle(case, steps, t, flag, U, L)
 
 
+@pytest.mark.parametrize("dim,n,bc", F.DEGENERATE_GRIDS)
+def test_degenerate_grids_sanitized_match_oracle(exe, tmp_path, dim, n, bc):
+    """Grids of one to a few cells per direction, where the two-cell halo
+    and the tile reach past the whole grid (a periodic one wraps more than
+    once)."""
+    case = F.degenerate_case(dim, n, bc)
+    t, flag, U, L = _run(exe, tmp_path, case, 5)
+    _assert_matches_oracle(case, 5, t, flag, U, L)
+
+
 @pytest.fixture(scope="module")
 def hencky_exe(tmp_path_factory):
     cxx = shutil.which("g++")
