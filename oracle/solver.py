@@ -5,15 +5,6 @@ SSP-RK3 stages of the hyperbolic system (Shu-Osher form,
 U1 = U + dt L(U), U2 = 3/4 U + 1/4 (U1 + dt L(U1)),
 U^{n+1} = 1/3 U + 2/3 (U2 + dt L(U2))), then the source step.  The outward
 boundary fluxes are accumulated with the matching weights 1/6, 1/6, 2/3.
-
-Step rejection (the paper gives no time-step control beyond the CFL
-number; this is the reading the kernels share): a first- or second-stage
-state with a non-finite value or a non-positive density in any cell rejects
-the step.  U, t and the outflow stay, and the step is halved once more
-(dt = CFL step / 2^k, k = self.halvings); a completed step takes one
-halving back.  The MAX_REJECTIONS-th rejection since the last step at the
-full CFL step is a non-physical state.  A dt given by the caller is never
-halved.
 """
 import numpy as np
 
@@ -23,16 +14,6 @@ from .scheme import Geometry, rhs, clamp_phi, dt_inverse
 from .source import source_step
 from .totals import interior_totals, boundary_totals
 from . import fragments as _frag
-
-
-MAX_REJECTIONS = 20
-
-
-def _bad(U, layout):
-    """Any non-finite value, or a cell whose density (sum of the phasic
-    masses) is not positive."""
-    rho = sum(U[r] for r in layout.mass)
-    return not (np.isfinite(U).all() and (rho > 0.0).all())
 
 
 class Solver:
@@ -45,8 +26,6 @@ class Solver:
         self.phi0 = case.phi0
         self.t = 0.0
         self.steps = 0
-        self.halvings = 0          # k: dt = CFL step / 2^k
-        self.rejections = 0        # since the last step at the full CFL step
         self.bacc = {}
         dx = self.geom.dx
         self.cell_volume = dx[0] * dx[1] * dx[2]
@@ -63,20 +42,9 @@ class Solver:
             else:
                 self.bacc[key] = inc
 
-    def _reject(self):
-        self.halvings += 1
-        self.rejections += 1
-        if self.rejections >= MAX_REJECTIONS:
-            raise RuntimeError("non-physical state: %d rejected steps"
-                               % self.rejections)
-        return 0.0
-
     def step(self, dt=None, t_end=None):
-        """One step; returns the dt taken, 0.0 at the end time or for a
-        rejected step (then self.rejections > 0)."""
-        fixed = dt is not None
         if dt is None:
-            dt = self.dt_cfl() / 2.0 ** self.halvings
+            dt = self.dt_cfl()
         if t_end is not None:
             dt = min(dt, t_end - self.t)
         if dt <= 0:
@@ -85,12 +53,8 @@ class Solver:
         U0 = self.U
         k1, b1 = rhs(U0, g, L, o)
         U1 = clamp_phi(U0 + dt * k1, L, o)
-        if not fixed and _bad(U1, L):
-            return self._reject()
         k2, b2 = rhs(U1, g, L, o)
         U2 = clamp_phi(0.75 * U0 + 0.25 * (U1 + dt * k2), L, o)
-        if not fixed and _bad(U2, L):
-            return self._reject()
         k3, b3 = rhs(U2, g, L, o)
         U3 = clamp_phi(U0 / 3.0 + (2.0 / 3.0) * (U2 + dt * k3), L, o)
         self._accumulate(b1, dt / 6.0)
@@ -99,17 +63,13 @@ class Solver:
         self.U = source_step(U3, self.phi0, g, L, o)
         self.t += dt
         self.steps += 1
-        if not fixed:
-            if self.halvings <= 1:
-                self.rejections = 0
-            self.halvings = max(self.halvings - 1, 0)
         return dt
 
     def run(self, t_end, max_steps=None):
         while self.t < t_end:
             if max_steps is not None and self.steps >= max_steps:
                 break
-            if self.step(t_end=t_end) <= 0 and self.rejections == 0:
+            if self.step(t_end=t_end) <= 0:
                 break
         return self
 

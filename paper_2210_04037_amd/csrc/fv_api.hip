@@ -153,7 +153,7 @@ static int validate(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
 }
 
 struct WsPlan {
-  std::vector<size_t> u1, u2, bacc, bstep, dts, wb, fb[3];
+  std::vector<size_t> u1, u2, bacc, dts, wb, fb[3];
   size_t insts = 0, block_tab = 0, bins = 0, total = 0;
   int max_blocks = 0;
 };
@@ -187,7 +187,6 @@ static void plan_ws(int32_t n_inst, const fv_grid* grids, const std::vector<Ops>
       nb += 2 * (size_t)nt * o.NC;
     }
     W.bacc.push_back(off); off += align256(nb * sizeof(double));
-    W.bstep.push_back(off); off += align256(nb * sizeof(double));
     W.dts.push_back(off); off += align256(DTS_SIZE * sizeof(double));
     // 3D passes: primitives of every cell and the face data of each direction
     W.wb.push_back(off);
@@ -383,7 +382,6 @@ int32_t fv_init(fv_ctx** out, int32_t n_inst, const fv_grid* grids, int32_t n_ma
     I.U2 = ws + W.u2[i];
     I.phi0 = phi0[i];
     I.bacc = (double*)(ws + W.bacc[i]);
-    I.bstep = (double*)(ws + W.bstep[i]);
     I.Wb = g.dim == 3 ? (void*)(ws + W.wb[i]) : nullptr;
     for (int a = 0; a < 3; ++a) I.Fb[a] = g.dim == 3 ? (void*)(ws + W.fb[a][i]) : nullptr;
     I.dts = (double*)(ws + W.dts[i]);
@@ -514,7 +512,8 @@ int32_t fv_cfl_dt(fv_ctx* c, double* dt_host) {
   const int q = (int)(c->step & 1);
   for (int i = 0; i < c->n_inst; ++i) {
     const double* d = &h[(size_t)i * DTS_SIZE];
-    dt_host[i] = dts_step(d, q, c->P.cfl);
+    double dt = d[DTS_DTFIX] > 0 ? d[DTS_DTFIX] : c->P.cfl / dts_dtinv(d, q);
+    dt_host[i] = std::fmin(dt, d[DTS_TEND] - d[DTS_T + q]);
   }
   return FV_OK;
 }

@@ -103,46 +103,6 @@ __device__ __forceinline__ int64_t xcd_block() {
 // ---------------------------------------------------------------------------
 // stage kernel
 // ---------------------------------------------------------------------------
-// Step rejection.  A stage-1 or stage-2 state with a non-finite value or a
-// non-positive density sets the step's rejection flag (DTS_REJ + parity);
-// the later stages of that step then leave the state alone, and the third
-// stage's first block keeps the time and carries the CFL inverse over with
-// one more halving of the step.  A completed step takes one halving back,
-// so the step returns to the CFL step gradually.  With a fixed dt, or at
-// DTS_MAXREJ rejections since the last step at the full CFL step, the state
-// is flagged non-physical instead.
-__device__ __forceinline__ bool step_rejected(const double* dts, int stage, bool dry, int q) {
-  return stage >= 2 && !dry && dts_bits(dts, DTS_REJ + q) != 0;
-}
-
-__device__ __forceinline__ void flag_bad(double* dts, int stage, bool dry, int q) {
-  if (dry) return;
-  if (stage == 3 || dts[DTS_DTFIX] > 0.0)
-    atomicOr(reinterpret_cast<unsigned int*>(&dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);
-  else
-    atomicOr(reinterpret_cast<unsigned int*>(&dts[DTS_REJ + q]), 1u);
-}
-
-// third stage, first block: the bookkeeping of a rejected step, or the
-// cleared flag and one halving taken back after a completed one
-__device__ __forceinline__ void close_step(double* dts, int q, bool rejected, double t,
-                                           double dtinv) {
-  dts[DTS_REJ + 1 - q] = 0.0;
-  const double k = dts[DTS_NREJ];
-  if (!rejected) {
-    dts[DTS_NREJ] = k > 0.0 ? k - 1.0 : 0.0;
-    if (k <= 1.0) dts[DTS_RTOT] = 0.0;
-    return;
-  }
-  dts[DTS_T + 1 - q] = t;
-  dts_set_dtinv(dts, 1 - q, dtinv);
-  dts[DTS_NREJ] = k + 1.0;
-  const double n = dts[DTS_RTOT] + 1.0;
-  dts[DTS_RTOT] = n;
-  if (n >= (double)DTS_MAXREJ)
-    atomicOr(reinterpret_cast<unsigned int*>(&dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);
-}
-
 template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH>
 __global__ void __launch_bounds__(NTH)
 stage_kernel(const Inst* insts, const int2* block_tab, Params P, int stage, int parity) {
@@ -160,7 +120,8 @@ stage_kernel(const Inst* insts, const int2* block_tab, Params P, int stage, int 
   const int q = parity & 1;
   const double t = dts[DTS_T + q];
   const double dtinv = dts_dtinv(dts, q);
-  const double dt = dts_step(dts, q, P.cfl);
+  double dt = dts[DTS_DTFIX] > 0.0 ? dts[DTS_DTFIX] : P.cfl / dtinv;
+  dt = fmin(dt, dts[DTS_TEND] - t);
   const int lb = e.y;
   const int tid = threadIdx.x;
   // stage 0: a timing run of stage 1 that leaves the time, the dt state and
@@ -178,9 +139,6 @@ stage_kernel(const Inst* insts, const int2* block_tab, Params P, int stage, int 
     dts[DTS_T + 1 - q] = t + dt;
     dts_set_dtinv(dts, 1 - q, 0.0);
   }
-  const bool rejected = step_rejected(dts, stage, dry, q);
-  if (stage == 3 && lb == 0 && tid == 0) close_step(dts, q, rejected, t, dtinv);
-  if (rejected) return;
   typename St::Ctx cx;
   cx.I = &I;
   cx.P = P;
@@ -234,7 +192,7 @@ stage_kernel(const Inst* insts, const int2* block_tab, Params P, int stage, int 
   if (own) {
     bool bad = false;
     cflv = St::finish_cell(cx, g, acc, UA, UN, &bad);
-    if (bad) flag_bad(dts, stage, dry, q);
+    if (bad) atomicOr(reinterpret_cast<unsigned int*>(&dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);
   }
   // blocks are dispatched round-robin over the XCDs: blockIdx.x & 7 is the
   // block's XCD and picks its CFL slot
@@ -319,7 +277,8 @@ __device__ __forceinline__ bool setup3(const Inst& I, const Params& P, int stage
   const double* dts = I.dts;
   t = dts[DTS_T + q];
   dtinv = dts_dtinv(dts, q);
-  dt = dts_step(dts, q, P.cfl);
+  dt = dts[DTS_DTFIX] > 0.0 ? dts[DTS_DTFIX] : P.cfl / dtinv;
+  dt = fmin(dt, dts[DTS_TEND] - t);
   const bool dry = stage == 0;
   if (dry) stage = 1;
   cx.I = &I;
@@ -334,7 +293,7 @@ __device__ __forceinline__ bool setup3(const Inst& I, const Params& P, int stage
   cx.base = U;
   cx.src = stage == 1 ? U : (stage == 2 ? (const T*)I.U1 : (const T*)I.U2);
   cx.out = stage == 1 ? (T*)I.U1 : (stage == 2 ? (T*)I.U2 : (T*)I.U);
-  return dt > 0.0 && !step_rejected(dts, stage, dry, q);
+  return dt > 0.0;
 }
 
 __device__ __forceinline__ int64_t nfaces3(const Inst& I, int a) {
@@ -445,9 +404,6 @@ __global__ void __launch_bounds__(256) finish3_kernel(const Inst* insts, int ii,
     I.dts[DTS_T + 1 - q] = go ? t + dt : t;
     dts_set_dtinv(I.dts, 1 - q, go ? 0.0 : dtinv);
   }
-  const bool rejected = step_rejected(I.dts, cx.stage, dry, q);
-  if (cx.stage == 3 && blockIdx.x == 0 && threadIdx.x == 0 && (go || rejected))
-    close_step(I.dts, q, rejected, t, dtinv);
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double cflv = 0.0;
   if (go && g < I.ncell) {
@@ -486,7 +442,7 @@ __global__ void __launch_bounds__(256) finish3_kernel(const Inst* insts, int ii,
     }
     bool bad = false;
     cflv = St::finish_cell(cx, g, acc, &bad);
-    if (bad) flag_bad(I.dts, cx.stage, dry, q);
+    if (bad) atomicOr(reinterpret_cast<unsigned int*>(&I.dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);
   }
   if (cx.stage == 3 && go)
     block_max_to<256>(cflv, scratch, &I.dts[dts_slot(1 - q, blockIdx.x & (DTS_NSLOT - 1))]);

@@ -33,7 +33,6 @@ struct Inst {
   void* U2;         // stage-2 result (workspace)
   const void* phi0; // perturbation field on the initial mesh
   double* bacc;     // outward boundary flux accumulators
-  double* bstep;    // the current step's share of them, committed in stage 3
   void* Wb;         // 3D: primitives of every cell (workspace)
   void* Fb[3];      // 3D: face data of each direction (workspace)
   double* dts;      // dt state, see DTS_* below
@@ -48,25 +47,14 @@ struct Inst {
 };
 
 // dt state of an instance (doubles).  First line: t[2] (DTS_T), t_end,
-// dt_fixed, flags, the step-rejection flag of each parity (DTS_REJ, set by
-// a stage that produced a non-finite value or a non-positive density), the
-// halving exponent k of the time step (DTS_NREJ: dt = CFL step / 2^k) and
-// the rejections since the last step at the full CFL step (DTS_RTOT).  The CFL inverse of each parity is the maximum of
+// dt_fixed, flags.  The CFL inverse of each parity is the maximum of
 // DTS_NSLOT partial maxima, each on a 128-byte line of its own: a block
 // folds its maximum into the slot of the XCD it runs on with an integer
 // atomicMax on the bits (an unsigned max of non-negative doubles is their
 // floating max).  A single address would take the atomics of every block of
 // a launch one after another.
-enum { DTS_T = 2, DTS_TEND = 4, DTS_DTFIX = 5, DTS_FLAG = 6, DTS_REJ = 8, DTS_NREJ = 10,
-       DTS_RTOT = 11, DTS_MAXREJ = 20, DTS_NSLOT = 8,
+enum { DTS_T = 2, DTS_TEND = 4, DTS_DTFIX = 5, DTS_FLAG = 6, DTS_NSLOT = 8,
        DTS_LINE = 16, DTS_SIZE = DTS_LINE * (1 + 2 * DTS_NSLOT) };
-// the flags word of slot k of the dt state as an unsigned integer
-FV_HD unsigned dts_bits(const double* dts, int k) {
-  union { double d; unsigned long long u; } v;
-  v.d = dts[k];
-  return (unsigned)v.u;
-}
-
 // slot k of parity q
 FV_HD int dts_slot(int q, int k) { return DTS_LINE * (1 + q * DTS_NSLOT + k); }
 // CFL inverse of parity q
@@ -75,14 +63,6 @@ FV_HD double dts_dtinv(const double* dts, int q) {
   for (int k = 1; k < DTS_NSLOT; ++k) m = m > dts[dts_slot(q, k)] ? m : dts[dts_slot(q, k)];
   return m;
 }
-// time step of parity q: the CFL step halved DTS_NREJ times, or the fixed
-// step; clamped to the end time
-FV_HD double dts_step(const double* dts, int q, double cfl) {
-  if (dts[DTS_DTFIX] > 0.0) return m_min(dts[DTS_DTFIX], dts[DTS_TEND] - dts[DTS_T + q]);
-  const double dt = ldexp(cfl / dts_dtinv(dts, q), -(int)dts[DTS_NREJ]);
-  return m_min(dt, dts[DTS_TEND] - dts[DTS_T + q]);
-}
-
 // the slots of parity q hold v (first slot) and nothing else
 FV_HD void dts_set_dtinv(double* dts, int q, double v) {
   for (int k = 0; k < DTS_NSLOT; ++k) dts[dts_slot(q, k)] = k == 0 ? v : 0.0;
@@ -531,23 +511,13 @@ struct Stage {
         for (int l = 0; l < NM; ++l) phif[l] = 0;
       }
     }
-    // outward boundary flux accumulation, RK3 weights 1/6, 1/6, 2/3: the
-    // step's share is gathered in bstep and added to the accumulators in
-    // stage 3, so that a rejected step leaves them as they were (each
-    // boundary face belongs to one thread of one launch per stage)
+    // outward boundary flux accumulation, RK3 weights 1/6, 1/6, 2/3
     if (!periodic && (lo_b || hi_b) && !cx.dry) {
       const C w = cx.stage == 3 ? (C)(2.0 / 3.0) : (C)(1.0 / 6.0);
       const C sgn = lo_b ? (C)-1 : (C)1;
-      const int64_t off = I.bacc_off[2 * a + (hi_b ? 1 : 0)] + (int64_t)bslot * NC;
-      double* acc = I.bacc + off;
-      double* stp = I.bstep + off;
+      double* acc = I.bacc + I.bacc_off[2 * a + (hi_b ? 1 : 0)] + (int64_t)bslot * NC;
 #pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const double c = (double)(w * cx.dt * (sgn * F[q]));
-        if (cx.stage == 1) stp[q] = c;
-        else if (cx.stage == 2) stp[q] += c;
-        else acc[q] += stp[q] + c;
-      }
+      for (int q = 0; q < NC; ++q) acc[q] += (double)(w * cx.dt * (sgn * F[q]));
     }
     // store
     const IDX NF = fstride;

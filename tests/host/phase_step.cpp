@@ -63,7 +63,7 @@ struct Run {
   Params P;
   Inst I;
   int64_t nc = 0;
-  std::vector<double> U, U1, U2, phi0, bacc, bstep, dts, Wb, Fb[3];
+  std::vector<double> U, U1, U2, phi0, bacc, dts, Wb, Fb[3];
 };
 
 template <int DIM, int NM, int NS>
@@ -94,7 +94,6 @@ static void setup(Run& r, const fv_grid* g, const fv_material* mats, const fv_op
     off += nt * L::NC;
   }
   r.bacc.assign(off, 0.0);
-  r.bstep.assign(off, NAN);
   r.dts.assign(DTS_SIZE, 0.0);
   r.I.ncell = r.nc;
   r.I.U = r.U.data();
@@ -102,7 +101,6 @@ static void setup(Run& r, const fv_grid* g, const fv_material* mats, const fv_op
   r.I.U2 = r.U2.data();
   r.I.phi0 = r.phi0.data();
   r.I.bacc = r.bacc.data();
-  r.I.bstep = r.bstep.data();
   r.I.dts = r.dts.data();
   if (DIM == 3) {
     r.Wb.assign(L::NW * r.nc, NAN);
@@ -128,7 +126,7 @@ static void setup(Run& r, const fv_grid* g, const fv_material* mats, const fv_op
 // and clears its CFL slot, as the device does
 static double stage_dt(Run& r, int stage, int q) {
   const double t = r.dts[DTS_T + q];
-  const double dt = dts_step(r.dts.data(), q, r.P.cfl);
+  const double dt = std::min(r.P.cfl / dts_dtinv(r.dts.data(), q), r.dts[DTS_TEND] - t);
   if (stage == 1) {
     r.dts[DTS_T + 1 - q] = t + dt;
     dts_set_dtinv(r.dts.data(), 1 - q, 0.0);

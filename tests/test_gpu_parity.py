@@ -181,18 +181,12 @@ def test_deterministic_bitwise():
 
 
 def test_nonphysical_state_is_reported():
-    """A NaN written into the state: each step is rejected (no smaller step
-    cures it) and the twentieth rejection in a row raises the flag."""
     import torch
     from paper_2210_04037_amd import abi
     case = F.make_case(1, n=64)
     g = _gpu(case)
-    t0 = g.time()[0]
     g.states[0][4, 0, 0, 10] = float("nan")     # rho u of one cell
     torch.cuda.synchronize()
-    g.step(19)
-    assert g.time()[0] == t0
-    g.cfl_dt()                                  # not flagged yet
     g.step(1)
     with pytest.raises(abi.FvError) as ei:
         g.cfl_dt()
@@ -302,27 +296,23 @@ def test_unloaded_state_is_a_call_order_error():
     ref.close()
 
 
-@pytest.mark.parametrize("which,precision", [("ring", "fp64"), ("member1", "fp64")])
-def test_runs_reach_their_end_time(which, precision):
-    """The FP64 form carries the 1024^2 ring and ensemble member 1 (768^2)
-    through fracture to their 40 us end time without the non-physical flag
-    (the FP32-bulk form stops short of it on a third-stage state that a
-    rejection cannot undo).
-    Late in these runs the rarefied gas behind the fragments leaving through
-    the sides holds stretches with principal ratios beyond 1e8 (whose Hencky
-    strain the kernels form from det V), and a full step can empty a
-    near-vacuum cell in its first stage: that step is rejected and retried
-    at half the step."""
+@pytest.mark.parametrize("which", ["ring", "member1"])
+def test_fp64_runs_reach_their_end_time(which):
+    """The FP64 form carries the 1024^2 ring (about 11300 steps) and ensemble
+    member 1 (768^2, about 27000 steps) through fracture to their 40 us end
+    time without the non-physical flag.  Late in these runs the rarefied gas
+    behind the fragments holds stretches with principal ratios beyond 1e8,
+    whose Hencky strain the kernels form from det V (a strain formed from
+    the entries of V V^T alone gave NaN there)."""
     from paper_2210_04037_amd.solver import GpuSolver
     case = F.make_case(2) if which == "ring" else F.make_case(4, member=1)
-    print(f"[end time] {which} {case.n[0]}^2 {precision} to {case.t_end:.1e} s", flush=True)
-    g = GpuSolver(case, precision=precision, use_graph=True)
+    print(f"[end time] {which} {case.n[0]}^2 fp64 to {case.t_end:.1e} s", flush=True)
+    g = GpuSolver(case, precision="fp64", use_graph=True)
     g.step(0, t_end=[case.t_end])
     steps = 0
     while g.time()[0] < case.t_end:
         g.step(500)
         steps += 500
-        g.cfl_dt()                           # raises on the device flag
         assert steps < 40000
     assert g.cfl_dt()[0] >= 0.0              # raises on the device flag
     lab, frags = g.fragments(0, 0.5)

@@ -375,49 +375,3 @@ def test_radial_return_closed_form():
     assert abs(np.linalg.det(Vn) - 1.0) < 1e-14
     # total energy untouched
     assert np.all(U[L.energy] == s.U[L.energy])
-
-
-def test_step_rejection_keeps_the_state_and_halves_dt(monkeypatch):
-    """A rejected step leaves U, t and the outflow alone; the retry takes
-    half the CFL step (a quarter after two rejections); each completed step
-    takes one halving back, and the rejection count clears once the step is
-    back at the full CFL step."""
-    import oracle.solver as OS
-    case = F.make_case(1, n=40)
-    o = Solver(case)
-    o.step()
-    dt_cfl = o.dt_cfl()
-    U, t, bacc = o.U.copy(), o.t, {k: v.copy() for k, v in o.bacc.items()}
-    calls = {"n": 0}
-    real = OS._bad
-
-    def bad_twice(Ux, L):
-        calls["n"] += 1
-        return True if calls["n"] <= 2 else real(Ux, L)
-
-    monkeypatch.setattr(OS, "_bad", bad_twice)
-    assert o.step() == 0.0 and o.rejections == 1
-    assert o.step() == 0.0 and o.rejections == 2
-    assert np.array_equal(o.U, U) and o.t == t
-    assert all(np.array_equal(o.bacc[k], bacc[k]) for k in bacc)
-    assert o.step() == dt_cfl / 4.0 and o.halvings == 1 and o.rejections == 2
-    assert o.t == t + dt_cfl / 4.0
-    dt2 = o.dt_cfl()
-    assert o.step() == dt2 / 2.0 and o.halvings == 0 and o.rejections == 0
-
-
-def test_step_rejection_of_a_lasting_bad_state():
-    """A negative density that no smaller step can cure: MAX_REJECTIONS
-    rejections make the state non-physical; the state and time never change
-    meanwhile."""
-    import oracle.solver as OS
-    case = F.make_case(1, n=40)
-    L = Layout(1, case.mats)
-    o = Solver(case)
-    o.U[L.mass[0]][..., 20] = -1.0
-    U, t = o.U.copy(), o.t
-    for k in range(1, OS.MAX_REJECTIONS):
-        assert o.step() == 0.0 and o.rejections == k
-    assert np.array_equal(o.U, U) and o.t == t
-    with pytest.raises(RuntimeError):
-        o.step()
