@@ -246,7 +246,7 @@ def fragment_report(cases, chunk):
         g.step(0, t_end=t_end)
         n = max(chunk, 1) * 10
         steps, flag = 0, None
-        while np.any(g.time() < t_end):
+        while np.any(g.time() < t_end) and steps < 200000:
             ck = g.checkpoint()
             try:
                 g.step(n)

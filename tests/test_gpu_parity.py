@@ -313,6 +313,7 @@ def test_fp64_runs_reach_their_end_time(which):
     while g.time()[0] < case.t_end:
         g.step(500)
         steps += 500
+        g.cfl_dt()                           # raises on the device flag
         assert steps < 40000
     assert g.cfl_dt()[0] >= 0.0              # raises on the device flag
     lab, frags = g.fragments(0, 0.5)
