@@ -73,8 +73,11 @@ typedef struct fv_ctx fv_ctx;
 /* Uniform grid of one instance.  dim in {1, 2, 3}; n[k] cells on [lo[k],hi[k]]
  * for k < dim (unused directions: n = 1, and their extent sets the cell
  * volume).  bc[k][0] / bc[k][1] are the lower / upper sides; periodic sides
- * come in pairs, on a direction of at least 2 cells (the two-cell halo wraps
- * once). */
+ * come in pairs, on a direction of at least 2 cells (a one-cell periodic
+ * direction would be its own neighbour).  An instance holds at most 2^31
+ * cells; in 1D and 2D one field of its state (cells times the element size)
+ * holds at most 4 GiB, i.e. 2^30 cells in FP32-bulk and 2^29 in FP64, so the
+ * stage kernels address a cell with a 32-bit offset (FV_EINVAL beyond). */
 typedef struct {
   int32_t dim;
   int32_t n[3];

@@ -30,9 +30,9 @@ def hipcc():
 
 # per translation unit: the FP32-bulk kernels take fast reciprocals and
 # approximate transcendental functions, the FP64 form keeps IEEE arithmetic
-# The stage kernels walk tiles in a loop whose body holds the whole cell
-# update; hoisting its constants (EOS and log/exp coefficients) out of that
-# loop would keep them in registers across it and spill, so machine-level
+# The face and halo phases of the stage kernels are loops over items; hoisting
+# their constants (EOS and log/exp coefficients) out of them keeps those in
+# registers across the whole phase for no gain, so machine-level
 # loop-invariant code motion is off for the two kernel units.
 KERNEL_UNIT = ["-mllvm", "-disable-machine-licm"]
 UNITS = [

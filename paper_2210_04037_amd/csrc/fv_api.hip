@@ -143,11 +143,17 @@ static int validate(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
         for (int s = 0; s < 2; ++s)
           if (g.bc[k][s] < FV_BC_TRANSMISSIVE || g.bc[k][s] > FV_BC_PERIODIC) { msg = "bad boundary kind"; return FV_EINVAL; }
         if ((g.bc[k][0] == FV_BC_PERIODIC) != (g.bc[k][1] == FV_BC_PERIODIC)) { msg = "periodic sides must be paired"; return FV_EINVAL; }
-        // the two-cell halo wraps once: a periodic direction needs two cells
+        // a one-cell periodic direction would be its own neighbour
         if (g.bc[k][0] == FV_BC_PERIODIC && g.n[k] < 2) { msg = "a periodic direction needs at least 2 cells"; return FV_EINVAL; }
       }
     }
-    if ((int64_t)g.n[0] * g.n[1] * g.n[2] > ((int64_t)1 << 31)) { msg = "too many cells"; return FV_EINVAL; }
+    const int64_t nc = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    if (nc > ((int64_t)1 << 31)) { msg = "too many cells"; return FV_EINVAL; }
+    // 1D and 2D stage kernels address a cell within a field by a 32-bit byte offset
+    const int64_t elem = opt->precision == FV_FP64 ? 8 : 4;
+    if (g.dim <= 2 && nc * elem > ((int64_t)1 << 32)) {
+      msg = "1D/2D instance too large: one state field must fit in 4 GiB"; return FV_EINVAL;
+    }
   }
   return FV_OK;
 }

@@ -23,6 +23,19 @@
 
 namespace fv {
 
+#if defined(__HIP_DEVICE_COMPILE__)
+// A pointer that every lane of the wave holds alike, returned as a value the
+// compiler keeps in scalar registers: address arithmetic on it then stays
+// scalar instead of being folded into 64-bit per-lane addresses.
+template <class E>
+__device__ __forceinline__ E* wave_uniform(E* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (E*)(((uint64_t)hi << 32) | lo);
+}
+#endif
+
 // ----------------------------------------------------------------------------
 // scalar helpers (double and float overloads)
 // ----------------------------------------------------------------------------

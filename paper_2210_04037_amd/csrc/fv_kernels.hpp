@@ -105,7 +105,8 @@ __device__ __forceinline__ int64_t xcd_block() {
 // ---------------------------------------------------------------------------
 template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH>
 __global__ void __launch_bounds__(NTH)
-stage_kernel(const Inst* insts, const int2* block_tab, Params P, int stage, int parity) {
+stage_kernel(const Inst* __restrict__ insts, const int2* __restrict__ block_tab, Params P,
+             int stage, int parity) {
   using St = Stage<DIM, NM, NS, T, C, TX, TY, NTH>;
   using TL = typename St::TL;
   constexpr int NT = NTH;

@@ -179,10 +179,39 @@ struct Stage {
     return (int64_t)gy * I.n[0] + gx;
   }
 
+  // Element g of field f of an instance's state.  In 1D and 2D a field holds
+  // at most 4 GiB (checked when a context is made), so the cell's byte offset
+  // within it fits 32 bits.  On the device the field's base is then made a
+  // wave-uniform global address: each access is a global load or store with
+  // a scalar base and a 32-bit lane offset, not a flat access with a 64-bit
+  // address per lane.
+  static constexpr bool OFF32 = DIM <= 2;
+  FV_HD static T ld(const T* base, int f, int64_t ncell, int64_t g) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (OFF32) {
+      using GB = __attribute__((address_space(1))) const char;
+      GB* fb = (GB*)wave_uniform(base + (int64_t)f * ncell);
+      return *(__attribute__((address_space(1))) const T*)(fb + (uint32_t)g * (uint32_t)sizeof(T));
+    }
+#endif
+    return base[(int64_t)f * ncell + g];
+  }
+  FV_HD static void st(T* base, int f, int64_t ncell, int64_t g, T v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (OFF32) {
+      using GB = __attribute__((address_space(1))) char;
+      GB* fb = (GB*)wave_uniform(base + (int64_t)f * ncell);
+      *(__attribute__((address_space(1))) T*)(fb + (uint32_t)g * (uint32_t)sizeof(T)) = v;
+      return;
+    }
+#endif
+    base[(int64_t)f * ncell + g] = v;
+  }
+
   FV_HD static void load_state(const Ctx& cx, const T* src, int64_t g, C* U) {
     const Inst& I = *cx.I;
 #pragma unroll
-    for (int f = 0; f < S; ++f) U[f] = (C)src[(int64_t)f * I.ncell + g];
+    for (int f = 0; f < S; ++f) U[f] = (C)ld(src, f, I.ncell, g);
   }
 
   FV_HD static void load_cell(const Ctx& cx, C* sm, int tc) {
@@ -964,7 +993,7 @@ struct Stage {
     for (int l = 0; l < NM; ++l) rho += Un[L::MASS + l];
     *bad = nan || !(rho > 0.0);
 #pragma unroll
-    for (int f = 0; f < S; ++f) cx.out[(int64_t)f * I.ncell + g] = (T)Un[f];
+    for (int f = 0; f < S; ++f) st(cx.out, f, I.ncell, g, (T)Un[f]);
     return cfl;
   }
 };

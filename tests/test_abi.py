@@ -44,6 +44,27 @@ def test_state_fields_and_workspace():
     assert lib.fv_workspace_bytes(1, g, 2, mats, ctypes.byref(bad)) == 0
 
 
+def test_two_dimensional_field_size_limit():
+    """In 1D and 2D one state field may hold up to 4 GiB: 2^29 cells in
+    FP64, 2^30 in FP32-bulk; one row more is rejected."""
+    lib = _lib()
+    c = F.make_case(2, n=64)
+    mats = abi.material_array(c.mats)
+    for prec, rows in (("fp64", 1 << 14), ("fp32", 1 << 15)):
+        o = abi.options_struct(prec)
+        g = (abi.FvGrid * 1)(abi.grid_struct(c))
+        g[0].n[0], g[0].n[1] = 1 << 15, rows
+        assert lib.fv_workspace_bytes(1, g, 2, mats, ctypes.byref(o)) > 0
+        g[0].n[1] = rows + 1
+        assert lib.fv_workspace_bytes(1, g, 2, mats, ctypes.byref(o)) == 0
+        ctx = ctypes.c_void_p()
+        ptrs = (ctypes.c_void_p * 1)(ctypes.c_void_p(0x1000))
+        rc = lib.fv_init(ctypes.byref(ctx), 1, g, 2, mats, ctypes.byref(o),
+                         ptrs, ptrs, ctypes.c_void_p(0x1000), 1 << 30, None)
+        assert rc == abi.FV_EINVAL
+        assert b"4 GiB" in lib.fv_last_error(None)
+
+
 def test_init_rejects_invalid_arguments():
     lib = _lib()
     c = F.make_case(2, n=32)
