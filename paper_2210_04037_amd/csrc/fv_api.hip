@@ -242,6 +242,7 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
   P.weno_eps = opt->weno_eps;
   P.c_min2 = 1.0e-6;
   P.phi_fp64_cut = opt->phi_fp64_cut;
+  set_float_constants(P);
 }
 
 // Select tile shape v: per-instance tile counts, the block -> instance table,

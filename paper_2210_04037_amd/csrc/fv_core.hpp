@@ -83,6 +83,10 @@ struct MatP {
   double nu;         // Poisson ratio of the undamaged moduli
   double bonA;       // alpha_B (Dc - D0)^(1/alpha_B) / ln(eps_c / eps_th)
   double bonExp;     // (alpha_B - 1) / alpha_B
+  // the closure constants rounded to float on the host, for the FP32-bulk
+  // closures: the kernels read them as arguments in scalar registers instead
+  // of converting the doubles per wave (the same rounding either way)
+  float f_rho0, f_K0, f_alpha, f_G0, f_beta, f_Gamma0, f_invGamma, f_Dcrit_eff;
 };
 
 struct Params {
@@ -92,7 +96,26 @@ struct Params {
   double weno_eps;
   double c_min2;
   double phi_fp64_cut;
+  float f_weno_eps, f_c_min2, f_phi_fp64_cut, f_pad;
 };
+
+// Host: fill the float copies once the double parameters are set.
+inline void set_float_constants(Params& P) {
+  for (MatP& m : P.mat) {
+    m.f_rho0 = (float)m.rho0; m.f_K0 = (float)m.K0; m.f_alpha = (float)m.alpha;
+    m.f_G0 = (float)m.G0; m.f_beta = (float)m.beta; m.f_Gamma0 = (float)m.Gamma0;
+    m.f_invGamma = (float)m.invGamma; m.f_Dcrit_eff = (float)m.Dcrit_eff;
+  }
+  P.f_weno_eps = (float)P.weno_eps;
+  P.f_c_min2 = (float)P.c_min2;
+  P.f_phi_fp64_cut = (float)P.phi_fp64_cut;
+}
+
+// A parameter in the closure precision C: the double itself, or its float
+// copy.
+template <class C> FV_HD C cst(double d, float f);
+template <> FV_HD double cst<double>(double d, float) { return d; }
+template <> FV_HD float cst<float>(double, float f) { return f; }
 
 // ----------------------------------------------------------------------------
 // field layout of the conserved state (Section 2.1 equation order)
@@ -181,16 +204,17 @@ template <class C>
 FV_HD RefT<C> ref_terms(const MatP& m, C rho, C J2, C D) {
   RefT<C> r;
   if (m.kind != 0) { r.rho_eref = 0; r.pref = 0; r.rho_dpref = 0; r.G = 0; return r; }
-  const C a = (C)m.alpha;
-  const C eta = rho / (C)m.rho0;
+  const C a = cst<C>(m.alpha, m.f_alpha);
+  const C rho0 = cst<C>(m.rho0, m.f_rho0);
+  const C eta = rho / rho0;
   const C ea = powi_or(eta, a, m.alpha_i);
   const C ea1 = ea * eta;
-  const C K0 = (C)m.K0;
-  const C rho_ec = rho * K0 / ((C)2 * (C)m.rho0 * a * a) * (ea - (C)1) * (ea - (C)1);
+  const C K0 = cst<C>(m.K0, m.f_K0);
+  const C rho_ec = rho * K0 / ((C)2 * rho0 * a * a) * (ea - (C)1) * (ea - (C)1);
   const C pc = K0 / a * ea1 * (ea - (C)1);
   const C rho_dpc = K0 / a * ea1 * (((C)2 * a + (C)1) * ea - (a + (C)1));
-  const C Gt = (C)m.G0 * powi_or(eta, (C)m.beta + (C)1, m.beta1_i);
-  const C b = (C)m.beta;
+  const C b = cst<C>(m.beta, m.f_beta);
+  const C Gt = cst<C>(m.G0, m.f_G0) * powi_or(eta, b + (C)1, m.beta1_i);
   const C w = (C)1 - D;
   r.rho_eref = w * (rho_ec + Gt * J2);
   r.pref = w * (pc + b * Gt * J2);
@@ -201,7 +225,8 @@ FV_HD RefT<C> ref_terms(const MatP& m, C rho, C J2, C D) {
 
 template <class C>
 FV_HD C shear_modulus_undamaged(const MatP& m, C rho) {
-  return (C)m.G0 * powi_or(rho / (C)m.rho0, (C)m.beta + (C)1, m.beta1_i);
+  return cst<C>(m.G0, m.f_G0) *
+         powi_or(rho / cst<C>(m.rho0, m.f_rho0), cst<C>(m.beta, m.f_beta) + (C)1, m.beta1_i);
 }
 
 // ----------------------------------------------------------------------------
@@ -225,7 +250,7 @@ constexpr double PHI_TRACE = 1.0e-6;
 
 template <class C>
 FV_HD C closure_density(const MatP& m, C phi_l, C rho_l) {
-  return phi_l < (C)PHI_TRACE ? (C)m.rho0 : rho_l;
+  return phi_l < (C)PHI_TRACE ? cst<C>(m.rho0, m.f_rho0) : rho_l;
 }
 
 template <int NM, int NS, class C>
@@ -236,7 +261,7 @@ FV_HD void mix_terms(const Params& P, const C* phi, const C* rho_l, const C* D,
   for (int l = 0; l < NM; ++l) {
     const C Dl = l < NS ? D[l < NS ? l : 0] : (C)0;
     mx.t[l] = ref_terms<C>(P.mat[l], closure_density(P.mat[l], phi[l], rho_l[l]), J2, Dl);
-    mx.xi += phi[l] * (C)P.mat[l].invGamma;
+    mx.xi += phi[l] * cst<C>(P.mat[l].invGamma, P.mat[l].f_invGamma);
   }
 }
 
@@ -249,7 +274,7 @@ FV_HD C mix_pressure(const Params& P, const C* phi, const Mix<NM, NS, C>& mx,
 #pragma unroll
   for (int l = 0; l < NM; ++l) {
     th = th - phi[l] * mx.t[l].rho_eref;
-    cold = cold + phi[l] * mx.t[l].pref * (C)P.mat[l].invGamma;
+    cold = cold + phi[l] * mx.t[l].pref * cst<C>(P.mat[l].invGamma, P.mat[l].f_invGamma);
   }
   return (m_max(th, (C)0) + cold) / mx.xi;
 }
@@ -259,7 +284,8 @@ FV_HD C mix_energy(const Params& P, const C* phi, const Mix<NM, NS, C>& mx, C p)
   C re = mx.xi * p;
 #pragma unroll
   for (int l = 0; l < NM; ++l)
-    re = re + phi[l] * mx.t[l].rho_eref - phi[l] * mx.t[l].pref * (C)P.mat[l].invGamma;
+    re = re + phi[l] * mx.t[l].rho_eref -
+         phi[l] * mx.t[l].pref * cst<C>(P.mat[l].invGamma, P.mat[l].f_invGamma);
   return re;
 }
 
@@ -279,16 +305,16 @@ FV_HD C mix_sound(const Params& P, const C* phi, const Mix<NM, NS, C>& mx, C p,
   Gmix = 0;
 #pragma unroll
   for (int l = 0; l < NM; ++l) {
-    const C g = (C)P.mat[l].Gamma0;
+    const C g = cst<C>(P.mat[l].Gamma0, P.mat[l].f_Gamma0);
     // thermal term non-negative: a state below the cold curve (a gas
     // fraction pulled into tension) must not collapse the wave speed
-    acc += phi[l] * (C)P.mat[l].invGamma *
+    acc += phi[l] * cst<C>(P.mat[l].invGamma, P.mat[l].f_invGamma) *
            (mx.t[l].rho_dpref + (g + (C)1) * m_max(p - mx.t[l].pref, (C)0));
     Gmix += phi[l] * mx.t[l].G;
   }
   const C cb2 = solid_frac<NM>(phi) * acc / (mx.xi * rho);
   const C c2 = m_max(cb2, (C)0) + (C)(4.0 / 3.0) * Gmix / rho;
-  return m_sqrt(m_max(c2, (C)P.c_min2));
+  return m_sqrt(m_max(c2, cst<C>(P.c_min2, P.f_c_min2)));
 }
 
 // ----------------------------------------------------------------------------

@@ -28,6 +28,7 @@ bool select_ops_fp32(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t
     return true;
   }
   if (dim == 2 && nm == 1 && ns == 1) {
+    FV_VARN(2, 1, 1, float, float, 16, 14, 256)
     FV_VARN(2, 1, 1, float, float, 16, 15, 256)
     FV_VARN(2, 1, 1, float, float, 32, 7, 256)
     FV_VARN(2, 1, 1, float, float, 15, 16, 256)
@@ -37,6 +38,7 @@ bool select_ops_fp32(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t
     return true;
   }
   if (dim == 2 && nm == 2 && ns == 1) {
+    FV_VARN(2, 2, 1, float, float, 16, 14, 256)
     FV_VARN(2, 2, 1, float, float, 16, 15, 256)
     FV_VARN(2, 2, 1, float, float, 32, 7, 256)
     FV_VARN(2, 2, 1, float, float, 15, 16, 256)

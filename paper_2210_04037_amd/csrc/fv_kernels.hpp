@@ -103,8 +103,19 @@ __device__ __forceinline__ int64_t xcd_block() {
 // ---------------------------------------------------------------------------
 // stage kernel
 // ---------------------------------------------------------------------------
+// Three 256-thread FP32-bulk 2D blocks share a CU (160 KiB of LDS) when the
+// tile's LDS fits a third of it (16 x 14: 52 KiB), and then each lane may
+// hold at most 168 registers: the bound makes the compiler keep to that
+// rather than lose the third block.  Larger tiles keep the default.
+template <class St, int DIM, class C, int NTH>
+constexpr int stage_waves_per_eu() {
+  return (DIM == 2 && sizeof(C) == 4 && NTH == 256 && 3 * St::smem_bytes() <= 160 * 1024) ? 3
+                                                                                          : 1;
+}
+
 template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH>
-__global__ void __launch_bounds__(NTH)
+__global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(
+    stage_waves_per_eu<Stage<DIM, NM, NS, T, C, TX, TY, NTH>, DIM, C, NTH>())))
 stage_kernel(const Inst* __restrict__ insts, const int2* __restrict__ block_tab, Params P,
              int stage, int parity) {
   using St = Stage<DIM, NM, NS, T, C, TX, TY, NTH>;

@@ -263,7 +263,7 @@ struct Stage {
     bool island = false;
     if (sizeof(C) == 4) {
 #pragma unroll
-      for (int l = 0; l < NM; ++l) island = island || phi[l] < (C)cx.P.phi_fp64_cut;
+      for (int l = 0; l < NM; ++l) island = island || phi[l] < cst<C>(cx.P.phi_fp64_cut, cx.P.f_phi_fp64_cut);
     }
     if (island) p = island_pressure(cx.P, U, mx);
     else p = mix_pressure<NM, NS, C>(cx.P, phi, mx, rho_e);
@@ -274,7 +274,7 @@ struct Stage {
     C crit = 0;
 #pragma unroll
     for (int s = 0; s < NS; ++s)
-      if (D[s] >= (C)crit_level(cx.P.mat[s])) crit = 1;
+      if (D[s] >= cst<C>(crit_level(cx.P.mat[s]), cx.P.mat[s].f_Dcrit_eff)) crit = 1;
     const IDX NCELL = wstride;
 #pragma unroll
     for (int l = 0; l < NM; ++l) {
@@ -480,7 +480,7 @@ struct Stage {
       Vf[q] = up ? vl : (dn ? vr : (C)0.5 * (vl + vr));
     }
     const C ext = (C)(I.dx[a] * I.n[a]);
-    const C weps = (C)P.weno_eps * ext * ext;
+    const C weps = cst<C>(P.weno_eps, P.f_weno_eps) * ext * ext;
     C XL[DIM], XR[DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
@@ -877,7 +877,7 @@ struct Stage {
     mix_terms<NM, NS, C>(P, phic, rlc, Dc, J2n, mx2);
     bool isl = false;
 #pragma unroll
-    for (int l = 0; l < NM; ++l) isl = isl || phic[l] < (C)P.phi_fp64_cut;
+    for (int l = 0; l < NM; ++l) isl = isl || phic[l] < cst<C>(P.phi_fp64_cut, P.f_phi_fp64_cut);
     C p2;
     if (sizeof(C) == 8 || !isl) {
       p2 = mix_pressure<NM, NS, C>(P, phic, mx2, (C)rho_e);

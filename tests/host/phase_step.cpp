@@ -14,6 +14,8 @@
 // Input (binary, native endian): fv_grid, int32 n_mat, n_mat fv_material,
 // fv_options, int64 S, int64 ncell, int32 steps, int32 tile_x, then the
 // primitive state (S x ncell doubles, field-major) and phi0 (ncell doubles).
+// tile_x picks the 2D two-material tile: 32 (32 x 8), 16 (16 x 15 cells on
+// 256 threads), 14 (16 x 14 cells on 256 threads), else 8 x 4.
 // Output: time, device flag, then the conserved state (S x ncell doubles).
 #include <algorithm>
 #include <cassert>
@@ -57,6 +59,7 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
   P.weno_eps = opt->weno_eps;
   P.c_min2 = 1.0e-6;
   P.phi_fp64_cut = opt->phi_fp64_cut;
+  set_float_constants(P);
 }
 
 struct Run {
@@ -355,6 +358,9 @@ int main(int argc, char** argv) {
     // more threads than interior cells: 16 x 15 cells, 256 threads
     setup<2, 2, 1>(r, &g, m, &o, P, Z);
     step_tiles<2, 2, 1, 16, 15, 256>(r, nsteps);
+  } else if (g.dim == 2 && tx == 14) {
+    setup<2, 2, 1>(r, &g, m, &o, P, Z);
+    step_tiles<2, 2, 1, 16, 14, 256>(r, nsteps);
   } else if (g.dim == 2) {
     setup<2, 2, 1>(r, &g, m, &o, P, Z);
     step_tiles<2, 2, 1, 8, 4>(r, nsteps);

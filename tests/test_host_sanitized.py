@@ -90,6 +90,7 @@ def _assert_matches_oracle(case, steps, t, flag, U, L):
 
 @pytest.mark.parametrize("which,steps", [
     ("spall1d", 12), ("ring2d", 4), ("ring2d_wide", 3), ("ring2d_spare", 3),
+    ("ring2d_spare14", 3),
     ("shell3d", 2),
     ("impact3d", 2)])
 def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
@@ -104,6 +105,9 @@ def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
     elif which == "ring2d_spare":
         case = F.make_case(2, n=37)            # 16 x 15 tiles on 256 threads
         tile_x = 16
+    elif which == "ring2d_spare14":
+        case = F.make_case(2, n=35)            # 16 x 14 tiles on 256 threads
+        tile_x = 14
     elif which == "shell3d":
         case = F.make_case(3, n=10)
     else:
