@@ -196,14 +196,15 @@ template <int DIM> FV_HD int hk_j(int q) {
 //   rho dp_ref/drho = (1-D)(rho dp~_c/drho + beta (beta+1) G~ J^2),
 // with the Romenskii cold energy e~_c = K0/(2 rho0 a^2)(eta^a - 1)^2 (the
 // denominator read as 2 rho0 a^2 so that a -> 0 is the log EOS) and shear
-// modulus G~ = G0 eta^(beta+1).  Gas: all zero.
+// modulus G~ = G0 eta^(beta+1).  Gas: all zero.  Solids come first in a
+// material list (checked when a context is made), so material l is a solid
+// exactly when l < NS and the kernels decide the kind at compile time.
 template <class C>
 struct RefT { C rho_eref, pref, rho_dpref, G; };
 
 template <class C>
-FV_HD RefT<C> ref_terms(const MatP& m, C rho, C J2, C D) {
+FV_HD RefT<C> solid_ref_terms(const MatP& m, C rho, C J2, C D) {
   RefT<C> r;
-  if (m.kind != 0) { r.rho_eref = 0; r.pref = 0; r.rho_dpref = 0; r.G = 0; return r; }
   const C a = cst<C>(m.alpha, m.f_alpha);
   const C rho0 = cst<C>(m.rho0, m.f_rho0);
   const C eta = rho / rho0;
@@ -259,8 +260,12 @@ FV_HD void mix_terms(const Params& P, const C* phi, const C* rho_l, const C* D,
   mx.xi = 0;
 #pragma unroll
   for (int l = 0; l < NM; ++l) {
-    const C Dl = l < NS ? D[l < NS ? l : 0] : (C)0;
-    mx.t[l] = ref_terms<C>(P.mat[l], closure_density(P.mat[l], phi[l], rho_l[l]), J2, Dl);
+    if (l < NS) {
+      mx.t[l] = solid_ref_terms<C>(P.mat[l], closure_density(P.mat[l], phi[l], rho_l[l]), J2,
+                                   D[l < NS ? l : 0]);
+    } else {
+      mx.t[l].rho_eref = 0; mx.t[l].pref = 0; mx.t[l].rho_dpref = 0; mx.t[l].G = 0;
+    }
     mx.xi += phi[l] * cst<C>(P.mat[l].invGamma, P.mat[l].f_invGamma);
   }
 }
