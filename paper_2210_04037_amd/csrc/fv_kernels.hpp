@@ -128,46 +128,30 @@ stage_kernel(const Inst* __restrict__ insts, const int2* __restrict__ block_tab,
   const int2 e = block_tab[b];  // (instance, tile of that instance)
   const int ii = e.x;
   const Inst& I = insts[ii];
-  double* dts = I.dts;
-  const int q = parity & 1;
-  const double t = dts[DTS_T + q];
-  const double dtinv = dts_dtinv(dts, q);
-  double dt = dts[DTS_DTFIX] > 0.0 ? dts[DTS_DTFIX] : P.cfl / dtinv;
-  dt = fmin(dt, dts[DTS_TEND] - t);
   const int lb = e.y;
   const int tid = threadIdx.x;
   // stage 0: a timing run of stage 1 that leaves the time, the dt state and
   // the boundary accumulators alone (its output goes to the stage-1 buffer)
   const bool dry = stage == 0;
   if (dry) stage = 1;
-  if (!(dt > 0.0)) {
-    if (stage == 1 && !dry && lb == 0 && tid == 0) {
-      dts[DTS_T + 1 - q] = t;
-      dts_set_dtinv(dts, 1 - q, dtinv);
-    }
-    return;
-  }
-  if (stage == 1 && !dry && lb == 0 && tid == 0) {
-    dts[DTS_T + 1 - q] = t + dt;
-    dts_set_dtinv(dts, 1 - q, 0.0);
-  }
   typename St::Ctx cx;
   cx.I = &I;
   cx.P = P;
   cx.stage = stage;
   cx.dry = dry;
-  cx.parity = q;
+  cx.parity = parity & 1;
   cx.bx = lb % I.tiles[0];
   cx.by = lb / I.tiles[0];
-  cx.dt = (C)dt;
   const T* U = (const T*)I.U;
   cx.base = U;
   cx.src = stage == 1 ? U : (stage == 2 ? (const T*)I.U1 : (const T*)I.U2);
   cx.out = stage == 1 ? (T*)I.U1 : (stage == 2 ? (T*)I.U2 : (T*)I.U);
 
-  // Every global load of the thread goes out at once: its own cell's stage
-  // input (kept for the update), the cell's U^n (stages 2 and 3) and its
-  // first halo cell; the primitives are formed after they arrive.
+  // Every global load of the thread goes out at once, ahead of the time-step
+  // test so that the two do not wait one after the other: its own cell's
+  // stage input (kept for the update), the cell's U^n (stages 2 and 3) and
+  // its first halo cell (in bounds whatever the step).  The primitives are
+  // formed after they arrive.
   constexpr int S = St::S;
   const bool has_a = NT == TL::NOWN || tid < TL::NOWN;
   const int tcA = has_a ? TL::own(tid) : 0;
@@ -180,6 +164,26 @@ stage_kernel(const Inst* __restrict__ insts, const int2* __restrict__ block_tab,
   const bool has_h = tid < TL::NHALO;
   const int tcH = has_h ? TL::halo_cell(tid) : 0;
   if (has_h) St::load_state(cx, cx.src, St::tile_global(cx, tcH), UH);
+
+  double* dts = I.dts;
+  const int q = parity & 1;
+  const double t = dts[DTS_T + q];
+  const double dtinv = dts_dtinv(dts, q);
+  double dt = dts[DTS_DTFIX] > 0.0 ? dts[DTS_DTFIX] : P.cfl / dtinv;
+  dt = fmin(dt, dts[DTS_TEND] - t);
+  // an instance at its end time takes no step
+  if (!(dt > 0.0)) {
+    if (stage == 1 && !dry && lb == 0 && tid == 0) {
+      dts[DTS_T + 1 - q] = t;
+      dts_set_dtinv(dts, 1 - q, dtinv);
+    }
+    return;
+  }
+  if (stage == 1 && !dry && lb == 0 && tid == 0) {
+    dts[DTS_T + 1 - q] = t + dt;
+    dts_set_dtinv(dts, 1 - q, 0.0);
+  }
+  cx.dt = (C)dt;
   if (has_a) St::template prims_of<int>(cx, UA, sm, TL::NCELL, tcA);
   if (has_h) St::template prims_of<int>(cx, UH, sm, TL::NCELL, tcH);
   for (int h = tid + NT; h < TL::NHALO; h += NT) St::load_cell(cx, sm, TL::halo_cell(h));
