@@ -99,6 +99,13 @@ struct Params {
   float f_weno_eps, f_c_min2, f_phi_fp64_cut, f_pad;
 };
 
+// Host: the derived constants of a solid, from its own fields.
+inline void set_solid_constants(MatP& q) {
+  q.nu = (3.0 * q.K0 - 2.0 * q.G0) / (2.0 * (3.0 * q.K0 + q.G0));
+  q.bonA = q.balpha * pow(q.Dcrit - q.D0, 1.0 / q.balpha) / log(q.eps_c / q.eps_th);
+  q.bonExp = (q.balpha - 1.0) / q.balpha;
+}
+
 // Host: fill the float copies once the double parameters are set.
 inline void set_float_constants(Params& P) {
   for (MatP& m : P.mat) {

@@ -48,10 +48,7 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
     if (q.kind == 0) {
       q.alpha_i = small_int(m.alpha);
       q.beta1_i = small_int(m.beta + 1.0);
-      q.nu = (3.0 * m.K0 - 2.0 * m.G0) / (2.0 * (3.0 * m.K0 + m.G0));
-      q.bonA = m.bonora_alpha * std::pow(m.D_crit - m.D0, 1.0 / m.bonora_alpha) /
-               std::log(m.eps_c / m.eps_th);
-      q.bonExp = (m.bonora_alpha - 1.0) / m.bonora_alpha;
+      set_solid_constants(q);
     }
   }
   P.cfl = opt->cfl;

@@ -175,3 +175,48 @@ def test_hencky_of_strongly_sheared_stretch(hencky_exe, dim):
         kappa = sig.max() / sig.min()
         bound = (1e-11 + 4 * np.finfo(float).eps * kappa) * np.max(np.abs(ref))
         assert np.max(np.abs(H - ref)) <= bound, (s, np.max(np.abs(H - ref)), bound)
+
+
+@pytest.fixture(scope="module")
+def damage_exe(tmp_path_factory):
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    out = str(tmp_path_factory.mktemp("dm") / "damage_check")
+    cmd = [cxx, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-Wall", "-Wno-unknown-pragmas",
+           "-Werror", "-o", out, os.path.join(HERE, "host", "damage_check.cpp")]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-4000:]
+    return out
+
+
+def test_damage_closures_match_oracle(damage_exe):
+    """The kernels' threshold strain and Bonora damage rate (Section 2.2),
+    with the solid's derived constants formed as the library forms them,
+    equal the oracle's to 1e-13 over the triaxialities, damage levels and
+    strains the source step meets (R from 2/3 to 12, D up to just below
+    D_crit, eps_p from 1e-4 to 2)."""
+    from oracle import closures as Cl
+    m = dict(F.COPPER)
+    rng = np.random.default_rng(11)
+    R = np.concatenate([[2.0 / 3.0, 1.0, 1.5, 12.0], rng.uniform(0.67, 12.0, 60)])
+    D = np.concatenate([[0.0, 0.5, m["D_crit"] * (1 - 1e-9), 0.3],
+                        rng.uniform(0.0, m["D_crit"] * 0.999, 60)])
+    eps = np.concatenate([[1e-4, 0.08, 0.16, 2.0], 10 ** rng.uniform(-4, 0.3, 60)])
+    head = " ".join(repr(float(m[k])) for k in
+                    ("eps_th", "eps_c", "n_hard", "bonora_alpha", "D_crit", "D0",
+                     "K0", "G0"))
+    body = "\n".join(f"{float(a)!r} {float(b)!r} {float(c)!r}"
+                      for a, b, c in zip(R, D, eps))
+    r = subprocess.run([damage_exe], input=head + "\n" + body + "\n",
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr[-4000:]
+    got = np.array([[float(t) for t in row.split()]
+                    for row in r.stdout.strip().split("\n")])
+    thr = np.array([Cl.eps_threshold(a, m) for a in R])
+    rate = Cl.bonora_dD_deps(D, eps, R, m)
+    assert np.allclose(got[:, 0], thr, rtol=1e-13, atol=0)
+    assert np.allclose(got[:, 1], rate, rtol=1e-13, atol=0)
+    # R = 1 reduces the threshold to eps_th itself
+    assert got[1, 0] == pytest.approx(m["eps_th"], rel=1e-14)
