@@ -114,7 +114,22 @@ def cpu_baseline(case, seconds=15.0):
     return {"value": w * w * steps / wall, "unit": "cell-updates/s",
             "cores": 1, "kind": "oracle",
             "sample": f"{w}x{w} window of the 1024^2 ring workload through "
-                      f"the annulus, {steps} steps, single thread"}
+                      f"the annulus, {steps} steps, single thread",
+            "host": host_cpu()}
+
+
+def host_cpu():
+    """Model name and logical CPU count of the host the oracle ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
 
 
 def _step_chunked(g, n, chunk):
