@@ -167,10 +167,10 @@ stage_kernel(const Inst* __restrict__ insts, const int2* __restrict__ block_tab,
 
   double* dts = I.dts;
   const int q = parity & 1;
-  const double t = dts[DTS_T + q];
-  const double dtinv = dts_dtinv(dts, q);
-  double dt = dts[DTS_DTFIX] > 0.0 ? dts[DTS_DTFIX] : P.cfl / dtinv;
-  dt = fmin(dt, dts[DTS_TEND] - t);
+  double t, dtinv, dtfix, tend;
+  read_dt_state(dts, q, t, dtinv, dtfix, tend);
+  double dt = dtfix > 0.0 ? dtfix : P.cfl / dtinv;
+  dt = fmin(dt, tend - t);
   // an instance at its end time takes no step
   if (!(dt > 0.0)) {
     if (stage == 1 && !dry && lb == 0 && tid == 0) {
@@ -290,11 +290,10 @@ __device__ __forceinline__ bool setup3(const Inst& I, const Params& P, int stage
                                        typename St::Ctx& cx, double& t, double& dtinv,
                                        double& dt) {
   const int q = parity & 1;
-  const double* dts = I.dts;
-  t = dts[DTS_T + q];
-  dtinv = dts_dtinv(dts, q);
-  dt = dts[DTS_DTFIX] > 0.0 ? dts[DTS_DTFIX] : P.cfl / dtinv;
-  dt = fmin(dt, dts[DTS_TEND] - t);
+  double dtfix, tend;
+  read_dt_state(I.dts, q, t, dtinv, dtfix, tend);
+  dt = dtfix > 0.0 ? dtfix : P.cfl / dtinv;
+  dt = fmin(dt, tend - t);
   const bool dry = stage == 0;
   if (dry) stage = 1;
   cx.I = &I;

@@ -63,6 +63,24 @@ FV_HD double dts_dtinv(const double* dts, int q) {
   for (int k = 1; k < DTS_NSLOT; ++k) m = m > dts[dts_slot(q, k)] ? m : dts[dts_slot(q, k)];
   return m;
 }
+// The words of parity q a stage launch reads: its time, its CFL inverse, the
+// fixed dt and the end time.  Earlier launches wrote them and a launch writes
+// only parity 1 - q and the flag, so on the device they are read as
+// wave-uniform global words, which the compiler turns into scalar loads.
+FV_HD void read_dt_state(const double* dts, int q, double& t, double& dtinv, double& dtfix,
+                         double& tend) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  using GD = __attribute__((address_space(1))) const double;
+  GD* d = (GD*)wave_uniform(dts);
+#else
+  const double* d = dts;
+#endif
+  t = d[DTS_T + q];
+  dtinv = d[dts_slot(q, 0)];
+  for (int k = 1; k < DTS_NSLOT; ++k) dtinv = dtinv > d[dts_slot(q, k)] ? dtinv : d[dts_slot(q, k)];
+  dtfix = d[DTS_DTFIX];
+  tend = d[DTS_TEND];
+}
 // the slots of parity q hold v (first slot) and nothing else
 FV_HD void dts_set_dtinv(double* dts, int q, double v) {
   for (int k = 0; k < DTS_NSLOT; ++k) dts[dts_slot(q, k)] = k == 0 ? v : 0.0;
