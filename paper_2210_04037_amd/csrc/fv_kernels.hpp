@@ -125,7 +125,9 @@ stage_kernel(const Inst* __restrict__ insts, const int2* __restrict__ block_tab,
   C* sm = reinterpret_cast<C*>(smem_d);
   C* fb = sm + (size_t)St::NW * TL::NCELL;
   const int b = (int)xcd_block();
-  const int2 e = block_tab[b];  // (instance, tile of that instance)
+  // (instance, tile of that instance); a single instance passes no table
+  // and its blocks are its tiles in order
+  const int2 e = block_tab ? block_tab[b] : make_int2(0, b);
   const int ii = e.x;
   const Inst& I = insts[ii];
   const int lb = e.y;

@@ -99,7 +99,8 @@ Ops make_ops() {
   o.stage = [](fv_ctx* c, int stage, int parity, hipStream_t s) {
     hipLaunchKernelGGL((stage_kernel<DIM, NM, NS, T, C, TX, TY, NTH>), dim3(c->total_blocks),
                        dim3(NTH), St::smem_bytes(), s, c->insts_d,
-                       c->block_tab_d, c->P, stage, parity);
+                       c->n_inst == 1 ? (const int2*)nullptr : c->block_tab_d, c->P, stage,
+                       parity);
   };
   return o;
 }
