@@ -166,7 +166,10 @@ int32_t fv_primitive(fv_ctx* ctx, int32_t inst, void* prim);
 
 /* Time step of every instance from the CFL reduction of its current state
  * (Courant number times the inverse of the largest sum over directions of
- * (|u_d| + c) / dx_d), clamped to its end time.  dt_host: [n_inst] out.
+ * (|u_d| + c) / dx_d), clamped to its end time.  The explicit update of
+ * Section 3 advances at a time step set by a CFL number, which every test of
+ * Section 4 states (0.3 to 0.4); c is the longitudinal mixture sound speed of
+ * the closures of Sections 2.2 and 2.3.  dt_host: [n_inst] out.
  * Synchronises the stream; returns FV_ENONPHYS if the device flag is set. */
 int32_t fv_cfl_dt(fv_ctx* ctx, double* dt_host);
 
@@ -186,10 +189,13 @@ int32_t fv_step(fv_ctx* ctx, const double* dt_host, int32_t n_steps,
 /* Simulated time of every instance, t_host [n_inst] out.  Synchronises. */
 int32_t fv_time(fv_ctx* ctx, double* t_host);
 
-/* Conservation totals.  out: [n_inst][2 * (N + dim + 1)] doubles: the
- * interior totals of phi_l rho_l (N), rho u_i (dim) and rho E over the cells
- * times the cell volume, then the cumulative outward flux of the same
- * quantities through the domain boundary.  Each sum is exact before its one
+/* Conservation totals of the quantities whose equations Section 2.1 writes in
+ * conservation form (phasic mass, momentum, total energy); Section 3.1 opens
+ * void instead of deleting critically damaged cells so that fracture keeps
+ * them, and these sums are the check.  out: [n_inst][2 * (N + dim + 1)]
+ * doubles: the interior totals of phi_l rho_l (N), rho u_i (dim) and rho E
+ * over the cells times the cell volume, then the cumulative outward flux of
+ * the same quantities through the domain boundary.  Each sum is exact before its one
  * final rounding (an integer superaccumulator), so it equals the correctly
  * rounded sum of the same values.  Synchronises; FV_ENONPHYS if flagged. */
 int32_t fv_totals(fv_ctx* ctx, double* out);

@@ -222,7 +222,6 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
     q.Gamma0 = m.Gamma0; q.yield = m.yield; q.Dcrit = m.D_crit; q.D0 = m.D0;
     q.eps_th = m.eps_th; q.eps_c = m.eps_c; q.balpha = m.bonora_alpha;
     q.nhard = m.n_hard; q.pgate = m.p_gate;
-    q.Dcrit_eff = m.D_crit * (1.0 - 1.0e-6);
     q.invGamma = 1.0 / m.Gamma0;
     auto small_int = [](double v) {
       const double r = std::round(v);
@@ -615,6 +614,8 @@ int32_t fv_restore(fv_ctx* c, const void* src) {
   if (rc != FV_OK) return rc;
   c->step = (long long)hdr[2];
   for (int i = 0; i < c->n_inst; ++i) c->loaded[i] = 1;
+  // the restored dt state may hold a fixed step
+  c->dtfix_set = true;
   return FV_OK;
 }
 
@@ -622,7 +623,9 @@ int32_t fv_step(fv_ctx* c, const double* dt_host, int32_t n_steps, const double*
   if (!c) return FV_EINVAL;
   if (n_steps < 0) return fail(c, FV_EINVAL, "n_steps < 0");
   if (check_loaded(c) != FV_OK) return FV_ESTATE;
-  if (dt_host || t_end) {
+  // A NULL dt_host asks for the CFL step: a fixed step set by an earlier call
+  // (or restored from a checkpoint) is cleared first.
+  if (dt_host || t_end || c->dtfix_set) {
     // fixed step and end time of every instance (DTS_DTFIX, DTS_TEND)
     int rc = hip_check(c, hipStreamSynchronize(c->stream), "sync before parameter write");
     if (rc != FV_OK) return rc;
@@ -642,6 +645,8 @@ int32_t fv_step(fv_ctx* c, const double* dt_host, int32_t n_steps, const double*
     }
     rc = hip_check(c, hipStreamSynchronize(c->stream), "sync after parameter write");
     if (rc != FV_OK) return rc;
+    c->dtfix_set = false;
+    for (int i = 0; dt_host && i < c->n_inst; ++i) c->dtfix_set = c->dtfix_set || dt_host[i] > 0;
   }
   if (n_steps == 0) return FV_OK;
   const int p0 = (int)(c->step & 1);

@@ -76,9 +76,11 @@ struct MatP {
   double rho0, K0, alpha, G0, beta, Gamma0;
   double yield, Dcrit, D0, eps_th, eps_c, balpha, nhard, pgate;
   // host-derived constants
-  double Dcrit_eff;    // D_crit (1 - 1e-6): critical test up to the rounding of
-                       // the advected ratio (phi rho D)/(phi rho) in FP32
-                       // storage, the same in both precision forms
+  // Critical level of the Section 3.1 test D >= D_crit, which holds up to the
+  // rounding of the advected ratio (phi rho D)/(phi rho) of a clamped cell:
+  double Dcrit_eff;    // double storage: D_crit (1 - 1e-9)
+  double Dcrit_bulk;   // float storage (FP32-bulk policy): D_crit (1 - 1e-6),
+                       // about fifteen float ulps of D_crit
   double invGamma;   // 1 / Gamma0
   double nu;         // Poisson ratio of the undamaged moduli
   double bonA;       // alpha_B (Dc - D0)^(1/alpha_B) / ln(eps_c / eps_th)
@@ -101,6 +103,8 @@ struct Params {
 
 // Host: the derived constants of a solid, from its own fields.
 inline void set_solid_constants(MatP& q) {
+  q.Dcrit_eff = q.Dcrit * (1.0 - 1.0e-9);
+  q.Dcrit_bulk = q.Dcrit * (1.0 - 1.0e-6);
   q.nu = (3.0 * q.K0 - 2.0 * q.G0) / (2.0 * (3.0 * q.K0 + q.G0));
   q.bonA = q.balpha * pow(q.Dcrit - q.D0, 1.0 / q.balpha) / log(q.eps_c / q.eps_th);
   q.bonExp = (q.balpha - 1.0) / q.balpha;
@@ -111,7 +115,7 @@ inline void set_float_constants(Params& P) {
   for (MatP& m : P.mat) {
     m.f_rho0 = (float)m.rho0; m.f_K0 = (float)m.K0; m.f_alpha = (float)m.alpha;
     m.f_G0 = (float)m.G0; m.f_beta = (float)m.beta; m.f_Gamma0 = (float)m.Gamma0;
-    m.f_invGamma = (float)m.invGamma; m.f_Dcrit_eff = (float)m.Dcrit_eff;
+    m.f_invGamma = (float)m.invGamma; m.f_Dcrit_eff = (float)m.Dcrit_bulk;
   }
   P.f_weno_eps = (float)P.weno_eps;
   P.f_c_min2 = (float)P.c_min2;

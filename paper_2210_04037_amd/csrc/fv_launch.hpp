@@ -52,6 +52,7 @@ struct fv_ctx {
   int gkey[NGRAPH] = {};              // 2 * n_steps + parity, 0 = empty
   int gnext = 0;                      // slot replaced next
   std::vector<double> h_dt, h_tend;   // staging for async copies
+  bool dtfix_set = false;             // a fixed dt may be set on the device
   std::vector<char> loaded;           // state written (load_primitive / reset)
   std::vector<double> h_ck;           // checkpoint header staging
   std::string err;

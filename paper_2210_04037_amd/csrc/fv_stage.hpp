@@ -149,9 +149,10 @@ struct Stage {
   };
 
   // critical-damage level: the advected ratio (phi rho D)/(phi rho)
-  // returns D_crit only to the storage rounding; one level for both
-  // precision forms, so that they take this discontinuous decision alike
-  FV_HD static double crit_level(const MatP& m) { return m.Dcrit_eff; }
+  // returns D_crit only to the rounding of the storage precision T
+  FV_HD static double crit_level(const MatP& m) {
+    return sizeof(T) == 8 ? m.Dcrit_eff : m.Dcrit_bulk;
+  }
 
   // FP64 island of the FP32-bulk policy: the mixture pressure inversion of a
   // cell holding a trace volume fraction, with the phasic masses, energy and
@@ -761,7 +762,10 @@ struct Stage {
     for (int k = 0; k < DIM; ++k) {
       const int nk = I.n[k];
       double s = (X[k] - (I.lo[k] + 0.5 * I.dx[k])) / I.dx[k];
-      s = s < 0.0 ? 0.0 : (s > (double)(nk - 1) ? (double)(nk - 1) : s);
+      // clamped to the initial cell-centre span; a NaN coordinate (a state
+      // the non-physical check flags after this step) maps to the first
+      // centre, so the index below is always defined and in range
+      s = s >= 0.0 ? (s > (double)(nk - 1) ? (double)(nk - 1) : s) : 0.0;
       double fl = floor(s);
       const double top = nk >= 2 ? (double)(nk - 2) : 0.0;
       if (fl > top) fl = top;

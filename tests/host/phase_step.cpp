@@ -39,7 +39,6 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
     q.Gamma0 = m.Gamma0; q.yield = m.yield; q.Dcrit = m.D_crit; q.D0 = m.D0;
     q.eps_th = m.eps_th; q.eps_c = m.eps_c; q.balpha = m.bonora_alpha;
     q.nhard = m.n_hard; q.pgate = m.p_gate;
-    q.Dcrit_eff = m.D_crit * (1.0 - 1.0e-6);
     q.invGamma = 1.0 / m.Gamma0;
     auto small_int = [](double v) {
       const double r = std::round(v);
