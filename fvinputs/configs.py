@@ -315,6 +315,46 @@ def make_case(config, n=None, member=None, t_end=None):
     raise ValueError(f"unknown workload {config}")
 
 
+def spall_strip(dim, n_long=100, n_trans=8, bump=0.2e-3, v=200.0, seed=None,
+                t_end=3.0e-6):
+    """Plate impact on a 2D or 3D strip, for fracture checks off the 1D line:
+    the 1D spall workload (10 mm, copper with gate pressure -1.5 GPa, free
+    x-ends, phi0 ~ U(0.95, 1.05) per cell) widened to n_trans cells of the
+    same size in y (and z), periodic there.  The flyer's impact face is
+    curved, x < 2 mm + bump cos(2 pi y / W) (cos of y and z in 3D), so the
+    spall plane and the faces it opens vary across the strip."""
+    dx = 0.01 / n_long
+    W = n_trans * dx
+    lo = (0.0, 0.0, 0.0)
+    hi = (0.01, W if dim >= 2 else 1.0, W if dim >= 3 else 1.0)
+    grid = (n_long, n_trans if dim >= 2 else 1, n_trans if dim >= 3 else 1)
+    mats = [_copper(-1.5e9)]
+
+    def face(Y, Z):
+        c = np.cos(2 * np.pi * Y / W)
+        if dim >= 3:
+            c = 0.5 * (c + np.cos(2 * np.pi * Z / W))
+        return 0.002 + bump * c
+
+    def ind(X, Y, Z):
+        return np.ones_like(X, dtype=bool)
+
+    def vel(X, Y, Z):
+        out = [np.where(X < face(Y, Z), v, 0.0)]
+        out += [np.zeros_like(X)] * (dim - 1)
+        return out
+
+    frac, u = _subsample(dim, grid, lo, hi, ind, vel, mats[0]["rho0"], 1.0)
+    prim = _assemble(dim, mats, frac, u, P_ATM, grid, lo, hi)
+    sd = CONFIG_SEEDS[1] + 100 * dim if seed is None else seed
+    phi0 = uniform_field((grid[2], grid[1], grid[0]), 0.05, sd)
+    bc = (("free", "free"),) + tuple(
+        ("periodic", "periodic") if k < dim else ("transmissive",) * 2
+        for k in (1, 2))
+    return Case(f"spall{dim}d_strip", dim, grid, lo, hi, bc, mats, prim, phi0,
+                t_end)
+
+
 def uniform_case(dim, n, mats, phi, rho, u, p, bc="periodic", vbar=None,
                  phi0=1.0, lo=None, hi=None, t_end=1.0):
     """A spatially uniform primitive state (used for invariance checks)."""

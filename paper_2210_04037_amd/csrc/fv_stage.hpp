@@ -561,11 +561,12 @@ struct Stage {
     }
     // outward boundary flux accumulation, RK3 weights 1/6, 1/6, 2/3
     if (!periodic && (lo_b || hi_b) && !cx.dry) {
-      const C w = cx.stage == 3 ? (C)(2.0 / 3.0) : (C)(1.0 / 6.0);
-      const C sgn = lo_b ? (C)-1 : (C)1;
+      // the weights in double, as the cell update applies them
+      const double wdt = (cx.stage == 3 ? 2.0 / 3.0 : 1.0 / 6.0) * (double)cx.dt;
+      const double sgn = lo_b ? -1.0 : 1.0;
       double* acc = I.bacc + I.bacc_off[2 * a + (hi_b ? 1 : 0)] + (int64_t)bslot * NC;
 #pragma unroll
-      for (int q = 0; q < NC; ++q) acc[q] += (double)(w * cx.dt * (sgn * F[q]));
+      for (int q = 0; q < NC; ++q) acc[q] += wdt * (sgn * (double)F[q]);
     }
     // store
     const IDX NF = fstride;
@@ -991,17 +992,16 @@ struct Stage {
   FV_HD static double finish_cell(const Ctx& cx, int64_t g, const C* acc, const C* us,
                                   const C* ub, bool* bad) {
     const Inst& I = *cx.I;
+    // The third stage's weights 1/3 and 2/3 are applied in double: rounded
+    // to float they would not sum to one (2/3 rounds up by 3e-8), and every
+    // cell's mass, momentum and energy would grow by that fraction each step.
     double Un[S];
 #pragma unroll
     for (int f = 0; f < S; ++f) {
       const C v = us[f] + cx.dt * acc[f];
-      C o;
-      if (cx.stage == 1) {
-        o = v;
-      } else {
-        o = cx.stage == 2 ? (C)0.75 * ub[f] + (C)0.25 * v : ub[f] / (C)3 + (C)(2.0 / 3.0) * v;
-      }
-      Un[f] = (double)o;
+      if (cx.stage == 1) Un[f] = (double)v;
+      else if (cx.stage == 2) Un[f] = (double)((C)0.75 * ub[f] + (C)0.25 * v);
+      else Un[f] = ((double)ub[f] + 2.0 * (double)v) / 3.0;
     }
 #pragma unroll
     for (int l = 0; l < NM; ++l) Un[L::PHI + l] = m_clamp(Un[L::PHI + l], cx.P.phi_floor, 1.0);

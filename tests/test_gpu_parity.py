@@ -60,7 +60,7 @@ def test_spall_1d_parity_through_fracture():
     g, o = _run_pair(case, 400)
     U = g.state(0)
     L = Layout(1, case.mats)
-    assert np.max(o.U[L.dmg[0]] / o.U[L.mass[0]]) >= 0.9 * (1 - 1e-6)
+    assert np.max(o.U[L.dmg[0]] / o.U[L.mass[0]]) >= 0.9 * (1 - 1e-9)
     err = _field_errors(U, o.U)
     assert err.max() < 1e-7, err
     # same cells opened to void
@@ -266,7 +266,7 @@ def test_full_size_ring_long_run_stays_physical(precision):
     assert 0.3 * 5.66e3 * t < np.median(eps) < 3.0 * 5.66e3 * t
     # the radial stretching of the initial u ~ r field puts the wall in
     # hydrostatic tension, so damage may start locally, but it stays rare
-    crit = W[L.dmg[0]][solid] >= 0.9 * (1 - 1e-6)
+    crit = W[L.dmg[0]][solid] >= 0.9 * (1 - 1e-9)
     print(f"[long] median eps {np.median(eps):.4f} critical cells "
           f"{crit.sum()} of {solid.sum()}", flush=True)
     assert crit.mean() < 0.01
@@ -296,18 +296,31 @@ def test_unloaded_state_is_a_call_order_error():
     ref.close()
 
 
-@pytest.mark.parametrize("which", ["ring", "member1"])
-def test_fp64_runs_reach_their_end_time(which):
-    """The FP64 form carries the 1024^2 ring (about 11300 steps) and ensemble
-    member 1 (768^2, about 27000 steps) through fracture to their 40 us end
-    time without the non-physical flag.  Late in these runs the rarefied gas
-    behind the fragments holds stretches with principal ratios beyond 1e8,
-    whose Hencky strain the kernels form from det V (a strain formed from
-    the entries of V V^T alone gave NaN there)."""
+FP32_END_TIME_SKIP = (
+    "FP32-bulk raises the non-physical flag before 40 us on these two runs "
+    "(34.3 us on the 1024^2 ring, 38.6 us on member 1, as measured before the "
+    "critical bands of the two forms were split): rarefied gas/void mixtures "
+    "behind the fragments, within 30 cells of a transmissive side, reach "
+    "negative energy and ~2e4 m/s; the scheme has no positivity-preserving "
+    "treatment of near-vacuum cells yet")
+
+
+@pytest.mark.parametrize("which,precision", [
+    ("ring", "fp64"), ("member1", "fp64"),
+    pytest.param("ring", "fp32", marks=pytest.mark.skip(reason=FP32_END_TIME_SKIP)),
+    pytest.param("member1", "fp32", marks=pytest.mark.skip(reason=FP32_END_TIME_SKIP))])
+def test_runs_reach_their_end_time(which, precision):
+    """The 1024^2 ring (about 11300 steps) and ensemble member 1 (768^2,
+    about 27000 steps) go through fracture to their 40 us end time without
+    the non-physical flag.  Late in these runs the rarefied gas behind the
+    fragments holds stretches with principal ratios beyond 1e8, whose Hencky
+    strain the kernels form from det V (a strain formed from the entries of
+    V V^T alone gave NaN there)."""
     from paper_2210_04037_amd.solver import GpuSolver
     case = F.make_case(2) if which == "ring" else F.make_case(4, member=1)
-    print(f"[end time] {which} {case.n[0]}^2 fp64 to {case.t_end:.1e} s", flush=True)
-    g = GpuSolver(case, precision="fp64", use_graph=True)
+    print(f"[end time] {which} {case.n[0]}^2 {precision} to {case.t_end:.1e} s",
+          flush=True)
+    g = GpuSolver(case, precision=precision, use_graph=True)
     g.step(0, t_end=[case.t_end])
     steps = 0
     while g.time()[0] < case.t_end:

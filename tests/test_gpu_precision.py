@@ -1,22 +1,34 @@
-"""FP32-bulk form against the FP64 form on the GPU (both through the C ABI).
+"""The FP32-bulk form against the oracle (and beside the FP64 form), through
+the C ABI.
 
-Bars (per-field L1 of the FP32 run relative to the FP64 field's L1; solid
-cells for eps_p and D): density 1e-4, velocity 1e-3, eps_p 1e-3, damage
-1e-2.  Conservation drift of the FP32 run: every stage rounds each stored
-cell value to 2^-24, so after K steps the relative drift of mass and energy
-is bounded by 3 K 2^-24; the measured drift is printed beside it."""
+Bars (per-field L1 error relative to the reference field's L1; eps_p and D
+over solid cells, phi_s > 0.5): density 1e-4, velocity 1e-3, eps_p 1e-3,
+damage 1e-2; relative drift of the interior plus outflow totals of mass
+1e-6 and of energy 1e-5.  A damage bar is only asserted where the reference
+damage field is non-zero (the test says which runs carry damage).
+
+Runs: the 1D spall workload before the spall (300 steps) and through it
+(a 100-cell copy, 400 steps, critical damage and void opening), the 2D
+strip through fracture, and a 64^2 copy of the ring before fracture.  The
+FP32-bulk critical band is its own storage policy (D_crit (1 - 1e-6), about
+fifteen float ulps) where the double-precision reading uses 1e-9: after
+fracture the two forms may heal different cells, and that difference is
+part of the error measured here."""
 import numpy as np
 import pytest
 
 import fvinputs as F
+from oracle import Solver
 from oracle.layout import Layout
+from oracle.mixture import cons_to_prim
 
 pytestmark = pytest.mark.gpu
 
 BARS = dict(rho=1e-4, u=1e-3, eps=1e-3, D=1e-2)
+DRIFT = dict(mass=1e-6, energy=1e-5)
 
 
-def _run(case, precision, steps):
+def _gpu_run(case, precision, steps):
     from paper_2210_04037_amd.solver import GpuSolver
     g = GpuSolver(case, precision=precision)
     t0, _ = g.totals()
@@ -28,35 +40,73 @@ def _run(case, precision, steps):
     return W, t0[0], t1[0] + b1[0], t
 
 
+def _oracle_run(case, steps):
+    o = Solver(case)
+    for _ in range(steps):
+        o.step()
+    L = o.layout
+    P = cons_to_prim(o.U, L)
+    W = np.zeros_like(o.U)
+    W[L.phi] = P.phi
+    W[L.mass] = P.rho_l
+    W[L.eps[0]] = P.eps[0]
+    W[L.dmg[0]] = P.D[0]
+    W[L.mom] = P.u[:L.dim]
+    return W, o.t
+
+
 def _l1(a, b, mask=None):
     if mask is not None:
         a, b = a[mask], b[mask]
     den = np.sum(np.abs(b))
-    return np.sum(np.abs(a - b)) / den if den > 0 else np.sum(np.abs(a - b))
+    return float(np.sum(np.abs(a - b)) / den) if den > 0 else None
 
 
-@pytest.mark.parametrize("which,steps", [("spall", 300), ("ring", 150)])
-def test_fp32_bulk_within_bars(which, steps):
-    case = F.make_case(1, n=400) if which == "spall" else F.make_case(2, n=256)
-    print(f"[precision] {which} {case.n} {steps} steps", flush=True)
-    W64, a0, a1, t64 = _run(case, "fp64", steps)
-    W32, c0, c1, t32 = _run(case, "fp32", steps)
+def _errors(W, R, L):
+    rho = lambda X: np.sum(X[L.phi] * X[L.mass], axis=0)
+    spd = lambda X: np.sqrt(np.sum(X[L.mom] ** 2, axis=0))
+    solid = R[L.phi[0]] > 0.5
+    return dict(rho=_l1(rho(W), rho(R)), u=_l1(spd(W), spd(R)),
+                eps=_l1(W[L.eps[0]], R[L.eps[0]], solid),
+                D=_l1(W[L.dmg[0]], R[L.dmg[0]], solid))
+
+
+CASES = {
+    "spall_before": (lambda: F.make_case(1, n=400), 300, False),
+    "spall_through": (lambda: F.make_case(1, n=100), 400, True),
+    "strip2d_through": (lambda: F.spall_strip(2, 100, 8), 480, True),
+    "ring64_before": (lambda: F.make_case(2, n=64), 60, False),
+}
+
+
+@pytest.mark.parametrize("which", list(CASES))
+def test_fp32_bulk_against_oracle(which):
+    make, steps, fractured = CASES[which]
+    case = make()
     L = Layout(case.dim, case.mats)
-    rho64 = np.sum(W64[L.phi] * W64[L.mass], axis=0)
-    rho32 = np.sum(W32[L.phi] * W32[L.mass], axis=0)
-    sp64 = np.sqrt(np.sum(W64[L.mom] ** 2, axis=0))
-    sp32 = np.sqrt(np.sum(W32[L.mom] ** 2, axis=0))
-    solid = W64[L.phi[0]] > 0.5
-    errs = dict(rho=_l1(rho32, rho64), u=_l1(sp32, sp64),
-                eps=_l1(W32[L.eps[0]], W64[L.eps[0]], solid),
-                D=_l1(W32[L.dmg[0]], W64[L.dmg[0]], solid))
+    print(f"[precision] {which} {case.n} {steps} steps", flush=True)
+    W32, c0, c1, t32 = _gpu_run(case, "fp32", steps)
+    R, t_ref = _oracle_run(case, steps)
+    errs = _errors(W32, R, L)
+    W64, _, _, _ = _gpu_run(case, "fp64", steps)
+    errs64 = _errors(W64, R, L)
     nm = len(case.mats)
     drift_mass = max(abs(c1[l] - c0[l]) / abs(c0[l]) for l in range(nm))
     drift_e = abs(c1[-1] - c0[-1]) / abs(c0[-1])
-    bound = 3 * steps * 2.0 ** -24
-    print("[precision]", which, {k: f"{v:.2e}" for k, v in errs.items()},
-          f"mass drift {drift_mass:.2e} energy drift {drift_e:.2e} "
-          f"(bound {bound:.1e})", "t64", t64, "t32", t32, flush=True)
+    print("[precision]", which, "fp32-bulk vs oracle",
+          {k: (None if v is None else f"{v:.2e}") for k, v in errs.items()},
+          "fp64 vs oracle", {k: (None if v is None else f"{v:.1e}")
+                             for k, v in errs64.items()},
+          f"mass drift {drift_mass:.2e} energy drift {drift_e:.2e}",
+          "t32", t32, "t_oracle", t_ref, flush=True)
+    D_ref = R[L.dmg[0]]
+    if fractured:
+        assert np.max(D_ref) >= 0.9 * (1 - 1e-9)      # damage reached critical
+        assert errs["D"] is not None
+    else:
+        assert errs["D"] is None and np.max(np.abs(W32[L.dmg[0]])) == 0.0
     for k, v in errs.items():
-        assert v <= BARS[k], (k, v)
-    assert drift_mass <= bound and drift_e <= bound
+        if v is not None:
+            assert v <= BARS[k], (k, v)
+    assert drift_mass <= DRIFT["mass"] and drift_e <= DRIFT["energy"]
+    assert t32 == pytest.approx(t_ref, rel=1e-4)
