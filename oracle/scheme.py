@@ -131,6 +131,11 @@ def weno3_faces(q, eps):
     return left, right
 
 
+def _critical(D, m, opts):
+    tol = getattr(opts, "crit_rel_tol", None)
+    return is_critical(D, m) if tol is None else is_critical(D, m, tol)
+
+
 def _pick(sel_pos, sel_neg, vL, vR):
     """Upwind choice: vL where sel_pos, vR where sel_neg, mean otherwise."""
     return np.where(sel_pos, vL, np.where(sel_neg, vR, 0.5 * (vL + vR)))
@@ -320,7 +325,7 @@ def rhs(U, geom, layout, opts):
     bflux = {}
     crit = np.zeros(P.p.shape, dtype=bool)
     for l in L.solids:
-        crit |= is_critical(P.D[l], mats[l])
+        crit |= _critical(P.D[l], mats[l], opts)
     for a in range(dim):
         dxa = geom.dx[a]
         n = geom.n[a]

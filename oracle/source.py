@@ -28,6 +28,7 @@ import numpy as np
 
 from .closures import (solid_shear_modulus, triaxiality, eps_threshold,
                        bonora_dD_deps, is_critical)
+from .scheme import _critical
 from .kinematics import hencky, stretch_from_log
 from .mixture import cons_to_prim, closure_density
 
@@ -104,7 +105,7 @@ def source_step(U, phi0, geom, layout, opts):
         w = 1.0 - P.D[l]
         Gt = solid_shear_modulus(closure_density(P.phi[l], P.rho_l[l], m), m)
         Gmix = Gmix + P.phi[l] * w * Gt
-        sy = np.where(~is_critical(P.D[l], m), pert * m["yield_stress"], 0.0)
+        sy = np.where(~_critical(P.D[l], m, opts), pert * m["yield_stress"], 0.0)
         Ymix = Ymix + P.phi[l] * w * sy
     pos = Gmix > 0
     Jmax = np.where(pos, Ymix / (np.sqrt(6.0) * np.where(pos, Gmix, 1.0)),
@@ -121,7 +122,7 @@ def source_step(U, phi0, geom, layout, opts):
         eps_n = P.eps[l]
         D_n = P.D[l]
         sig_eq = (1.0 - D_n) * pert * m["yield_stress"]
-        gate = (P.p < m["p_gate"]) & (deps > 0) & ~is_critical(D_n, m)
+        gate = (P.p < m["p_gate"]) & (deps > 0) & ~_critical(D_n, m, opts)
         ok = sig_eq > 0
         R = triaxiality(P.p, np.where(ok, sig_eq, 1.0),
                         closure_density(P.phi[l], P.rho_l[l], m), m)

@@ -9,18 +9,25 @@ damage field is non-zero (the test says which runs carry damage).
 
 Runs: the 1D spall workload before the spall (300 steps) and through it
 (a 100-cell copy, 400 steps, critical damage and void opening), the 2D
-strip through fracture, and a 64^2 copy of the ring before fracture.  The
-FP32-bulk critical band is its own storage policy (D_crit (1 - 1e-6), about
-fifteen float ulps) where the double-precision reading uses 1e-9: after
-fracture the two forms may heal different cells, and that difference is
-part of the error measured here."""
+strip through fracture, and a 64^2 copy of the ring before fracture.
+
+The critical-damage test is a discontinuous decision with a band: the
+double-precision reading takes D >= D_crit (1 - 1e-9), the FP32-bulk kernels
+(float storage resolves D only to about 6e-8) D >= D_crit (1 - 1e-6).  After
+fracture the two bands heal different cells -- advection leaves a cell that
+was clamped at D_crit a few 1e-8 below it -- and the runs separate by far
+more than the bars (the oracle itself, run with the two bands, separates the
+same way).  So through fracture the FP32-bulk form is held to the bars
+against the oracle run with its own band, and its distance from the
+double-precision reading is checked to be that band effect: no larger than
+the oracle's own two-band difference plus the bar."""
 import numpy as np
 import pytest
 
 import fvinputs as F
 from oracle import Solver
 from oracle.layout import Layout
-from oracle.mixture import cons_to_prim
+from oracle.mixture import Options, cons_to_prim
 
 pytestmark = pytest.mark.gpu
 
@@ -40,8 +47,8 @@ def _gpu_run(case, precision, steps):
     return W, t0[0], t1[0] + b1[0], t
 
 
-def _oracle_run(case, steps):
-    o = Solver(case)
+def _oracle_run(case, steps, crit_rel_tol=None):
+    o = Solver(case, Options(cfl=case.cfl, crit_rel_tol=crit_rel_tol))
     for _ in range(steps):
         o.step()
     L = o.layout
@@ -93,20 +100,29 @@ def test_fp32_bulk_against_oracle(which):
     nm = len(case.mats)
     drift_mass = max(abs(c1[l] - c0[l]) / abs(c0[l]) for l in range(nm))
     drift_e = abs(c1[-1] - c0[-1]) / abs(c0[-1])
-    print("[precision]", which, "fp32-bulk vs oracle",
-          {k: (None if v is None else f"{v:.2e}") for k, v in errs.items()},
-          "fp64 vs oracle", {k: (None if v is None else f"{v:.1e}")
-                             for k, v in errs64.items()},
+    fmt = lambda e: {k: (None if v is None else f"{v:.2e}") for k, v in e.items()}
+    print("[precision]", which, "fp32-bulk vs oracle", fmt(errs),
+          "fp64 vs oracle", fmt(errs64),
           f"mass drift {drift_mass:.2e} energy drift {drift_e:.2e}",
           "t32", t32, "t_oracle", t_ref, flush=True)
     D_ref = R[L.dmg[0]]
-    if fractured:
-        assert np.max(D_ref) >= 0.9 * (1 - 1e-9)      # damage reached critical
-        assert errs["D"] is not None
-    else:
-        assert errs["D"] is None and np.max(np.abs(W32[L.dmg[0]])) == 0.0
-    for k, v in errs.items():
-        if v is not None:
-            assert v <= BARS[k], (k, v)
     assert drift_mass <= DRIFT["mass"] and drift_e <= DRIFT["energy"]
     assert t32 == pytest.approx(t_ref, rel=1e-4)
+    if not fractured:
+        assert errs["D"] is None and np.max(np.abs(W32[L.dmg[0]])) == 0.0
+        for k, v in errs.items():
+            if v is not None:
+                assert v <= BARS[k], (k, v)
+        return
+    assert np.max(D_ref) >= 0.9 * (1 - 1e-9)      # damage reached critical
+    R6, _ = _oracle_run(case, steps, crit_rel_tol=1e-6)
+    errs_band = _errors(W32, R6, L)
+    control = _errors(R6, R, L)
+    print("[precision]", which, "fp32-bulk vs oracle with the float band",
+          fmt(errs_band), "oracle float band vs double band", fmt(control),
+          flush=True)
+    assert errs_band["D"] is not None
+    for k, v in errs_band.items():
+        assert v <= BARS[k], (k, v)
+    for k, v in errs.items():
+        assert v <= control[k] + BARS[k], (k, v, control[k])
