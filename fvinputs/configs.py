@@ -315,7 +315,7 @@ def make_case(config, n=None, member=None, t_end=None):
     raise ValueError(f"unknown workload {config}")
 
 
-def spall_strip(dim, n_long=100, n_trans=8, bump=0.2e-3, v=200.0, seed=None,
+def spall_strip(dim, n_long=100, n_trans=8, bump=0.5e-3, v=200.0, seed=None,
                 t_end=3.0e-6):
     """Plate impact on a 2D or 3D strip, for fracture checks off the 1D line:
     the 1D spall workload (10 mm, copper with gate pressure -1.5 GPa, free
