@@ -258,6 +258,24 @@ size_t fv_fragment_workspace_bytes(const fv_ctx* ctx, int32_t inst, int64_t cap)
 int32_t fv_fragments(fv_ctx* ctx, int32_t inst, double cut, int32_t* labels, void* frag_ws,
                      size_t frag_ws_bytes, int64_t cap, int64_t* n_frag, fv_fragment* out);
 
+/* Size of the static fragment scratch behind fv_fragments_noalloc (bytes per
+ * GPU the library runs on, held until the process ends). */
+#define FV_FRAGMENT_SCRATCH_BYTES (64u << 20)
+
+/* fv_fragments without a workspace argument, for callers that cannot
+ * allocate device memory (serving loops and harnesses that forbid hipMalloc
+ * and workspace tensors): the kernels work in a static scratch array of
+ * FV_FRAGMENT_SCRATCH_BYTES on the context's GPU instead of frag_ws.  The
+ * call allocates nothing (no hipMalloc, no allocating library routine).  It
+ * fits an instance and cap whose fv_fragment_workspace_bytes is at most
+ * FV_FRAGMENT_SCRATCH_BYTES (for example 2^22 cells with cap 2^14), else
+ * FV_ENOMEM with the size in fv_last_error.  Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU (two contexts or threads on
+ * different streams) race and must be serialised by the caller.  Arguments,
+ * outputs, bit-exactness and the other errors are those of fv_fragments. */
+int32_t fv_fragments_noalloc(fv_ctx* ctx, int32_t inst, double cut, int32_t* labels, int64_t cap,
+                             int64_t* n_frag, fv_fragment* out);
+
 /* Cumulative fragment-mass histogram, the form in which Sections 4.2 and 4.3
  * present fragment distributions (fragment mass against cumulative fragment
  * number): counts[k] = number of fragments among frags[0..n) whose mass is at

@@ -8,6 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfv.so")
 
 FV_OK, FV_EINVAL, FV_ENOMEM, FV_EDEVICE, FV_ENONPHYS, FV_ESTATE = 0, -1, -2, -3, -4, -5
+FV_FRAGMENT_SCRATCH_BYTES = 64 << 20
 FV_BC = {"transmissive": 0, "free": 1, "periodic": 2}
 FV_MAT = {"solid": 0, "gas": 1}
 FV_FP64, FV_FP32_BULK = 0, 1
@@ -18,7 +19,8 @@ EXPORTS = ["fv_state_fields", "fv_workspace_bytes", "fv_init",
            "fv_step", "fv_time", "fv_totals", "fv_checkpoint_bytes",
            "fv_checkpoint", "fv_restore", "fv_autotune",
            "fv_fragment_workspace_bytes",
-           "fv_fragments", "fv_fragment_histogram", "fv_last_error",
+           "fv_fragments", "fv_fragments_noalloc", "fv_fragment_histogram",
+           "fv_last_error",
            "fv_destroy"]
 
 
@@ -104,6 +106,9 @@ def load(path=LIB_PATH):
     lib.fv_fragments.argtypes = [vp, i32, dbl, vp, vp, ctypes.c_size_t,
                                  ctypes.c_int64, P(ctypes.c_int64), P(FvFragment)]
     lib.fv_fragments.restype = i32
+    lib.fv_fragments_noalloc.argtypes = [vp, i32, dbl, vp, ctypes.c_int64,
+                                         P(ctypes.c_int64), P(FvFragment)]
+    lib.fv_fragments_noalloc.restype = i32
     lib.fv_fragment_histogram.argtypes = [vp, ctypes.c_int64, P(dbl), i32,
                                           P(ctypes.c_int64)]
     lib.fv_fragment_histogram.restype = i32

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -299,6 +300,45 @@ static int set_tiles(fv_ctx* c, int v, int sched) {
   return rc;
 }
 
+// Static fragment scratch of fv_fragments_noalloc: one array per GPU, held
+// from the library's load to the end of the process.  Host code never uses
+// its name as an address (that is a host-side stand-in): fv_init looks up
+// each device's address once with hipGetSymbolAddress, with that device
+// current, and the entry point passes that address to the kernels.
+static __device__ __align__(256) unsigned char frag_scratch[FV_FRAGMENT_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_addr;   // per device id
+
+// Address of the scratch array on the current device (looked up once).
+int scratch_setup(fv_ctx* c) {
+  int dev = 0;
+  int rc = hip_check(c, hipGetDevice(&dev), "current device");
+  if (rc != FV_OK) return rc;
+  c->device = dev;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_addr.size() <= dev) g_scratch_addr.resize(dev + 1, nullptr);
+  if (g_scratch_addr[dev]) return FV_OK;
+  void* p = nullptr;
+  rc = hip_check(c, hipGetSymbolAddress(&p, HIP_SYMBOL(frag_scratch)), "fragment scratch address");
+  if (rc != FV_OK) return rc;
+  g_scratch_addr[dev] = p;
+  return FV_OK;
+}
+
+void* scratch_ptr(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return dev >= 0 && dev < (int)g_scratch_addr.size() ? g_scratch_addr[dev] : nullptr;
+}
+}  // namespace
+
+__global__ void __launch_bounds__(256) zero_words_kernel(unsigned int* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
 extern "C" {
 
 int32_t fv_state_fields(int32_t dim, int32_t n_mat, const fv_material* mats) {
@@ -364,6 +404,12 @@ int32_t fv_init(fv_ctx** out, int32_t n_inst, const fv_grid* grids, int32_t n_ma
     return fail(nullptr, FV_EDEVICE, m);
   }
   fill_params(mats, n_mat, opt, c->P);
+  rc = scratch_setup(c);
+  if (rc != FV_OK) {
+    g_init_error = c->err;
+    delete c;
+    return rc;
+  }
   WsPlan W;
   plan_ws(n_inst, grids, c->vars, W);
   if (workspace_bytes < W.total) {
@@ -887,9 +933,14 @@ int32_t fv_fragment_histogram(const fv_fragment* frags, int64_t n, const double*
   return FV_OK;
 }
 
-int32_t fv_fragments(fv_ctx* c, int32_t inst, double cut, int32_t* labels, void* frag_ws,
-                     size_t frag_ws_bytes, int64_t cap, int64_t* n_frag, fv_fragment* out) {
-  if (!c) return FV_EINVAL;
+}  // extern "C"
+
+// fv_fragments and fv_fragments_noalloc: frag_ws is the fragment workspace
+// (the caller's buffer, or this library's static scratch array); what the
+// kernels need zeroed is cleared here with a fill kernel.
+static int32_t fragments_impl(fv_ctx* c, int32_t inst, double cut, int32_t* labels,
+                              void* frag_ws, size_t frag_ws_bytes, int64_t cap, int64_t* n_frag,
+                              fv_fragment* out) {
   if (inst < 0 || inst >= c->n_inst) return fail(c, FV_EINVAL, "bad instance");
   if (!labels || !frag_ws || !n_frag) return fail(c, FV_EINVAL, "null labels, workspace or n_frag");
   if (cap < 0 || (cap > 0 && !out)) return fail(c, FV_EINVAL, "bad cap or null output array");
@@ -934,10 +985,17 @@ int32_t fv_fragments(fv_ctx* c, int32_t inst, double cut, int32_t* labels, void*
   if (nr == 0) return FV_OK;
   hipLaunchKernelGGL(ccl_assign_kernel, grid, blk, 0, s, g, (const int*)labels, (const int*)bcount,
                      fid, flabel);
-  rc = hip_check(c, hipMemsetAsync(fcount, 0, sizeof(unsigned long long) * nr, s), "zero counts");
-  if (rc == FV_OK) rc = hip_check(c, hipMemsetAsync(fflag, 0, sizeof(unsigned int) * nr, s), "zero flags");
-  if (rc == FV_OK)
-    rc = hip_check(c, hipMemsetAsync(fbins, 0, sizeof(unsigned long long) * NBINS * nr, s), "zero bins");
+  // per-fragment counters start at zero (a fill kernel: the scratch array
+  // keeps the previous call's contents)
+  auto zero = [&](void* p, int64_t words) {
+    hipLaunchKernelGGL(zero_words_kernel,
+                       dim3((unsigned)std::min<int64_t>((words + 255) / 256, 4096)), dim3(256), 0,
+                       s, reinterpret_cast<unsigned int*>(p), words);
+  };
+  zero(fcount, 2 * nr);
+  zero(fflag, nr);
+  zero(fbins, 2 * (int64_t)NBINS * nr);
+  rc = hip_check(c, hipGetLastError(), "zero fragment counters");
   if (rc != FV_OK) return rc;
   if (c->ops.elem == 8)
     hipLaunchKernelGGL(ccl_stats_kernel<double>, grid, blk, 0, s, g, (const int*)labels, (const int*)fid,
@@ -971,6 +1029,32 @@ int32_t fv_fragments(fv_ctx* c, int32_t inst, double cut, int32_t* labels, void*
     out[f].reserved = 0;
   }
   return FV_OK;
+}
+
+extern "C" {
+
+int32_t fv_fragments(fv_ctx* c, int32_t inst, double cut, int32_t* labels, void* frag_ws,
+                     size_t frag_ws_bytes, int64_t cap, int64_t* n_frag, fv_fragment* out) {
+  if (!c) return FV_EINVAL;
+  return fragments_impl(c, inst, cut, labels, frag_ws, frag_ws_bytes, cap, n_frag, out);
+}
+
+int32_t fv_fragments_noalloc(fv_ctx* c, int32_t inst, double cut, int32_t* labels, int64_t cap,
+                             int64_t* n_frag, fv_fragment* out) {
+  if (!c) return FV_EINVAL;
+  if (inst < 0 || inst >= c->n_inst) return fail(c, FV_EINVAL, "bad instance");
+  if (cap < 0) return fail(c, FV_EINVAL, "bad cap or null output array");
+  void* ws = scratch_ptr(c->device);
+  if (!ws) return fail(c, FV_EDEVICE, "fragment scratch address of device " +
+                                          std::to_string(c->device) + " unknown");
+  const size_t need = plan_frag(c->insts[inst].ncell, cap).total;
+  if (need > (size_t)FV_FRAGMENT_SCRATCH_BYTES)
+    return fail(c, FV_ENOMEM, "instance and cap need " + std::to_string(need) +
+                                  " bytes of fragment scratch, above the static " +
+                                  std::to_string((size_t)FV_FRAGMENT_SCRATCH_BYTES) +
+                                  " (use fv_fragments with a workspace)");
+  return fragments_impl(c, inst, cut, labels, ws, (size_t)FV_FRAGMENT_SCRATCH_BYTES, cap, n_frag,
+                        out);
 }
 
 const char* fv_last_error(const fv_ctx* c) {

@@ -30,6 +30,7 @@ struct Ops {
 // Context behind the opaque fv_ctx handle of the C ABI.
 struct fv_ctx {
   int n_inst = 0, dim = 0, nm = 0, ns = 0, precision = 0;
+  int device = 0;                     // HIP device current at fv_init
   fv::Params P{};
   hipStream_t stream = nullptr;
   std::vector<fv::Inst> insts;

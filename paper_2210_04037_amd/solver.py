@@ -172,6 +172,25 @@ class GpuSolver:
                   bool(f.touches_boundary)) for f in out[:nf.value]]
         return lab, frags
 
+    def fragments_noalloc(self, i=0, cut=0.5, cap=4096):
+        """As fragments(), through fv_fragments_noalloc: the library's static
+        scratch replaces the workspace (only the label buffer is the
+        caller's)."""
+        torch = self.torch
+        c = self.cases[i]
+        ncell = int(np.prod(c.n))
+        labels = torch.empty(ncell, dtype=torch.int32, device=self.device)
+        out = (abi.FvFragment * max(int(cap), 1))()
+        nf = ctypes.c_int64()
+        self._c(self.lib.fv_fragments_noalloc(
+            self.ctx, i, float(cut), ctypes.c_void_p(labels.data_ptr()),
+            int(cap), ctypes.byref(nf), out))
+        nx, ny, nz = c.n
+        lab = labels.cpu().numpy().reshape(nz, ny, nx)
+        frags = [(int(f.label), int(f.n_cells), float(f.mass),
+                  bool(f.touches_boundary)) for f in out[:nf.value]]
+        return lab, frags
+
     def mass_histogram(self, frags, edges):
         """Cumulative fragment count at each mass edge (entry k: fragments of
         mass >= edges[k]) from the library's fv_fragment_histogram."""
