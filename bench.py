@@ -43,7 +43,7 @@ TRAFFIC_FILES = {
 }
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2210_04037_amd", "csrc", f)
                   for f in ("fv_core.hpp", "fv_stage.hpp", "fv_kernels.hpp",
-                            "fv_stage3.hpp", "fv_fp64.hip", "fv_fp32.hip")]
+                            "fv_fp64.hip", "fv_fp32.hip")]
 BARS = {"rho": 1e-4, "u": 1e-3, "eps_p": 1e-3, "D": 1e-2}
 DRIFT_BARS = {"mass": 1e-6, "energy": 1e-5}
 
@@ -186,8 +186,8 @@ def run_gpu(cases, precision, steps, warmup, autotune=True, chunk=10,
                   use_graph=chunk > 0, tile=tile)
     tot0, _ = g.totals()
     table = None
-    if autotune and tile is None and cases[0].dim < 3:
-        tile, table = g.autotune(reps=10)
+    if autotune and tile is None:
+        tile, table = g.autotune(reps=3 if cases[0].dim == 3 else 10)
     start = None
     if advance_to is not None:
         t_end = np.array([c.t_end for c in cases])

@@ -48,11 +48,11 @@ bool select_ops_fp32(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t
     return true;
   }
   if (dim == 3 && nm == 1 && ns == 1) {
-    FV_VAR3(1, 1, float, float, 16, 16, 256)
+    FV_VAR3(1, 1, float, float)
     return true;
   }
   if (dim == 3 && nm == 2 && ns == 1) {
-    FV_VAR3(2, 1, float, float, 16, 16, 256)
+    FV_VAR3(2, 1, float, float)
     return true;
   }
   return false;

@@ -1,4 +1,4 @@
-// Device kernels of libfv: the stage kernel (1D, 2D), the two 3D passes,
+// Device kernels of libfv: the stage kernel (1D, 2D), the three 3D passes,
 // state conversions, the CFL reduction and the exact sums.  Their launchers
 // and the host context are in fv_launch.hpp.
 #pragma once
@@ -12,7 +12,6 @@
 #include <vector>
 
 #include "fv_stage.hpp"
-#include "fv_stage3.hpp"
 #include "../../include/fv.h"
 
 namespace fvk {
@@ -279,9 +278,12 @@ __global__ void __launch_bounds__(256) cfl_kernel(const Inst* insts, int ii, Par
 
 
 // ---------------------------------------------------------------------------
-// 3D stage: the primitives of every cell go to HBM once (prim3_kernel), then
-// column tiles march up in z (zm_kernel, fv_stage3.hpp), computing every face
-// once from LDS (x, y) or from their own column (z) and updating their cells.
+// 3D stage: three passes over full-grid buffers in HBM.  A tile with a
+// two-cell halo in three directions does not fit in LDS at the number of
+// primitive fields a 3D cell carries, so the primitives go to HBM once, every
+// face of a direction is computed once from them, and a per-cell pass
+// gathers the six faces, applies the RK combination and (third stage) the
+// source step and CFL reduction.
 // ---------------------------------------------------------------------------
 // time step of the stage from the device dt state; fills the context.
 // stage 0 is the timing run of stage 1 (see stage_kernel).
@@ -311,6 +313,33 @@ __device__ __forceinline__ bool setup3(const Inst& I, const Params& P, int stage
   return dt > 0.0;
 }
 
+__device__ __forceinline__ int64_t nfaces3(const Inst& I, int a) {
+  return I.ncell / I.n[a] * (I.n[a] + 1);
+}
+
+// Brick traversal of the y- and z-face passes: a block of 256 threads covers
+// 64 faces along x by 4 along the other transverse direction, and consecutive
+// block numbers step along the face direction first, so the cell planes a
+// brick's stencil reaches are still in the XCD's L2 for the next block (a
+// 256^2 plane of primitives is larger than one XCD's L2).
+constexpr int BRX = 64, BRY = 4;
+__host__ __device__ inline int64_t brick_blocks(int n_t, int n_u, int n_s) {
+  // n_t: cells along x, n_u: along the other transverse direction,
+  // n_s: positions along the stepping direction
+  return (int64_t)((n_t + BRX - 1) / BRX) * ((n_u + BRY - 1) / BRY) * n_s;
+}
+// position of thread tid of brick block b: x, transverse u, step s;
+// false past the domain
+__device__ __forceinline__ bool brick_pos(int64_t b, int n_t, int n_u, int n_s, int& x, int& u,
+                                          int& s) {
+  s = (int)(b % n_s);
+  const int64_t br = b / n_s;
+  const int nbx = (n_t + BRX - 1) / BRX;
+  x = (int)(br % nbx) * BRX + (int)(threadIdx.x % BRX);
+  u = (int)(br / nbx) * BRY + (int)(threadIdx.x / BRX);
+  return x < n_t && u < n_u;
+}
+
 template <int NM, int NS, class T, class C>
 __global__ void __launch_bounds__(256) prim3_kernel(const Inst* insts, int ii, Params P,
                                                     int stage, int parity) {
@@ -324,100 +353,116 @@ __global__ void __launch_bounds__(256) prim3_kernel(const Inst* insts, int ii, P
   St::template cell_prims<int64_t>(cx, g, (C*)I.Wb, I.ncell, g);
 }
 
-// z-planes per block of the marching kernel
-constexpr int ZM_CHUNK = 16;
-
-__host__ __device__ inline int zm_chunks(int nz) { return (nz + ZM_CHUNK - 1) / ZM_CHUNK; }
-
-// Two 256-thread FP32-bulk 16 x 16 blocks share a CU (80 KiB of LDS each),
-// eight waves per CU: each lane may then hold 256 registers.
-template <class Zt, class C, int NTH>
-constexpr int zm_waves_per_eu() {
-  return (sizeof(C) == 4 && NTH == 256 && 2 * Zt::smem_bytes() <= 160 * 1024) ? 2 : 1;
+// the direction is a template argument: every per-direction index in the
+// face computation is then a constant (a runtime direction would put those
+// arrays in scratch memory)
+template <int NM, int NS, class T, class C, int A>
+__global__ void __launch_bounds__(256) face3_kernel(const Inst* insts, int ii, Params P,
+                                                    int stage, int parity) {
+  constexpr int a = A;
+  using St = Stage<3, NM, NS, T, C, 1, 1>;
+  const Inst& I = insts[ii];
+  typename St::Ctx cx;
+  double t, dtinv, dt;
+  if (!setup3<St, T, C>(I, P, stage, parity, cx, t, dtinv, dt)) return;
+  const int64_t nf = nfaces3(I, a);
+  const int nx = I.n[0], ny = I.n[1], nz = I.n[2];
+  int c[3], i;
+  int64_t f;
+  if constexpr (a == 0) {
+    // x-faces: rows of consecutive faces
+    f = xcd_block() * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    i = (int)(f % (nx + 1));
+    const int64_t r = f / (nx + 1);
+    c[1] = (int)(r % ny);
+    c[2] = (int)(r / ny);
+    c[0] = 0;
+  } else if constexpr (a == 1) {
+    // y-faces: bricks over (x, z), stepping along y
+    if (!brick_pos(xcd_block(), nx, nz, ny + 1, c[0], c[2], i)) return;
+    c[1] = 0;
+    f = ((int64_t)c[2] * (ny + 1) + i) * nx + c[0];
+  } else {
+    // z-faces: bricks over (x, y), stepping along z
+    if (!brick_pos(xcd_block(), nx, ny, nz + 1, c[0], c[1], i)) return;
+    c[2] = 0;
+    f = ((int64_t)i * ny + c[1]) * nx + c[0];
+  }
+  // the face lies between cells i - 1 and i along a; stencil i - 2 .. i + 1
+  int64_t st[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    int cc[3] = {c[0], c[1], c[2]};
+    cc[a] = St::map_index(i - 2 + s, I.n[a], I.bc[a][0], I.bc[a][1]);
+    st[s] = ((int64_t)cc[2] * ny + cc[1]) * nx + cc[0];
+  }
+  const int64_t bslot = a == 0 ? (int64_t)c[2] * ny + c[1]
+                                : (a == 1 ? (int64_t)c[2] * nx + c[0] : (int64_t)c[1] * nx + c[0]);
+  St::template compute_face<int64_t>(cx, (const C*)I.Wb, I.ncell, a, st[0], st[1], st[2], st[3],
+                                     i, f, nf, bslot, (C*)I.Fb[a]);
 }
 
-template <int NM, int NS, class T, class C, int TX, int TY, int NTH>
-__global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(
-    zm_waves_per_eu<Zm<NM, NS, T, C, TX, TY, NTH>, C, NTH>())))
-zm_kernel(const Inst* __restrict__ insts, int ii, Params P, int stage, int parity) {
-  using Zt = Zm<NM, NS, T, C, TX, TY, NTH>;
-  using St = typename Zt::St;
-  constexpr int S = Zt::S;
-  constexpr int NQ = Zt::NQ;
-  extern __shared__ double smem_d[];
-  C* W = reinterpret_cast<C*>(smem_d);
-  C* fb = W + (size_t)Zt::NW * Zt::NCC;
+template <int NM, int NS, class T, class C>
+__global__ void __launch_bounds__(256) finish3_kernel(const Inst* insts, int ii, Params P,
+                                                      int stage, int parity) {
+  using St = Stage<3, NM, NS, T, C, 1, 1>;
+  using L = Lay<3, NM, NS>;
+  __shared__ double scratch[4];
   const Inst& I = insts[ii];
-  const int tid = threadIdx.x;
-  typename Zt::Ctx cx;
+  typename St::Ctx cx;
   double t, dtinv, dt;
   const bool dry = stage == 0;
-  const bool go = setup3<St, T, C>(I, P, stage, parity, cx.s, t, dtinv, dt);
+  const bool go = setup3<St, T, C>(I, P, stage, parity, cx, t, dtinv, dt);
   const int q = parity & 1;
-  const int b = (int)xcd_block();
   // time of the next step and a cleared CFL slot for the third stage's
   // reduction (a finished instance carries its time and CFL value over)
-  if (cx.s.stage == 1 && !dry && b == 0 && tid == 0) {
+  if (cx.stage == 1 && !dry && blockIdx.x == 0 && threadIdx.x == 0) {
     I.dts[DTS_T + 1 - q] = go ? t + dt : t;
     dts_set_dtinv(I.dts, 1 - q, go ? 0.0 : dtinv);
   }
-  if (!go) return;
-  const int ntx = (I.n[0] + TX - 1) / TX, nty = (I.n[1] + TY - 1) / TY;
-  cx.bx = b % ntx;
-  const int r = b / ntx;
-  cx.by = r % nty;
-  cx.z0 = (r / nty) * ZM_CHUNK;
-  cx.z1 = min(cx.z0 + ZM_CHUNK, I.n[2]);
-  int tx = 0, ty = 0;
-  const bool own = Zt::own_column(cx, tid, tx, ty);
-  const int gx = cx.bx * TX + tx, gy = cx.by * TY + ty;
-  // z-face below the first plane, into this thread's face-buffer slot (no
-  // other thread touches it before the first barrier)
-  C zm[NQ];
-  if (own) {
-    Zt::zface(cx, tx, ty, cx.z0, fb, tid, Zt::NFACE);
-#pragma unroll
-    for (int v = 0; v < NQ; ++v) zm[v] = fb[v * Zt::NFACE + tid];
-  }
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double cflv = 0.0;
-  bool bad_any = false;
-  for (int z = cx.z0; z < cx.z1; ++z) {
-    __syncthreads();
-    for (int c = tid; c < Zt::NCC; c += NTH) Zt::load_cross(cx, z, c, W);
-    __syncthreads();
-    C acc[S];
+  if (go && g < I.ncell) {
+    const C* W = (const C*)I.Wb;
+    const int64_t nc = I.ncell;
+    C Xc[3], uc[3], phic[NM];
+    C Vc[3][3];
 #pragma unroll
-    for (int f = 0; f < S; ++f) acc[f] = 0;
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      for (int it = tid; it < Zt::face_items(a); it += NTH) {
-        int cm, c0, c1, c2, gf, fs;
-        int64_t bs;
-        if (Zt::face_item(cx, a, z, it, cm, c0, c1, c2, gf, fs, bs))
-          St::template compute_face<int>(cx.s, W, Zt::NCC, a, cm, c0, c1, c2, gf, fs, Zt::NFACE,
-                                         bs, fb);
-      }
-      __syncthreads();
-      if (own) Zt::gather_xy(cx, W, fb, a, tx, ty, acc);
-      __syncthreads();
+    for (int k = 0; k < 3; ++k) {
+      Xc[k] = W[(L::W_X + k) * nc + g];
+      uc[k] = W[(L::R_U + k) * nc + g];
     }
-    if (own) {
-      Zt::zface(cx, tx, ty, z + 1, fb, tid, Zt::NFACE);
-      Zt::gather_z(cx, W, zm, fb, tid, tx, ty, acc);
 #pragma unroll
-      for (int v = 0; v < NQ; ++v) zm[v] = fb[v * Zt::NFACE + tid];
-      bool bad = false;
-      const double v = St::finish_cell(cx.s, Zt::cell_index(I, gx, gy, z), acc, &bad);
-      cflv = fmax(cflv, v);
-      bad_any = bad_any || bad;
+    for (int l = 0; l < NM; ++l) phic[l] = W[(L::R_PHI + l) * nc + g];
+#pragma unroll
+    for (int qv = 0; qv < L::NV; ++qv) Vc[vb_i<3>(qv)][vb_j<3>(qv)] = W[(L::R_V + qv) * nc + g];
+    const int nx = I.n[0], ny = I.n[1];
+    const int x = (int)(g % nx);
+    const int64_t r = g / nx;
+    const int y = (int)(r % ny);
+    const int z = (int)(r / ny);
+    C acc[St::S];
+#pragma unroll
+    for (int f = 0; f < St::S; ++f) acc[f] = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      int64_t fm, fp;
+      if (a == 0) { fm = ((int64_t)z * ny + y) * (nx + 1) + x; fp = fm + 1; }
+      else if (a == 1) { fm = ((int64_t)z * (ny + 1) + y) * nx + x; fp = fm + nx; }
+      else { fm = g; fp = g + (int64_t)nx * ny; }
+      const int64_t nf = nfaces3(I, a);
+      typename St::FaceC m, p;
+      St::template face_contrib<int64_t>((const C*)I.Fb[a], fm, nf, a, 1, Xc, Vc, uc, m);
+      St::template face_contrib<int64_t>((const C*)I.Fb[a], fp, nf, a, 0, Xc, Vc, uc, p);
+      St::gather_dir(cx, a, m, p, Xc, uc, phic, Vc, acc);
     }
+    bool bad = false;
+    cflv = St::finish_cell(cx, g, acc, &bad);
+    if (bad) atomicOr(reinterpret_cast<unsigned int*>(&I.dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);
   }
-  if (bad_any) atomicOr(reinterpret_cast<unsigned int*>(&I.dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);
-  if (cx.s.stage == 3) {
-    __syncthreads();   // the scratch words of the reduction alias the plane's LDS
-    block_max_to<NTH>(cflv, reinterpret_cast<double*>(smem_d),
-                      &I.dts[dts_slot(1 - q, blockIdx.x & (DTS_NSLOT - 1))]);
-  }
+  if (cx.stage == 3 && go)
+    block_max_to<256>(cflv, scratch, &I.dts[dts_slot(1 - q, blockIdx.x & (DTS_NSLOT - 1))]);
 }
 
 }  // namespace fvk

@@ -107,38 +107,37 @@ Ops make_ops() {
   return o;
 }
 
-// 3D kernel set: per stage, the primitive pass and the z-marching pass of
-// TX x TY column tiles, launched instance by instance
-template <int NM, int NS, class T, class C, int TX, int TY, int NTH>
+// 3D kernel set: the three passes per stage, launched instance by instance
+// (block size 256; TX reports it, TY = 1)
+template <int NM, int NS, class T, class C>
 Ops make_ops3() {
-  using Zt = Zm<NM, NS, T, C, TX, TY, NTH>;
   Ops o;
   common_ops<3, NM, NS, T, C>(o);
-  o.TX = TX;
-  o.TY = TY;
-  o.NT = NTH;
-  o.smem = Zt::smem_bytes();
+  o.TX = 256;
+  o.TY = 1;
+  o.NT = 256;
+  o.smem = 0;
   o.stage = [](fv_ctx* c, int stage, int parity, hipStream_t s) {
     for (int ii = 0; ii < c->n_inst; ++ii) {
       const Inst& I = c->insts[ii];
       const unsigned nbc = (unsigned)((I.ncell + 255) / 256);
       hipLaunchKernelGGL((prim3_kernel<NM, NS, T, C>), dim3(nbc), dim3(256), 0, s, c->insts_d, ii,
                          c->P, stage, parity);
-      const unsigned nb = (unsigned)((int64_t)((I.n[0] + TX - 1) / TX) * ((I.n[1] + TY - 1) / TY) *
-                                     zm_chunks(I.n[2]));
-      hipLaunchKernelGGL((zm_kernel<NM, NS, T, C, TX, TY, NTH>), dim3(nb), dim3(NTH),
-                         Zt::smem_bytes(), s, c->insts_d, ii, c->P, stage, parity);
+      const int nx = I.n[0], ny = I.n[1], nz = I.n[2];
+      const int64_t nf0 = I.ncell / nx * (nx + 1);
+      hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 0>), dim3((unsigned)((nf0 + 255) / 256)),
+                         dim3(256), 0, s, c->insts_d, ii, c->P, stage, parity);
+      hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 1>),
+                         dim3((unsigned)brick_blocks(nx, nz, ny + 1)), dim3(256), 0, s,
+                         c->insts_d, ii, c->P, stage, parity);
+      hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 2>),
+                         dim3((unsigned)brick_blocks(nx, ny, nz + 1)), dim3(256), 0, s,
+                         c->insts_d, ii, c->P, stage, parity);
+      hipLaunchKernelGGL((finish3_kernel<NM, NS, T, C>), dim3(nbc), dim3(256), 0, s, c->insts_d,
+                         ii, c->P, stage, parity);
     }
   };
   return o;
-}
-
-template <int NM, int NS, class T, class C, int TX, int TY, int NTH>
-hipError_t set_smem_attr3() {
-  using Zt = Zm<NM, NS, T, C, TX, TY, NTH>;
-  return hipFuncSetAttribute((const void*)&zm_kernel<NM, NS, T, C, TX, TY, NTH>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)Zt::smem_bytes());
 }
 
 template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH>
@@ -160,11 +159,8 @@ hipError_t set_smem_attr() {
 // a tile shape with one thread per interior cell
 #define FV_VAR(D, M, S_, TT, CC, X, Y) FV_VARN(D, M, S_, TT, CC, X, Y, (X) * (Y))
 
-#define FV_VAR3(M, S_, TT, CC, X, Y, N)                                     \
-  {                                                                        \
-    vars.push_back(make_ops3<M, S_, TT, CC, X, Y, N>());                   \
-    if (set_attr && herr == hipSuccess) herr = set_smem_attr3<M, S_, TT, CC, X, Y, N>(); \
-  }
+#define FV_VAR3(M, S_, TT, CC)                                              \
+  { vars.push_back(make_ops3<M, S_, TT, CC>()); }
 
 // kernel sets of each translation unit: every tile shape compiled for a
 // (dimension, materials, solids) combination

@@ -34,6 +34,7 @@ struct Inst {
   const void* phi0; // perturbation field on the initial mesh
   double* bacc;     // outward boundary flux accumulators
   void* Wb;         // 3D: primitives of every cell (workspace)
+  void* Fb[3];      // 3D: face data of each direction (workspace)
   double* dts;      // dt state, see DTS_* below
   int n[3];
   int tiles[3];

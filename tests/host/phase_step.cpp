@@ -4,21 +4,18 @@
 //
 // 1D and 2D follow the stage kernel's tiles: primitives of every tile cell
 // with its halo, the faces of each direction into the face buffer, the gather
-// per owned cell, then update, source and CFL.  3D follows its two passes:
-// primitives of every cell into the full-grid buffer, then the column tiles
-// marching in z block by block (the plane's cross into LDS, x- and y-faces
-// into the face buffer and their gathers, each column's z-face, update,
-// source and CFL).  The shared-memory tile and the face buffers are exactly
-// the sizes the kernels use and start as NaN (refilled for every plane), so a
-// phase that reads a slot no earlier phase wrote poisons the result; every
-// index the glue forms is asserted in range.
+// per owned cell, then update, source and CFL.  3D follows the three passes:
+// primitives of every cell, faces of each direction, then gather with update,
+// source and CFL.  The shared-memory tile and the face buffers are exactly the
+// sizes the kernels use and start as NaN, so a phase that reads a slot no
+// earlier phase wrote poisons the result; every index the glue forms is
+// asserted in range.
 //
 // Input (binary, native endian): fv_grid, int32 n_mat, n_mat fv_material,
 // fv_options, int64 S, int64 ncell, int32 steps, int32 tile_x, then the
 // primitive state (S x ncell doubles, field-major) and phi0 (ncell doubles).
 // tile_x picks the 2D two-material tile: 32 (32 x 8), 16 (16 x 15 cells on
-// 256 threads), 14 (16 x 14 cells on 256 threads), else 8 x 4; in 3D, 4
-// picks 4 x 4 column tiles, else 16 x 16 (the compiled shape).
+// 256 threads), 14 (16 x 14 cells on 256 threads), else 8 x 4.
 // Output: time, device flag, then the conserved state (S x ncell doubles).
 #include <algorithm>
 #include <cassert>
@@ -28,7 +25,7 @@
 #include <vector>
 
 #include "../../include/fv.h"
-#include "../../paper_2210_04037_amd/csrc/fv_stage3.hpp"
+#include "../../paper_2210_04037_amd/csrc/fv_stage.hpp"
 
 using namespace fv;
 
@@ -65,7 +62,7 @@ struct Run {
   Params P;
   Inst I;
   int64_t nc = 0;
-  std::vector<double> U, U1, U2, phi0, bacc, dts, Wb;
+  std::vector<double> U, U1, U2, phi0, bacc, dts, Wb, Fb[3];
 };
 
 template <int DIM, int NM, int NS>
@@ -106,6 +103,10 @@ static void setup(Run& r, const fv_grid* g, const fv_material* mats, const fv_op
   r.I.dts = r.dts.data();
   if (DIM == 3) {
     r.Wb.assign(L::NW * r.nc, NAN);
+    for (int a = 0; a < 3; ++a) {
+      r.Fb[a].assign(L::NQ * (r.nc / g->n[a] * (g->n[a] + 1)), NAN);
+      r.I.Fb[a] = r.Fb[a].data();
+    }
     r.I.Wb = r.Wb.data();
   }
   double m = 0.0;
@@ -204,78 +205,97 @@ static void step_tiles(Run& r, int nsteps) {
   }
 }
 
-// z-planes per block, as the device kernel
-constexpr int ZCHUNK = 16;
+// face index f of direction a -> transverse cell (c with c[a] = 0) and the
+// face's position i along a, in the order the 3D face pass stores faces
+static void face_pos(int a, int64_t f, int nx, int ny, int c[3], int& i) {
+  c[0] = c[1] = c[2] = 0;
+  if (a == 0) {
+    i = (int)(f % (nx + 1));
+    const int64_t t = f / (nx + 1);
+    c[1] = (int)(t % ny);
+    c[2] = (int)(t / ny);
+  } else if (a == 1) {
+    c[0] = (int)(f % nx);
+    const int64_t t = f / nx;
+    i = (int)(t % (ny + 1));
+    c[2] = (int)(t / (ny + 1));
+  } else {
+    c[0] = (int)(f % nx);
+    const int64_t t = f / nx;
+    c[1] = (int)(t % ny);
+    i = (int)(t / ny);
+  }
+}
 
-template <int NM, int NS, int TX, int TY>
+template <int NM, int NS>
 static void step_3d(Run& r, int nsteps) {
-  using Zt = Zm<NM, NS, double, double, TX, TY>;
-  using St = typename Zt::St;
+  using St = Stage<3, NM, NS, double, double, 1, 1>;
+  using L = Lay<3, NM, NS>;
   const int64_t nc = r.nc;
-  const int nx = r.I.n[0], ny = r.I.n[1], nz = r.I.n[2];
-  const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, nzc = (nz + ZCHUNK - 1) / ZCHUNK;
-  std::vector<double> sm(Zt::smem_elems());
-  double* W = sm.data();
-  double* fb = W + (size_t)Zt::NW * Zt::NCC;
-  std::vector<double> zm((size_t)Zt::NT * Zt::NQ), acc((size_t)Zt::NT * Zt::S);
+  const int nx = r.I.n[0], ny = r.I.n[1];
+  int64_t nf[3];
+  for (int a = 0; a < 3; ++a) nf[a] = nc / r.I.n[a] * (r.I.n[a] + 1);
+  double* Wb = r.Wb.data();
   for (int s = 0; s < nsteps; ++s) {
     const int q = s & 1;
     for (int stage = 1; stage <= 3; ++stage) {
       const double dt = stage_dt(r, stage, q);
-      typename Zt::Ctx cx;
-      init_ctx(cx.s, r, stage, q, dt);
-      std::fill(r.Wb.begin(), r.Wb.end(), NAN);
-      for (int64_t g = 0; g < nc; ++g) St::template cell_prims<int64_t>(cx.s, g, r.Wb.data(), nc, g);
+      typename St::Ctx cx;
+      init_ctx(cx, r, stage, q, dt);
+      for (int64_t g = 0; g < nc; ++g) St::template cell_prims<int64_t>(cx, g, Wb, nc, g);
+      for (int a = 0; a < 3; ++a)
+        for (int64_t f = 0; f < nf[a]; ++f) {
+          int c[3], i;
+          face_pos(a, f, nx, ny, c, i);
+          assert(i >= 0 && i <= r.I.n[a]);
+          int64_t st[4];
+          for (int k = 0; k < 4; ++k) {
+            int cc[3] = {c[0], c[1], c[2]};
+            cc[a] = St::map_index(i - 2 + k, r.I.n[a], r.I.bc[a][0], r.I.bc[a][1]);
+            for (int d = 0; d < 3; ++d) assert(cc[d] >= 0 && cc[d] < r.I.n[d]);
+            st[k] = ((int64_t)cc[2] * ny + cc[1]) * nx + cc[0];
+          }
+          const int64_t bslot = a == 0 ? (int64_t)c[2] * ny + c[1]
+                                       : (a == 1 ? (int64_t)c[2] * nx + c[0]
+                                                 : (int64_t)c[1] * nx + c[0]);
+          assert(bslot >= 0 && bslot < nc / r.I.n[a]);
+          St::template compute_face<int64_t>(cx, Wb, nc, a, st[0], st[1], st[2], st[3], i, f,
+                                             nf[a], bslot, r.Fb[a].data());
+        }
       double bmax = 0.0;
-      for (int b = 0; b < ntx * nty * nzc; ++b) {
-        cx.bx = b % ntx;
-        cx.by = (b / ntx) % nty;
-        cx.z0 = (b / ntx / nty) * ZCHUNK;
-        cx.z1 = std::min(cx.z0 + ZCHUNK, nz);
-        std::fill(sm.begin(), sm.end(), NAN);
-        for (int tid = 0; tid < Zt::NT; ++tid) {
-          int tx, ty;
-          if (!Zt::own_column(cx, tid, tx, ty)) continue;
-          Zt::zface(cx, tx, ty, cx.z0, fb, tid, Zt::NFACE);
-          for (int v = 0; v < Zt::NQ; ++v) zm[(size_t)tid * Zt::NQ + v] = fb[v * Zt::NFACE + tid];
+      for (int64_t g = 0; g < nc; ++g) {
+        double Xc[3], uc[3], phic[NM], Vc[3][3];
+        for (int k = 0; k < 3; ++k) {
+          Xc[k] = Wb[(L::W_X + k) * nc + g];
+          uc[k] = Wb[(L::R_U + k) * nc + g];
         }
-        for (int z = cx.z0; z < cx.z1; ++z) {
-          std::fill(sm.begin(), sm.end(), NAN);
-          for (int c = 0; c < Zt::NCC; ++c) Zt::load_cross(cx, z, c, W);
-          std::fill(acc.begin(), acc.end(), 0.0);
-          for (int a = 0; a < 2; ++a) {
-            std::fill(fb, fb + (size_t)Zt::NQ * Zt::NFACE, NAN);
-            for (int it = 0; it < Zt::face_items(a); ++it) {
-              int cm, c0, c1, c2, gf, fs;
-              int64_t bs;
-              if (!Zt::face_item(cx, a, z, it, cm, c0, c1, c2, gf, fs, bs)) continue;
-              for (int k : {cm, c0, c1, c2}) assert(k >= 0 && k < Zt::NCC);
-              assert(fs >= 0 && fs < Zt::NFACE);
-              assert(bs >= 0 && bs < nc / r.I.n[a]);
-              St::template compute_face<int>(cx.s, W, Zt::NCC, a, cm, c0, c1, c2, gf, fs,
-                                             Zt::NFACE, bs, fb);
-            }
-            for (int tid = 0; tid < Zt::NT; ++tid) {
-              int tx, ty;
-              if (Zt::own_column(cx, tid, tx, ty))
-                Zt::gather_xy(cx, W, fb, a, tx, ty, &acc[(size_t)tid * Zt::S]);
-            }
+        for (int l = 0; l < NM; ++l) phic[l] = Wb[(L::R_PHI + l) * nc + g];
+        for (int v = 0; v < L::NV; ++v) Vc[vb_i<3>(v)][vb_j<3>(v)] = Wb[(L::R_V + v) * nc + g];
+        const int x = (int)(g % nx);
+        const int64_t t = g / nx;
+        const int y = (int)(t % ny), z = (int)(t / ny);
+        double acc[L::S] = {};
+        for (int a = 0; a < 3; ++a) {
+          int64_t fm, fp;
+          if (a == 0) {
+            fm = ((int64_t)z * ny + y) * (nx + 1) + x;
+            fp = fm + 1;
+          } else if (a == 1) {
+            fm = ((int64_t)z * (ny + 1) + y) * nx + x;
+            fp = fm + nx;
+          } else {
+            fm = g;
+            fp = g + (int64_t)nx * ny;
           }
-          std::fill(fb, fb + (size_t)Zt::NQ * Zt::NFACE, NAN);
-          for (int tid = 0; tid < Zt::NT; ++tid) {
-            int tx, ty;
-            if (!Zt::own_column(cx, tid, tx, ty)) continue;
-            double* zr = &zm[(size_t)tid * Zt::NQ];
-            Zt::zface(cx, tx, ty, z + 1, fb, tid, Zt::NFACE);
-            Zt::gather_z(cx, W, zr, fb, tid, tx, ty, &acc[(size_t)tid * Zt::S]);
-            for (int v = 0; v < Zt::NQ; ++v) zr[v] = fb[v * Zt::NFACE + tid];
-            const int64_t g = Zt::cell_index(r.I, cx.bx * TX + tx, cx.by * TY + ty, z);
-            assert(g >= 0 && g < nc);
-            bool bad = false;
-            bmax = std::max(bmax, St::finish_cell(cx.s, g, &acc[(size_t)tid * Zt::S], &bad));
-            if (bad) r.dts[DTS_FLAG] = 1.0;
-          }
+          assert(fm >= 0 && fp < nf[a]);
+          typename St::FaceC mf, pf;
+          St::template face_contrib<int64_t>(r.Fb[a].data(), fm, nf[a], a, 1, Xc, Vc, uc, mf);
+          St::template face_contrib<int64_t>(r.Fb[a].data(), fp, nf[a], a, 0, Xc, Vc, uc, pf);
+          St::gather_dir(cx, a, mf, pf, Xc, uc, phic, Vc, acc);
         }
+        bool bad = false;
+        bmax = std::max(bmax, St::finish_cell(cx, g, acc, &bad));
+        if (bad) r.dts[DTS_FLAG] = 1.0;
       }
       if (stage == 3) r.dts[dts_slot(1 - q, 0)] = bmax;
     }
@@ -342,12 +362,10 @@ int main(int argc, char** argv) {
     step_tiles<2, 2, 1, 8, 4>(r, nsteps);
   } else if (g.dim == 3 && nm == 1) {
     setup<3, 1, 1>(r, &g, m, &o, P, Z);
-    if (tx == 4) step_3d<1, 1, 4, 4>(r, nsteps);
-    else step_3d<1, 1, 16, 16>(r, nsteps);
+    step_3d<1, 1>(r, nsteps);
   } else if (g.dim == 3) {
     setup<3, 2, 1>(r, &g, m, &o, P, Z);
-    if (tx == 4) step_3d<2, 1, 4, 4>(r, nsteps);
-    else step_3d<2, 1, 16, 16>(r, nsteps);
+    step_3d<2, 1>(r, nsteps);
   } else {
     std::fprintf(stderr, "phase_step: unsupported dimension\n");
     return 2;

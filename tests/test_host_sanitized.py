@@ -3,8 +3,7 @@ source, CFL), stepped on the CPU by tests/host/phase_step.cpp under
 AddressSanitizer and UndefinedBehaviorSanitizer, against the oracle.
 
 The harness drives the same tile walk as the 2D stage kernel (halo loads,
-face items, per-cell gather) and the same two passes as the 3D path (the
-primitive pass, then column tiles marching in z over chunks of planes), with
+face items, per-cell gather) and the same three passes as the 3D path, with
 NaN-filled scratch and asserted indices, so an out-of-range access, a slot
 read before it is written, or undefined arithmetic (signed overflow, bad
 shifts, misaligned loads) ends the run; the state it produces must still
@@ -92,7 +91,7 @@ def _assert_matches_oracle(case, steps, t, flag, U, L):
 @pytest.mark.parametrize("which,steps", [
     ("spall1d", 12), ("ring2d", 4), ("ring2d_wide", 3), ("ring2d_spare", 3),
     ("ring2d_spare14", 3),
-    ("shell3d", 2), ("shell3d_chunks", 2), ("shell3d_t4", 2),
+    ("shell3d", 2),
     ("impact3d", 2)])
 def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
     tile_x = 0
@@ -111,11 +110,6 @@ def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
         tile_x = 14
     elif which == "shell3d":
         case = F.make_case(3, n=10)
-    elif which == "shell3d_chunks":
-        case = F.make_case(3, n=20)            # two z-chunks (16 + 4), ragged tiles
-    elif which == "shell3d_t4":
-        case = F.make_case(3, n=11)            # 4 x 4 column tiles, ragged
-        tile_x = 4
     else:
         case = F.make_case(5, n=9)
     t, flag, U, L = _run(exe, tmp_path, case, steps, tile_x)
