@@ -35,6 +35,17 @@ GAS = dict(
 )
 P_ATM = 1.0e5
 
+# 304L stainless steel of the expanding disk, all from the paper's Appendix A
+# rows: Romenskii table (rho0, K0, G0, alpha, beta, Gamma0), the Johnson-Cook
+# table's initial yield c1 (hardening, rate and thermal terms are not part
+# of this build: the yield is constant) and hardening exponent n, and the
+# Bonora table's expanding-disk row (D_crit, eps_thresh, eps_crit, alpha).
+STEEL_304L = dict(
+    kind="solid", rho0=8000.0, K0=158.3e9, alpha=0.569, G0=73.1e9, beta=2.437,
+    Gamma0=1.84, yield_stress=0.253e9, D_crit=0.3, D0=0.0, eps_th=0.002,
+    eps_c=0.5, bonora_alpha=0.5, n_hard=0.313, p_gate=0.0,
+)
+
 
 def vbar_components(dim):
     """Stored (i, j) components of the unimodular stretch, row-major:
@@ -73,6 +84,8 @@ class Case:
     t_end: float
     cfl: float = 0.6
     meta: dict = field(default_factory=dict)
+    # void-fraction threshold of the Lagrangian seeding (0: off)
+    seed_nu: float = 0.0
 
     @property
     def dx(self):
@@ -313,6 +326,33 @@ def make_case(config, n=None, member=None, t_end=None):
         return Case("impact3d", 3, grid, lo, hi, bc, mats, prim, phi0,
                     t_end if t_end is not None else 3.0e-6)
     raise ValueError(f"unknown workload {config}")
+
+
+def expanding_disk(n=400, t_end=200.0e-6, corr_len=1.0e-3, seed=221004043):
+    """The expanding disk of the paper's validation section: a 304L disk of
+    radius 10 cm centred in a [-13, 13]^2 cm domain of void, radial velocity
+    u = 2000 r (1/s), Gaussian phi0 (mean 1, std 0.1, rectified), CFL 0.4,
+    200 us, transmissive sides, Lagrangian seeding into cells of void
+    fraction above 0.99.  The paper leaves the correlation length of phi0
+    open: 1 mm here (1.5 cells at 400^2).  Void cells hold the solid at the
+    volume-fraction floor, at its reference density and zero pressure."""
+    lo, hi = (-0.13, -0.13, 0.0), (0.13, 0.13, 1.0)
+    grid = (n, n, 1)
+    mats = [dict(STEEL_304L)]
+
+    def ind(X, Y, Z):
+        return X * X + Y * Y <= 0.1 * 0.1
+
+    def vel(X, Y, Z):
+        return [2000.0 * X, 2000.0 * Y]
+
+    frac, u = _subsample(2, grid, lo, hi, ind, vel, mats[0]["rho0"], 1.0e-30)
+    prim = _assemble(2, mats, frac, u, 0.0, grid, lo, hi)
+    d = (hi[0] - lo[0]) / n
+    phi0 = gaussian_field((1, n, n), (1.0, d, d), corr_len, 0.1, seed)
+    bc = (("transmissive",) * 2,) * 3
+    return Case("disk2d", 2, grid, lo, hi, bc, mats, prim, phi0, t_end,
+                cfl=0.4, seed_nu=0.99)
 
 
 def spall_strip(dim, n_long=100, n_trans=8, bump=0.5e-3, v=200.0, seed=None,

@@ -16,6 +16,8 @@ Modules:
               SSP-RK3 update, CFL (Sections 3.1, 3.2.1)
   source      plastic return, Bonora damage by RK4, phi0 gather
               (Sections 2.1, 2.2, 3.1, 3.2.2)
+  seeding     Lagrangian coordinates of void cells extrapolated from the
+              material (Section 3.2.1 seeding routine)
   totals      correctly rounded conservation totals
   fragments   fragment labelling and masses (Section 4 fragment delineation)
   solver      time stepping driver

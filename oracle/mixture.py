@@ -34,10 +34,12 @@ C_MIN2 = 1.0e-6       # floor on c^2 [m^2/s^2]
 
 class Options:
     def __init__(self, phi_floor=1.0e-8, cfl=0.6, weno_eps=1.0e-6,
-                 crit_rel_tol=None):
+                 crit_rel_tol=None, seed_nu=0.0):
         self.phi_floor = phi_floor
         self.cfl = cfl
         self.weno_eps = weno_eps
+        # void-fraction threshold of the Lagrangian seeding (0: off)
+        self.seed_nu = seed_nu
         # band of the critical-damage test (None: the double-precision
         # reading, closures.CRIT_REL_TOL)
         self.crit_rel_tol = crit_rel_tol

@@ -12,6 +12,7 @@ from .layout import Layout
 from .mixture import Options, prim_to_cons, cons_to_prim
 from .scheme import Geometry, rhs, clamp_phi, dt_inverse
 from .source import source_step
+from .seeding import seed_void
 from .totals import interior_totals, boundary_totals
 from . import fragments as _frag
 
@@ -19,7 +20,8 @@ from . import fragments as _frag
 class Solver:
     def __init__(self, case, opts=None):
         self.case = case
-        self.opts = opts or Options(cfl=case.cfl)
+        self.opts = opts or Options(cfl=case.cfl,
+                                    seed_nu=getattr(case, "seed_nu", 0.0))
         self.layout = Layout(case.dim, case.mats)
         self.geom = Geometry(case.dim, case.n, case.lo, case.hi, case.bc)
         self.U = prim_to_cons(case.prim.copy(), self.layout, self.opts)
@@ -61,6 +63,8 @@ class Solver:
         self._accumulate(b2, dt / 6.0)
         self._accumulate(b3, dt * (2.0 / 3.0))
         self.U = source_step(U3, self.phi0, g, L, o)
+        if getattr(o, "seed_nu", 0.0) > 0.0:
+            self.U = seed_void(self.U, g, L, o.seed_nu)
         self.t += dt
         self.steps += 1
         return dt
