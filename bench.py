@@ -11,9 +11,10 @@ The headline is the largest single-GPU workload: the 3D plate impact on
 inclusions), FP32-bulk timed, the plain FP64 form timed after it on the same
 input, and the per-field L1 error of the FP32-bulk run against the FP64 run.
 The same JSON line carries the 2D expanding ring at 1024^2 (both forms, plus
-a window timed after fracture: the run restarts from its state at 20 us) and
+a window timed after fracture: the run restarts from its state at 20 us),
 the batched ensemble of 64 rings of uneven sizes in one context (FP32-bulk,
-beside a loop of the same members run one context at a time).
+beside a loop of the same members run one context at a time) and the 400^2
+expanding disk in void with Lagrangian seeding (both forms).
 
 Prints one JSON line: cell-updates/s, the roofline of the dominant (stage)
 kernel and the CPU oracle timed on a bounded window of the headline
@@ -364,6 +365,13 @@ def make_workload(name, n=None, members=64):
                 "(0.2 mm, 5%)")
         x0 = int(ne * (0.5 + 0.4292 * 0.7071)) - 48     # on the ring, 45 deg
         return cases, desc, ((x0, x0, 0), 96)
+    if name == "disk":
+        ne = n or 400
+        cases = [F.expanding_disk(ne)]
+        desc = (f"2D expanding disk {ne}x{ne} over a 26 cm square: 304L disk of "
+                "radius 10 cm in void at u = 2000 r, Gaussian phi0 (std 0.1), "
+                "Lagrangian seeding of void cells, CFL 0.4")
+        return cases, desc, None
     if name == "ensemble":
         cases = [F.make_case(4, member=m) for m in range(members)]
         desc = (f"ensemble of {members} seeded 2D expanding rings, edges drawn "
@@ -481,7 +489,7 @@ def main():
                          "full size)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="impact3d",
-                    choices=["impact3d", "ring", "ensemble", "shell3d"],
+                    choices=["impact3d", "ring", "ensemble", "shell3d", "disk"],
                     help="headline workload: impact3d, the 512^3 plate impact "
                          "(default, the largest single-GPU workload); ring: "
                          "the 1024^2 expanding ring; ensemble: 64 seeded "
@@ -556,9 +564,9 @@ def main():
     del cases
     if not args.only and head == "impact3d":
         others = {}
-        for name in ("ring", "ensemble"):
+        for name in ("ring", "ensemble", "disk"):
             c2, d2, _ = make_workload(name, None, args.members)
-            m = measure(name, c2, d2, args, compare=name == "ring"
+            m = measure(name, c2, d2, args, compare=name in ("ring", "disk")
                         and not args.no_compare,
                         post_fracture=(args.post_fracture if name == "ring"
                                        and args.post_fracture > 0 else None))

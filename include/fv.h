@@ -109,7 +109,12 @@ typedef struct {
  * them) or fv_init fails with FV_EINVAL, as does a schedule outside 0..2.
  * Results depend on neither.  use_graph:
  * nonzero makes fv_step capture its n_steps steps into a HIP graph at the
- * first call with that step count and replay it afterwards. */
+ * first call with that step count and replay it afterwards.  seed_nu: the
+ * Lagrangian seeding of Section 3.2.1 -- after each step, every cell whose
+ * void fraction 1 - sum phi_l exceeds seed_nu (and has a void-fraction
+ * gradient) takes Lagrangian coordinates extrapolated from the point 1.5
+ * cells towards the material, X(p) - (p - c); 0 turns it off (the default
+ * of the workloads surrounded by gas), values in [0, 1). */
 typedef struct {
   int32_t precision;
   double cfl;
@@ -118,6 +123,7 @@ typedef struct {
   double phi_fp64_cut;
   int32_t tile[3];
   int32_t use_graph;
+  double seed_nu;
 } fv_options;
 
 /* Number of state fields S for a dimension and material list (the first
@@ -179,7 +185,9 @@ int32_t fv_cfl_dt(fv_ctx* ctx, double* dt_host);
  * modifier of Section 3.1), then the source step (radial return to the
  * perturbed yield of Section 2.4, Bonora damage integrated by RK4 as in
  * Section 3.1, phi0 interpolated at the Lagrangian coordinates as in
- * Section 3.2.2) and the CFL reduction for the next step.  dt_host: NULL to
+ * Section 3.2.2), the Lagrangian seeding of void cells when
+ * fv_options.seed_nu is set (Section 3.2.1) and the CFL reduction for the
+ * next step.  dt_host: NULL to
  * use the device CFL step, else [n_inst] fixed steps.  t_end: NULL to keep
  * the current end times, else [n_inst]; an instance at its end time does no
  * work. */

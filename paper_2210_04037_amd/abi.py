@@ -41,7 +41,8 @@ class FvOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("cfl", ctypes.c_double),
                 ("phi_floor", ctypes.c_double), ("weno_eps", ctypes.c_double),
                 ("phi_fp64_cut", ctypes.c_double),
-                ("tile", ctypes.c_int32 * 3), ("use_graph", ctypes.c_int32)]
+                ("tile", ctypes.c_int32 * 3), ("use_graph", ctypes.c_int32),
+                ("seed_nu", ctypes.c_double)]
 
 
 class FvFragment(ctypes.Structure):
@@ -152,7 +153,7 @@ def material_array(mats):
 
 
 def options_struct(precision="fp64", cfl=0.6, phi_floor=1e-8, weno_eps=1e-6,
-                   phi_fp64_cut=1e-6, tile=None, use_graph=False):
+                   phi_fp64_cut=1e-6, tile=None, use_graph=False, seed_nu=0.0):
     o = FvOptions()
     o.precision = PRECISIONS[precision]
     o.cfl = cfl
@@ -164,6 +165,7 @@ def options_struct(precision="fp64", cfl=0.6, phi_floor=1e-8, weno_eps=1e-6,
         for k, v in enumerate(tile):
             o.tile[k] = int(v)
     o.use_graph = 1 if use_graph else 0
+    o.seed_nu = float(seed_nu)
     return o
 
 

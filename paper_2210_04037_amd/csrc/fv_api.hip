@@ -129,6 +129,7 @@ static int validate(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
   if (!(opt->cfl > 0 && opt->cfl <= 1)) { msg = "cfl must be in (0, 1]"; return FV_EINVAL; }
   if (!(opt->phi_floor > 0 && opt->phi_floor < 0.5)) { msg = "phi_floor must be in (0, 0.5)"; return FV_EINVAL; }
   if (!(opt->weno_eps > 0)) { msg = "weno_eps must be > 0"; return FV_EINVAL; }
+  if (!(opt->seed_nu >= 0 && opt->seed_nu < 1)) { msg = "seed_nu must be in [0, 1)"; return FV_EINVAL; }
   if (opt->tile[2] < FV_SCHED_BY_INSTANCE || opt->tile[2] > FV_SCHED_INTERLEAVED) {
     msg = "tile[2] must be a block schedule (0, 1 or 2)"; return FV_EINVAL;
   }
@@ -239,6 +240,7 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
   P.weno_eps = opt->weno_eps;
   P.c_min2 = 1.0e-6;
   P.phi_fp64_cut = opt->phi_fp64_cut;
+  P.seed_nu = opt->seed_nu;
   set_float_constants(P);
 }
 
@@ -700,6 +702,7 @@ int32_t fv_step(fv_ctx* c, const double* dt_host, int32_t n_steps, const double*
     for (int s = 0; s < n_steps; ++s) {
       const int parity = (p0 + s) & 1;
       for (int st = 1; st <= 3; ++st) c->ops.stage(c, st, parity, c->stream);
+      if (c->P.seed_nu > 0) c->ops.seed(c, parity, c->stream);
     }
     c->step += n_steps;
     return hip_check(c, hipGetLastError(), "stage kernel launch");
@@ -729,6 +732,7 @@ int32_t fv_step(fv_ctx* c, const double* dt_host, int32_t n_steps, const double*
     for (int s = 0; s < n_steps; ++s) {
       const int parity = (p0 + s) & 1;
       for (int st = 1; st <= 3; ++st) c->ops.stage(c, st, parity, c->cap_stream);
+      if (c->P.seed_nu > 0) c->ops.seed(c, parity, c->cap_stream);
     }
     hipGraph_t graph = nullptr;
     const hipError_t le = hipGetLastError();

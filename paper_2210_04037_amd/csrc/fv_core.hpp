@@ -98,6 +98,7 @@ struct Params {
   double weno_eps;
   double c_min2;
   double phi_fp64_cut;
+  double seed_nu;      // void fraction above which X is reseeded (0: off)
   float f_weno_eps, f_c_min2, f_phi_fp64_cut, f_pad;
 };
 

@@ -254,6 +254,44 @@ __global__ void __launch_bounds__(256) cons_to_prim_kernel(const Inst* insts, in
   for (int f = 0; f < L::S; ++f) prim[(int64_t)f * I.ncell + g] = W[f];
 }
 
+// Lagrangian seeding after the step of parity `parity` (Section 3.2.1): the
+// coordinates every cell takes (reseeded or kept) go to the X rows of the
+// stage-1 buffer, free until the next step, and a second pass copies them
+// back, so that every cell is seeded from the coordinates before seeding.
+// An instance that did not step (at its end time) is left alone.
+__device__ __forceinline__ bool stepped(const Inst& I, int parity) {
+  const int q = parity & 1;
+  return I.dts[DTS_T + 1 - q] != I.dts[DTS_T + q];
+}
+
+template <int DIM, int NM, int NS, class T>
+__global__ void __launch_bounds__(256) seed_kernel(const Inst* insts, int ii, Params P,
+                                                   int parity) {
+  using L = Lay<DIM, NM, NS>;
+  using St = Stage<DIM, NM, NS, T, T, 1, 1>;
+  const Inst& I = insts[ii];
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= I.ncell || !stepped(I, parity)) return;
+  double Xn[DIM];
+  St::seed_cell(P, I, (const T*)I.U, g, Xn);
+  T* out = (T*)I.U1;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) out[(int64_t)(L::XC + k) * I.ncell + g] = (T)Xn[k];
+}
+
+template <int DIM, int NM, int NS, class T>
+__global__ void __launch_bounds__(256) seed_copy_kernel(const Inst* insts, int ii, int parity) {
+  using L = Lay<DIM, NM, NS>;
+  const Inst& I = insts[ii];
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= I.ncell || !stepped(I, parity)) return;
+  const T* src = (const T*)I.U1;
+  T* U = (T*)I.U;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k)
+    U[(int64_t)(L::XC + k) * I.ncell + g] = src[(int64_t)(L::XC + k) * I.ncell + g];
+}
+
 template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
 __global__ void __launch_bounds__(256) cfl_kernel(const Inst* insts, int ii, Params P, int parity) {
   using St = Stage<DIM, NM, NS, T, C, TX, TY>;

@@ -22,6 +22,7 @@ struct Ops {
   void (*p2c)(fv_ctx*, int, const double*) = nullptr;
   void (*c2p)(fv_ctx*, int, double*) = nullptr;
   void (*cfl)(fv_ctx*, int, int) = nullptr;
+  void (*seed)(fv_ctx*, int, hipStream_t) = nullptr;
   size_t elem = 8;
 };
 
@@ -81,6 +82,16 @@ void common_ops(Ops& o) {
     const int64_t n = c->insts[ii].ncell;
     hipLaunchKernelGGL((cons_to_prim_kernel<DIM, NM, NS, T>), dim3((unsigned)((n + 255) / 256)),
                        dim3(256), 0, c->stream, c->insts_d, ii, c->P, prim);
+  };
+  o.seed = [](fv_ctx* c, int parity, hipStream_t s) {
+    for (int ii = 0; ii < c->n_inst; ++ii) {
+      const int64_t n = c->insts[ii].ncell;
+      const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
+      hipLaunchKernelGGL((seed_kernel<DIM, NM, NS, T>), grid, blk, 0, s, c->insts_d, ii, c->P,
+                         parity);
+      hipLaunchKernelGGL((seed_copy_kernel<DIM, NM, NS, T>), grid, blk, 0, s, c->insts_d, ii,
+                         parity);
+    }
   };
   o.cfl = [](fv_ctx* c, int ii, int parity) {
     const int64_t n = c->insts[ii].ncell;

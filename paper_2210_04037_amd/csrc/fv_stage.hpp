@@ -756,7 +756,14 @@ struct Stage {
   // Source step on the new state of one cell (FP64), Section 2.4 / 3.1 /
   // 3.2.2 readings: phi0 gather, radial return, Bonora RK4, Vbar rebuild.
   FV_HD static double phi0_gather(const Inst& I, const double* X) {
-    const T* f = (const T*)I.phi0;
+    return gather_field(I, (const T*)I.phi0, X);
+  }
+
+  // Multilinear interpolation of a cell-centred field f (one field of
+  // ncell values) at position X, clamped to the span of the cell centres;
+  // nested linear interpolations, x first, so a constant field is returned
+  // exactly.
+  FV_HD static double gather_field(const Inst& I, const T* f, const double* X) {
     int i0[3] = {0, 0, 0};
     double w[3] = {0, 0, 0};
 #pragma unroll
@@ -788,6 +795,60 @@ struct Stage {
     const double f2 = lerp(at(0, 0, 1), at(1, 0, 1), w[0]);
     const double f3 = lerp(at(0, 1, 1), at(1, 1, 1), w[0]);
     return lerp(g0, lerp(f2, f3, w[1]), w[2]);
+  }
+
+  // Lagrangian seeding of cell g (Section 3.2.1 seeding routine) from the
+  // state U after the step: if the cell's void fraction exceeds seed_nu and
+  // the void fraction has a gradient there (central differences, one-sided at
+  // a domain side), its coordinates are extrapolated from the point probed
+  // 1.5 cells towards the material, X(p) - (p - c); otherwise they are kept.
+  // Xn: the cell's coordinates after seeding (DIM values).
+  FV_HD static void seed_cell(const Params& P, const Inst& I, const T* U, int64_t g,
+                              double* Xn) {
+    const int64_t nc = I.ncell;
+    int ix[3];
+    {
+      int64_t r = g;
+      ix[0] = (int)(r % I.n[0]);
+      r /= I.n[0];
+      ix[1] = (int)(r % I.n[1]);
+      ix[2] = (int)(r / I.n[1]);
+    }
+    auto nu_at = [&](int64_t h) -> double {
+      double sphi = 0.0;
+#pragma unroll
+      for (int l = 0; l < NM; ++l) sphi += (double)U[(int64_t)(L::PHI + l) * nc + h];
+      sphi = sphi < 0.0 ? 0.0 : (sphi > 1.0 ? 1.0 : sphi);
+      return 1.0 - sphi;
+    };
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) Xn[k] = (double)U[(int64_t)(L::XC + k) * nc + g];
+    if (!(nu_at(g) > P.seed_nu)) return;
+    const int64_t stride[3] = {1, (int64_t)I.n[0], (int64_t)I.n[0] * I.n[1]};
+    double grad[3] = {0.0, 0.0, 0.0}, n2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const int nk = I.n[k];
+      if (nk < 2) continue;
+      if (ix[k] == 0) grad[k] = (nu_at(g + stride[k]) - nu_at(g)) / I.dx[k];
+      else if (ix[k] == nk - 1) grad[k] = (nu_at(g) - nu_at(g - stride[k])) / I.dx[k];
+      else grad[k] = (nu_at(g + stride[k]) - nu_at(g - stride[k])) / (2.0 * I.dx[k]);
+      n2 += grad[k] * grad[k];
+    }
+    if (!(n2 > 0.0)) return;
+    const double nrm = sqrt(n2);
+    double h = I.dx[0];
+#pragma unroll
+    for (int k = 1; k < DIM; ++k) h = I.dx[k] < h ? I.dx[k] : h;
+    double c[3] = {0.0, 0.0, 0.0}, p[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      c[k] = I.lo[k] + (ix[k] + 0.5) * I.dx[k];
+      p[k] = c[k] - 1.5 * h * grad[k] / nrm;
+    }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+      Xn[k] = gather_field(I, U + (int64_t)(L::XC + k) * nc, p) - (p[k] - c[k]);
   }
 
   // Returns the cell's CFL sum  sum_a (|u_a| + c)/dx_a  after the source step.

@@ -55,6 +55,7 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
   P.weno_eps = opt->weno_eps;
   P.c_min2 = 1.0e-6;
   P.phi_fp64_cut = opt->phi_fp64_cut;
+  P.seed_nu = opt->seed_nu;
   set_float_constants(P);
 }
 
@@ -148,6 +149,23 @@ static void init_ctx(Ctx& cx, Run& r, int stage, int q, double dt) {
   cx.out = stage == 1 ? r.U1.data() : (stage == 2 ? r.U2.data() : r.U.data());
 }
 
+// Lagrangian seeding after a step, as the device's two passes: every cell's
+// new coordinates from the state before seeding, then copied back.
+template <int DIM, int NM, int NS>
+static void seed_all(Run& r) {
+  using St = Stage<DIM, NM, NS, double, double, 1, 1>;
+  using L = Lay<DIM, NM, NS>;
+  if (!(r.P.seed_nu > 0)) return;
+  std::vector<double> X((size_t)DIM * r.nc, NAN);
+  for (int64_t g = 0; g < r.nc; ++g) {
+    double Xn[DIM];
+    St::seed_cell(r.P, r.I, r.U.data(), g, Xn);
+    for (int k = 0; k < DIM; ++k) X[(size_t)k * r.nc + g] = Xn[k];
+  }
+  for (int k = 0; k < DIM; ++k)
+    for (int64_t g = 0; g < r.nc; ++g) r.U[(size_t)(L::XC + k) * r.nc + g] = X[(size_t)k * r.nc + g];
+}
+
 template <int DIM, int NM, int NS, int TX, int TY, int NTH = TX * TY>
 static void step_tiles(Run& r, int nsteps) {
   using St = Stage<DIM, NM, NS, double, double, TX, TY, NTH>;
@@ -202,6 +220,7 @@ static void step_tiles(Run& r, int nsteps) {
         }
       if (stage == 3) r.dts[dts_slot(1 - q, 0)] = bmax;
     }
+    seed_all<DIM, NM, NS>(r);
   }
 }
 
@@ -299,6 +318,7 @@ static void step_3d(Run& r, int nsteps) {
       }
       if (stage == 3) r.dts[dts_slot(1 - q, 0)] = bmax;
     }
+    seed_all<3, NM, NS>(r);
   }
 }
 

@@ -47,7 +47,8 @@ def _write_input(path, case, steps, tile_x):
         f.write(bytes(abi.grid_struct(case)))
         f.write(np.int32(len(case.mats)).tobytes())
         f.write(bytes(abi.material_array(case.mats)))
-        f.write(bytes(abi.options_struct("fp64", case.cfl)))
+        f.write(bytes(abi.options_struct("fp64", case.cfl,
+                                         seed_nu=getattr(case, "seed_nu", 0.0))))
         f.write(np.int64(L.S).tobytes())
         f.write(np.int64(ncell).tobytes())
         f.write(np.int32(steps).tobytes())
@@ -92,7 +93,7 @@ def _assert_matches_oracle(case, steps, t, flag, U, L):
     ("spall1d", 12), ("ring2d", 4), ("ring2d_wide", 3), ("ring2d_spare", 3),
     ("ring2d_spare14", 3),
     ("shell3d", 2),
-    ("impact3d", 2)])
+    ("impact3d", 2), ("disk2d", 40)])
 def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
     tile_x = 0
     if which == "spall1d":
@@ -110,6 +111,8 @@ def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
         tile_x = 14
     elif which == "shell3d":
         case = F.make_case(3, n=10)
+    elif which == "disk2d":
+        case = F.expanding_disk(20)            # void around the disk: seeding
     else:
         case = F.make_case(5, n=9)
     t, flag, U, L = _run(exe, tmp_path, case, steps, tile_x)
