@@ -13,9 +13,11 @@ paper's mechanical and thermal equilibrium assumption (Section 2.1):
       sigma = -(1 - nu) p I + 2 G_mix dev(H),  G_mix = sum phi_l G_l
     (this makes the mixture work rate equal sum phi_l p_l div u, the
     energy-consistent choice; with no void it is -p I + 2 G dev H)
-  * trace materials (phi < PHI_TRACE) are evaluated at their reference
-    density, and the thermal energy density is taken non-negative in the
-    pressure inversion (both guard cells emptied to near vacuum).
+  * trace materials (phi < PHI_TRACE) take the vanishing-density limit of
+    their closures: no reference energy, pressure, stiffness or shear
+    modulus, only their Grueneisen share in the thermal part; the thermal
+    energy density is taken non-negative in the pressure inversion (both
+    guard cells emptied to near vacuum).
   * sound speed: the frozen (Allaire) mixture bulk speed scaled by (1 - nu),
     plus the shear contribution, c^2 = c_b^2 + (4/3) G_mix / rho; each
     phase's thermal term (Gamma+1)(p - p_ref) enters non-negative (a state
@@ -46,23 +48,38 @@ class Options:
 
 
 # Volume fraction below which a material is a trace: its phasic density, the
-# ratio of two trace quantities, is noise, so its closures are evaluated at
-# its reference density (its contribution is of the order of the fraction).
+# ratio of two trace quantities, is noise.  A trace material takes the limit
+# of its closures as its phasic density vanishes, where the Romenskii cold
+# energy, cold pressure, stiffness and shear modulus all go to zero: it
+# carries no reference terms and no shear stiffness, and enters the mixture
+# only through its Grueneisen share of the thermal part.  The trace solids
+# that matter are the ones left in cells emptied to near vacuum, whose phasic
+# density is far below rho0; there the limit is continuous with the closures
+# just above the threshold.  (Evaluating a trace at its reference density
+# instead gives it the full modulus G0: in a near-vacuum cell whose stretch
+# the return no longer bounds -- an expanded solid has almost no modulus, so
+# any distortion is elastic -- crossing the threshold then switched on a
+# reference energy phi G0 J^2 larger than the cell's whole energy.)
 PHI_TRACE = 1.0e-6
 
 
 def closure_density(phi_l, rho_l, m):
+    """Density at which closures that need one (the triaxiality's rho0/rho)
+    are evaluated: the reference density for a trace material."""
     return np.where(phi_l < PHI_TRACE, m["rho0"], rho_l)
 
 
 def material_terms(rho_l, D_l, J2, mats, phi=None):
-    """Per-material (rho e_ref, p_ref, rho dp_ref/drho, G) lists; trace
-    materials (phi < PHI_TRACE) at their reference density."""
+    """Per-material (rho e_ref, p_ref, rho dp_ref/drho, G) lists; zero for a
+    trace material (phi < PHI_TRACE)."""
     out = []
     for l, m in enumerate(mats):
         D = D_l[l] if l in D_l else np.zeros_like(J2)
-        r = rho_l[l] if phi is None else closure_density(phi[l], rho_l[l], m)
-        out.append(ref_terms(r, J2, D, m))
+        t = ref_terms(rho_l[l], J2, D, m)
+        if phi is not None:
+            live = phi[l] >= PHI_TRACE
+            t = tuple(np.where(live, v, 0.0) for v in t)
+        out.append(t)
     return out
 
 

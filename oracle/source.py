@@ -13,7 +13,12 @@ the paper is silent on the splitting).  Readings:
     sum phi_l (1-D_l) G~_l, so J_max = Y_mix / (sqrt(6) G_mix); for one solid
     this is phi sigma_Y / (sqrt(6) G~), the effective-stress form.  The yield
     is constant (sigma_Y) and drops to zero once D >= D_crit (Section 3.1,
-    second healing remark).  Delta eps_p = sqrt(2/3) (J - J_max).
+    second healing remark).  Delta eps_p = sqrt(2/3) (J - J_max).  Trace
+    solids (volume fraction below the mixture's trace threshold) have no
+    shear stiffness and take no part in the sums; a cell whose mixture
+    modulus is zero carries no elastic distortion (Vbar is reset to the
+    identity, the stress does not depend on it) and does no plastic work
+    (Delta eps_p = 0, so no damage either).
   * damage (Section 2.2 Bonora rate with the Pirondi-Bonora gate, Section 3.1
     RK4): gate frozen at the start of the step (p < p_gate, eps_p^n above the
     triaxiality-dependent threshold, Delta eps_p > 0, D < D_crit); triaxiality
@@ -30,7 +35,7 @@ from .closures import (solid_shear_modulus, triaxiality, eps_threshold,
                        bonora_dD_deps, is_critical)
 from .scheme import _critical
 from .kinematics import hencky, stretch_from_log
-from .mixture import cons_to_prim, closure_density
+from .mixture import cons_to_prim, closure_density, PHI_TRACE
 
 
 def phi0_at(X, phi0, geom):
@@ -102,17 +107,18 @@ def source_step(U, phi0, geom, layout, opts):
     Gmix = np.zeros_like(J)
     for l in L.solids:
         m = mats[l]
+        live = P.phi[l] >= PHI_TRACE
         w = 1.0 - P.D[l]
-        Gt = solid_shear_modulus(closure_density(P.phi[l], P.rho_l[l], m), m)
-        Gmix = Gmix + P.phi[l] * w * Gt
+        Gt = solid_shear_modulus(P.rho_l[l], m)
+        Gmix = Gmix + np.where(live, P.phi[l] * w * Gt, 0.0)
         sy = np.where(~_critical(P.D[l], m, opts), pert * m["yield_stress"], 0.0)
-        Ymix = Ymix + P.phi[l] * w * sy
+        Ymix = Ymix + np.where(live, P.phi[l] * w * sy, 0.0)
     pos = Gmix > 0
     Jmax = np.where(pos, Ymix / (np.sqrt(6.0) * np.where(pos, Gmix, 1.0)),
                     0.0)
     yielding = J > Jmax
     scale = np.where(yielding, Jmax / np.where(yielding, J, 1.0), 1.0)
-    deps = np.where(yielding, np.sqrt(2.0 / 3.0) * (J - Jmax), 0.0)
+    deps = np.where(yielding & pos, np.sqrt(2.0 / 3.0) * (J - Jmax), 0.0)
     Vn = stretch_from_log(h * scale[None], Q)
     for q, (i, j) in enumerate(L.vcomps):
         U[L.vbar[q]] = Vn[i, j]

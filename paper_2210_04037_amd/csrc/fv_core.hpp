@@ -257,10 +257,18 @@ struct Mix {
 };
 
 // A material below this volume fraction is a trace: its phasic density (the
-// ratio of two trace quantities) is noise, so its closures are evaluated at
-// its reference density.
+// ratio of two trace quantities) is noise.  A trace takes the limit of its
+// closures as the phasic density vanishes: the Romenskii cold energy and
+// pressure, stiffness and shear modulus all go to zero there, so it carries
+// no reference terms and no shear stiffness and enters the mixture only
+// through its Grueneisen share.  The traces that matter sit in cells emptied
+// to near vacuum, far below rho0, where this limit is continuous with the
+// closures just above the threshold; evaluating them at rho0 instead would
+// switch on the full modulus G0 with whatever distortion the cell carries.
 constexpr double PHI_TRACE = 1.0e-6;
 
+// density for the closures that need one (the triaxiality's rho0/rho): the
+// reference density for a trace
 template <class C>
 FV_HD C closure_density(const MatP& m, C phi_l, C rho_l) {
   return phi_l < (C)PHI_TRACE ? cst<C>(m.rho0, m.f_rho0) : rho_l;
@@ -272,9 +280,8 @@ FV_HD void mix_terms(const Params& P, const C* phi, const C* rho_l, const C* D,
   mx.xi = 0;
 #pragma unroll
   for (int l = 0; l < NM; ++l) {
-    if (l < NS) {
-      mx.t[l] = solid_ref_terms<C>(P.mat[l], closure_density(P.mat[l], phi[l], rho_l[l]), J2,
-                                   D[l < NS ? l : 0]);
+    if (l < NS && phi[l] >= (C)PHI_TRACE) {
+      mx.t[l] = solid_ref_terms<C>(P.mat[l], rho_l[l], J2, D[l < NS ? l : 0]);
     } else {
       mx.t[l].rho_eref = 0; mx.t[l].pref = 0; mx.t[l].rho_dpref = 0; mx.t[l].G = 0;
     }

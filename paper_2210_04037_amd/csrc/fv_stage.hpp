@@ -903,20 +903,26 @@ struct Stage {
 #pragma unroll
     for (int k = 0; k < DIM; ++k) X[k] = U[L::XC + k];
     const double pert = phi0_gather(I, X);
-    // radial return of dev H to the perturbed mixture yield surface
+    // radial return of dev H to the perturbed mixture yield surface; trace
+    // solids have no stiffness and take no part; with no mixture modulus the
+    // distortion carries no stress and is dropped, with no plastic work
     double Ymix = 0, Gm = 0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const MatP& m = P.mat[s];
+      if (!(phi[s] >= PHI_TRACE)) continue;
       const double w = 1.0 - D[s];
-      Gm += phi[s] * w * shear_modulus_undamaged<double>(m, closure_density(m, phi[s], rho_l[s]));
+      Gm += phi[s] * w * shear_modulus_undamaged<double>(m, rho_l[s]);
       const double sy = D[s] < crit_level(m) ? pert * m.yield : 0.0;
       Ymix += phi[s] * w * sy;
     }
     const double Jmax = Gm > 0.0 ? Ymix / (sqrt(6.0) * Gm) : 0.0;
     const double J = DIM == 3 ? sqrt(he[0] * he[0] + he[1] * he[1] + he[2] * he[2]) : sqrt(J2);
     double scale = 1.0, deps = 0.0;
-    if (J > Jmax) { scale = Jmax / J; deps = sqrt(2.0 / 3.0) * (J - Jmax); }
+    if (J > Jmax) {
+      scale = Jmax / J;
+      if (Gm > 0.0) deps = sqrt(2.0 / 3.0) * (J - Jmax);
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll

@@ -12,7 +12,15 @@ from oracle.layout import Layout
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-9
+# Through critical damage and at a front that keeps entering void, the run
+# takes discontinuous decisions: the critical band, and the trace threshold
+# of the mixture (a volume fraction crossing 1e-6 switches a material's
+# reference terms on or off).  At the disk's expanding edge cells cross the
+# threshold every step with the steel near its reference density, where the
+# switch moves the cell's pressure by the trace fraction times the cold
+# pressure; a rounding-order difference that flips it shows at ~1e-9 of a
+# field's largest value.  The bar is the one of the fracture strips.
+TOL = 1e-7
 
 
 def _gpu(case, **kw):
@@ -44,6 +52,8 @@ def test_disk_parity_with_seeding_fp64():
     L = Layout(2, case.mats)
     D = o.U[L.dmg[0]] / o.U[L.mass[0]]
     assert np.max(D) >= 0.3 * (1 - 1e-9)          # through critical damage
+    Dg = got[L.dmg[0]] / got[L.mass[0]]
+    assert np.array_equal(D >= 0.3 * (1 - 1e-9), Dg >= 0.3 * (1 - 1e-9))
     assert t == pytest.approx(o.t, rel=1e-12)
     err = _scaled_errors(got, o.U, L)
     print("[disk] worst field error", float(err.max()), flush=True)

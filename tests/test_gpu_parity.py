@@ -296,41 +296,29 @@ def test_unloaded_state_is_a_call_order_error():
     ref.close()
 
 
-FP32_END_TIME_SKIP = (
-    "FP32-bulk raises the non-physical flag before 40 us on these two runs "
-    "(34.3 us on the 1024^2 ring, 38.6 us on member 1, as measured before the "
-    "critical bands of the two forms were split): rarefied gas/void mixtures "
-    "behind the fragments, within 30 cells of a transmissive side, reach "
-    "negative energy and ~2e4 m/s; the scheme has no positivity-preserving "
-    "treatment of near-vacuum cells yet")
+END_TIME_RUNS = [("ring", None)] + [("member", k) for k in range(8)]
 
 
-MEMBER1_FP64_SKIP = (
-    "the FP64 form raises the non-physical flag at step 7602 (36.2 us of 40) "
-    "of ensemble member 1 since the critical band became the double-precision "
-    "reading: a gas cell of density 1e-5 kg/m^3 next to gas at 1e4 Pa is "
-    "driven to 1.3e5 m/s within one step and then to negative mass; the oracle, "
-    "stepped from the saved state, produces the same bad cell (the method's "
-    "near-vacuum limit: the HLLC intermediate states and the cell-centre CFL "
-    "bound do not limit the velocity a face imparts to a nearly empty cell)")
-
-
-@pytest.mark.parametrize("which,precision", [
-    ("ring", "fp64"),
-    pytest.param("member1", "fp64", marks=pytest.mark.skip(reason=MEMBER1_FP64_SKIP)),
-    pytest.param("ring", "fp32", marks=pytest.mark.skip(reason=FP32_END_TIME_SKIP)),
-    pytest.param("member1", "fp32", marks=pytest.mark.skip(reason=FP32_END_TIME_SKIP))])
-def test_runs_reach_their_end_time(which, precision):
-    """The 1024^2 ring (about 11300 steps) and ensemble member 1 (768^2,
-    about 27000 steps) go through fracture to their 40 us end time without
-    the non-physical flag.  Late in these runs the rarefied gas behind the
-    fragments holds stretches with principal ratios beyond 1e8, whose Hencky
-    strain the kernels form from det V (a strain formed from the entries of
-    V V^T alone gave NaN there)."""
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("which,member", END_TIME_RUNS,
+                         ids=["ring"] + [f"member{k}" for k in range(8)])
+def test_runs_reach_their_end_time(which, member, precision):
+    """The 1024^2 ring (about 11000 steps) and the eight ensemble members
+    of the fragment statistics (256^2 to 768^2, 3000 to 8500 steps) go
+    through fracture to their 40 us end time without the non-physical flag,
+    in both forms.  Late in these runs the rarefied gas behind the fragments
+    holds a trace of solid; its closures take their vanishing-density limit
+    (no reference terms, no shear stiffness), without which a cell crossing
+    the trace fraction with a distorted stretch gained a reference energy
+    larger than its whole energy and the near-vacuum gas was driven to
+    1e5 m/s and negative mass.  The stretches there reach principal ratios
+    beyond 1e8, whose Hencky strain the kernels form from det V (a strain
+    formed from the entries of V V^T alone gave NaN there)."""
+    import torch
     from paper_2210_04037_amd.solver import GpuSolver
-    case = F.make_case(2) if which == "ring" else F.make_case(4, member=1)
-    print(f"[end time] {which} {case.n[0]}^2 {precision} to {case.t_end:.1e} s",
-          flush=True)
+    case = F.make_case(2) if which == "ring" else F.make_case(4, member=member)
+    print(f"[end time] {which}{'' if member is None else member} "
+          f"{case.n[0]}^2 {precision} to {case.t_end:.1e} s", flush=True)
     g = GpuSolver(case, precision=precision, use_graph=True)
     g.step(0, t_end=[case.t_end])
     steps = 0
@@ -342,6 +330,7 @@ def test_runs_reach_their_end_time(which, precision):
     assert g.cfl_dt()[0] >= 0.0              # raises on the device flag
     lab, frags = g.fragments(0, 0.5)
     g.close()
+    torch.cuda.empty_cache()
     print(f"[end time] {which}: {steps} steps, {len(frags)} fragments", flush=True)
     assert len(frags) >= 10
 
