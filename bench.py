@@ -13,8 +13,9 @@ input, and the per-field L1 error of the FP32-bulk run against the FP64 run.
 The same JSON line carries the 2D expanding ring at 1024^2 (both forms, plus
 a window timed after fracture: the run restarts from its state at 20 us),
 the batched ensemble of 64 rings of uneven sizes in one context (FP32-bulk,
-beside a loop of the same members run one context at a time) and the 400^2
-expanding disk in void with Lagrangian seeding (both forms).
+beside a loop of the same members run one context at a time), the 400^2
+expanding disk in void with Lagrangian seeding and the 800^2 Al-on-CuBe
+spallation test with Johnson-Cook plasticity (both forms).
 
 Prints one JSON line: cell-updates/s, the roofline of the dominant (stage)
 kernel and the CPU oracle timed on a bounded window of the headline
@@ -352,6 +353,117 @@ def calibrate_copy(nbytes=1 << 30, reps=5):
 
 
 # ---------------------------------------------------------------------------
+# rocprofv3 summaries (written on the GPU host from the csv output of
+# --kernel-trace and --pmc runs of this script; read back by profile_value)
+# ---------------------------------------------------------------------------
+def _prof_rows(d, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)):
+        with open(f, newline="") as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _kernel_key(name):
+    """Short kernel name: the template-id between the namespace and the
+    argument list ('stage_kernel<2, 2, 1, float, float, 16, 14, 256>')."""
+    n = name.split("(")[0]
+    n = n.split("fvk::")[-1] if "fvk::" in n else n.replace("void ", "")
+    return n.strip()
+
+
+STAGE_PASSES = ("stage_kernel", "prim3_kernel", "face3_kernel", "finish3_kernel")
+
+
+def _median(v):
+    v = sorted(v)
+    n = len(v)
+    return 0.0 if n == 0 else (v[n // 2] if n % 2 else 0.5 * (v[n // 2 - 1] + v[n // 2]))
+
+
+def _counter_by_kernel(d, counter):
+    """{kernel key: [value per dispatch]} for one counter of a --pmc run."""
+    out = {}
+    for r in _prof_rows(d, "counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        out.setdefault(_kernel_key(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+    return out
+
+
+def profile_summary(args):
+    """Write a committed-style summary of one workload's rocprofv3 runs:
+    per-pass dispatch durations, HBM bytes per stage from FETCH_SIZE and
+    WRITE_SIZE scaled by a plain 1 GiB copy, and instruction counters."""
+    prec = args.precision
+    lines = [f"# stage passes, workload {args.workload} ({prec}): rocprofv3 summaries",
+             "# kernel_source_hash: hash of the stage-kernel sources the counters belong to",
+             f"kernel_source_hash: {kernel_source_hash()}"]
+    if args.prof_notes and os.path.exists(args.prof_notes):
+        lines.append("## commands (R = repository root; run from /tmp with TMPDIR=/tmp)")
+        lines += ["# " + l.rstrip() for l in open(args.prof_notes) if l.strip()]
+    if args.tile:
+        lines.append(f"tile_{prec}: " + "x".join(args.tile.split(",")[:2]))
+    # durations
+    dur = {}
+    for r in _prof_rows(args.prof_kt, "kernel_trace.csv"):
+        k = _kernel_key(r["Kernel_Name"])
+        dur.setdefault(k, []).append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    passes = [k for k in dur if k.startswith(STAGE_PASSES)]
+    lines.append("## kernel trace: dispatches and median duration (us)")
+    for k in sorted(dur, key=lambda k: -sum(dur[k])):
+        lines.append(f"#   {k:64s} calls {len(dur[k]):5d}  median_us {_median(dur[k]):10.1f}"
+                     f"  mean_us {sum(dur[k]) / len(dur[k]):10.1f}")
+    two_d = any(k.startswith("stage_kernel") for k in passes)
+    if two_d:
+        k = [k for k in passes if k.startswith("stage_kernel")][0]
+        v = dur[k]
+        by = [[v[i] for i in range(j, len(v), 3)] for j in range(3)]
+        lines.append("# stage kernel by stage (median us): " + "  ".join(
+            f"stage{j + 1} {_median(by[j]):.1f}" for j in range(3)))
+        stage_us = sum(v) / len(v)
+    else:
+        stage_us = sum(sum(dur[k]) / len(dur[k]) for k in passes)
+    lines.append(f"stage_mean_us_{prec}: {stage_us:.2f}")
+    # counter scaling from the copy
+    fc = max((max(v) for v in _counter_by_kernel(args.prof_copy_fetch, "FETCH_SIZE").values()),
+             default=0.0)
+    wc = max((max(v) for v in _counter_by_kernel(args.prof_copy_write, "WRITE_SIZE").values()),
+             default=0.0)
+    copy_kib = (1 << 30) / 1024.0
+    fscale = copy_kib / fc if fc > 0 else float("nan")
+    wscale = copy_kib / wc if wc > 0 else float("nan")
+    lines.append("## counter scaling from a plain 1 GiB device copy")
+    lines.append(f"# copy FETCH_SIZE KiB per copy {fc:.1f} -> fetch_scale {fscale:.4f}; "
+                 f"WRITE_SIZE KiB per copy {wc:.1f} -> write_scale {wscale:.4f}")
+    fetch = _counter_by_kernel(args.prof_fetch, "FETCH_SIZE")
+    write = _counter_by_kernel(args.prof_write, "WRITE_SIZE")
+    total = 0.0
+    lines.append("## HBM traffic per dispatch (median; KiB as counted, GB scaled)")
+    for k in sorted(passes):
+        f = _median(fetch.get(k, [])) * 1024 * fscale
+        w = _median(write.get(k, [])) * 1024 * wscale
+        total += f + w
+        lines.append(f"#   {k:64s} read_GB {f / 1e9:8.3f} write_GB {w / 1e9:8.3f}"
+                     f"  GB/s {(f + w) / (_median(dur[k]) * 1e-6) / 1e9:8.0f}")
+    lines.append(f"bytes_per_launch_{prec}: {total:.6e}")
+    if args.prof_sq:
+        lines.append("## instruction counters of the stage passes (median per dispatch)")
+        rows = _prof_rows(args.prof_sq, "counter_collection.csv")
+        names = sorted({r["Counter_Name"] for r in rows})
+        for c in names:
+            by = _counter_by_kernel(args.prof_sq, c)
+            tot = sum(_median(by.get(k, [])) for k in passes)
+            lines.append(f"{c}: {tot:.0f}")
+    with open(args.profile_summary, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+# ---------------------------------------------------------------------------
 # workloads
 # ---------------------------------------------------------------------------
 def make_workload(name, n=None, members=64):
@@ -365,6 +477,14 @@ def make_workload(name, n=None, members=64):
                 "(0.2 mm, 5%)")
         x0 = int(ne * (0.5 + 0.4292 * 0.7071)) - 48     # on the ring, 45 deg
         return cases, desc, ((x0, x0, 0), 96)
+    if name == "alcube":
+        ne = n or 800
+        cases = [F.al_cube_spall(2, n=ne)]
+        desc = (f"2D Al-on-CuBe spallation {ne}x{ne} over an 11 mm square "
+                "(the paper's quasi-1D test): Al-H32 flyer 2 mm at 400 m/s on "
+                "a CuBe target, Johnson-Cook hardening and rate terms, Bonora "
+                "damage in the copper, yield perturbation U(0.95, 1.05)")
+        return cases, desc, None
     if name == "disk":
         ne = n or 400
         cases = [F.expanding_disk(ne)]
@@ -489,7 +609,8 @@ def main():
                          "full size)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="impact3d",
-                    choices=["impact3d", "ring", "ensemble", "shell3d", "disk"],
+                    choices=["impact3d", "ring", "ensemble", "shell3d", "disk",
+                             "alcube"],
                     help="headline workload: impact3d, the 512^3 plate impact "
                          "(default, the largest single-GPU workload); ring: "
                          "the 1024^2 expanding ring; ensemble: 64 seeded "
@@ -517,9 +638,17 @@ def main():
                     help="steps per captured graph (0: eager launches)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device copy (counter scaling)")
+    ap.add_argument("--profile-summary", default=None, metavar="OUT",
+                    help="write the summary of rocprofv3 csv runs of this "
+                         "script (--prof-* directories) to OUT and exit")
+    for k in ("kt", "fetch", "write", "sq", "copy-fetch", "copy-write", "notes"):
+        ap.add_argument(f"--prof-{k}", default=None)
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.profile_summary:
+        profile_summary(args)
         return
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not "
@@ -564,9 +693,9 @@ def main():
     del cases
     if not args.only and head == "impact3d":
         others = {}
-        for name in ("ring", "ensemble", "disk"):
+        for name in ("ring", "ensemble", "disk", "alcube"):
             c2, d2, _ = make_workload(name, None, args.members)
-            m = measure(name, c2, d2, args, compare=name in ("ring", "disk")
+            m = measure(name, c2, d2, args, compare=name in ("ring", "disk", "alcube")
                         and not args.no_compare,
                         post_fracture=(args.post_fracture if name == "ring"
                                        and args.post_fracture > 0 else None))

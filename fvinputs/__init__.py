@@ -17,7 +17,8 @@ from .configs import (  # noqa: F401
     COPPER, GAS, Case, make_case, uniform_case, config_member_draws,
     vbar_components,
     prim_field_names, CONFIG_SEEDS, mass_edges, DEGENERATE_GRIDS,
-    degenerate_case, spall_strip, expanding_disk, STEEL_304L,
+    degenerate_case, spall_strip, expanding_disk, STEEL_304L, STEEL_304L_JC,
+    CUBE, AL_H32, al_cube_spall,
 )
 from .fields import (  # noqa: F401
     uniform_field, gaussian_field, lognormal_field, inclusion_field,

@@ -46,6 +46,63 @@ STEEL_304L = dict(
     eps_c=0.5, bonora_alpha=0.5, n_hard=0.313, p_gate=0.0,
 )
 
+# The two solids of the paper's spallation test (Section 4.1), all from its
+# Appendix A rows: the Romenskii table (rho0, K0, G0, alpha, beta, Gamma0),
+# the Johnson-Cook table (c1 the yield, c2 = jc_B, c3 = jc_C, n; neither
+# material has thermal terms there) and, for the damageable CuBe target, the
+# Bonora table (D_crit, eps_thresh, eps_crit, alpha).  The aluminium flyer
+# does not damage (the paper damages the copper only): its damage gate never
+# opens.  The CuBe gate is the plate impacts' -1.5 GPa.
+CUBE = dict(
+    kind="solid", rho0=8370.0, K0=131.3e9, alpha=1.0, G0=53.6e9, beta=3.0,
+    Gamma0=2.0, yield_stress=1.041e9, jc_B=0.0, jc_C=0.025, n_hard=0.31,
+    D_crit=0.85, D0=0.0, eps_th=0.08, eps_c=0.16, bonora_alpha=0.631,
+    p_gate=-1.5e9,
+)
+AL_H32 = dict(
+    kind="solid", rho0=2670.0, K0=72.2e9, alpha=0.627354, G0=25.8e9,
+    beta=2.28816, Gamma0=1.48389, yield_stress=0.275e9, jc_B=0.114e9,
+    jc_C=0.002, n_hard=0.42, D_crit=0.99, D0=0.0, eps_th=0.08, eps_c=0.16,
+    bonora_alpha=1.0, p_gate=-1.0e30,
+)
+# 304L with the full Johnson-Cook row of the paper's plasticity table
+# (hardening, rate and thermal softening), for the Johnson-Cook variant of
+# the expanding disk.
+STEEL_304L_JC = dict(STEEL_304L, jc_B=0.685e9, jc_C=0.097, jc_m=2.044,
+                     T_melt=1689.0, C_V=468.6)
+
+
+def al_cube_spall(dim=1, n=None, flyer=2.0e-3, v=400.0, a=0.05, t_end=5.0e-6,
+                  seed=None, ny=None):
+    """The paper's spallation test (Section 4.1): an Al-H32 flyer strikes a
+    CuBe target on [0, 11] mm (the paper's domain, CFL 0.4, 5 us).  The
+    initial-condition figure is not available: the flyer here is the first
+    `flyer` metres, moving at `v` m/s, the rest of the domain is the target
+    at rest, both at zero pressure, with free x-ends.  The CuBe yield is
+    perturbed by a field uniform in [1 - a, 1 + a] per cell (the paper's
+    perturbation study).  dim 2 gives the paper's quasi-one-dimensional
+    square (n x n cells unless ny is given, transmissive in y)."""
+    nx = n or (110 if dim == 1 else 800)
+    nyy = 1 if dim == 1 else (ny or nx)
+    lo = (0.0, 0.0, 0.0)
+    hi = (0.011, 0.011 if dim == 2 else 1.0, 1.0)
+    grid = (nx, nyy, 1)
+    mats = [dict(CUBE), dict(AL_H32)]
+    dx = (hi[0] - lo[0]) / nx
+    xl = lo[0] + np.arange(nx) * dx
+    # exact target fraction of each cell (the interface is a plane x = flyer)
+    frac_x = np.clip((xl + dx - flyer) / dx, 0.0, 1.0)
+    shp = (1, nyy, nx)
+    frac = np.broadcast_to(frac_x, shp).copy()
+    mc, ma = frac * mats[0]["rho0"], (1.0 - frac) * mats[1]["rho0"]
+    u = [ma * v / (mc + ma)] + [np.zeros(shp)] * (dim - 1)
+    prim = _assemble(dim, mats, frac, u, 0.0, grid, lo, hi)
+    sd = CONFIG_SEEDS[1] + 300 + dim if seed is None else seed
+    phi0 = uniform_field(shp, a, sd)
+    bc = (("free", "free"), ("transmissive",) * 2, ("transmissive",) * 2)
+    return Case(f"alcube{dim}d", dim, grid, lo, hi, bc, mats, prim, phi0, t_end,
+                cfl=0.4)
+
 
 def vbar_components(dim):
     """Stored (i, j) components of the unimodular stretch, row-major:
@@ -328,17 +385,19 @@ def make_case(config, n=None, member=None, t_end=None):
     raise ValueError(f"unknown workload {config}")
 
 
-def expanding_disk(n=400, t_end=200.0e-6, corr_len=1.0e-3, seed=221004043):
+def expanding_disk(n=400, t_end=200.0e-6, corr_len=1.0e-3, seed=221004043,
+                   mat=None):
     """The expanding disk of the paper's validation section: a 304L disk of
     radius 10 cm centred in a [-13, 13]^2 cm domain of void, radial velocity
     u = 2000 r (1/s), Gaussian phi0 (mean 1, std 0.1, rectified), CFL 0.4,
     200 us, transmissive sides, Lagrangian seeding into cells of void
     fraction above 0.99.  The paper leaves the correlation length of phi0
-    open: 1 mm here (1.5 cells at 400^2).  Void cells hold the solid at the
+    open: 1 mm here (1.5 cells at 400^2).  `mat` replaces the constant-yield
+    304L (STEEL_304L_JC: its full Johnson-Cook row).  Void cells hold the solid at the
     volume-fraction floor, at its reference density and zero pressure."""
     lo, hi = (-0.13, -0.13, 0.0), (0.13, 0.13, 1.0)
     grid = (n, n, 1)
-    mats = [dict(STEEL_304L)]
+    mats = [dict(STEEL_304L if mat is None else mat)]
 
     def ind(X, Y, Z):
         return X * X + Y * Y <= 0.1 * 0.1

@@ -89,14 +89,23 @@ typedef struct {
 /* Material constants, SI units (Sections 2.2, 2.3; Appendix A tables).
  * Solid: rho0, K0 (bulk modulus), alpha (Romenskii exponent), G0, beta
  * (shear-modulus exponent, G = G0 (rho/rho0)^(beta+1)), Gamma0, yield (the
- * constant yield stress the perturbation field scales), D_crit, D0, eps_th,
- * eps_c, bonora_alpha, n_hard (hardening exponent of the threshold strain),
- * p_gate (damage accrues only for p < p_gate).  Gas: Gamma0 = gamma - 1; the
- * other fields are ignored. */
+ * yield stress c1 the perturbation field scales), D_crit, D0, eps_th,
+ * eps_c, bonora_alpha, n_hard (hardening exponent, of the threshold strain
+ * and of the Johnson-Cook law), p_gate (damage accrues only for
+ * p < p_gate).  Johnson-Cook plasticity (the paper's plasticity table:
+ * c2 = jc_B, c3 = jc_C, m = jc_m, T_melt, C_V): the yield is
+ *   (yield + jc_B eps_p^n_hard) (1 + jc_C ln max(rate / 1 s^-1, 1))
+ *   (1 - T*^jc_m),   T* = clamp((T - 300 K) / (T_melt - 300 K), 0, 1),
+ * with the rate the step's plastic increment over dt and T from the thermal
+ * energy C_V (T - 300 K eta^Gamma0) of Section 2.2.  jc_B = jc_C = 0 and
+ * T_melt = 0 give the constant yield; T_melt > 300 K needs jc_m > 0 and
+ * C_V > 0, and negative jc_B or jc_C are rejected (FV_EINVAL).  Gas:
+ * Gamma0 = gamma - 1; the other fields are ignored. */
 typedef struct {
   int32_t kind;
   double rho0, K0, alpha, G0, beta, Gamma0;
   double yield, D_crit, D0, eps_th, eps_c, bonora_alpha, n_hard, p_gate;
+  double jc_B, jc_C, jc_m, T_melt, C_V;
 } fv_material;
 
 /* Run options.  cfl: Courant number of the CFL reduction.  phi_floor:

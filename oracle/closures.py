@@ -141,3 +141,59 @@ def bonora_closed_form(eps, R, m):
     s = 1.0 - R * np.log(eps / m["eps_th"]) / np.log(m["eps_c"] / m["eps_th"])
     s = np.maximum(s, 0.0)
     return Dc - ((Dc - D0) ** (1.0 / a) * s) ** a
+
+
+# ---------------------------------------------------------------------------
+# Johnson-Cook plasticity (named by the paper for its solids, with the
+# constants of its Appendix A plasticity table: c1, c2, c3, n, m, T_melt,
+# C_V; the law itself is not printed).  The form is the one of Johnson and
+# Cook (1983):
+#   sigma_Y = (c1 + c2 eps_p^n) (1 + c3 ln max(rate / RATE_REF, 1))
+#             (1 - T*^m),   T* = clamp((T - T_REF) / (T_melt - T_REF), 0, 1).
+# Readings: the reference strain rate is 1/s and rates below it leave the
+# yield at its quasi-static value; the reference temperature of the law and
+# of the thermal energy below is room temperature, 300 K; a material without
+# a melting temperature (the paper's "-" entries) has no thermal softening.
+# With c2 = c3 = 0 and no melting temperature the law is the constant yield
+# c1 of the workloads that do not use it.
+# ---------------------------------------------------------------------------
+T_REF = 300.0
+RATE_REF = 1.0
+
+
+def jc_active(m):
+    """Whether a material's yield depends on strain, rate or temperature."""
+    return (m["kind"] == "solid"
+            and (m.get("jc_B", 0.0) != 0.0 or m.get("jc_C", 0.0) != 0.0
+                 or m.get("T_melt", 0.0) > 0.0))
+
+
+def jc_flow_stress(eps, rate, T, m):
+    """Johnson-Cook flow stress at plastic strain eps, plastic strain rate
+    `rate` [1/s] and temperature T [K] (see above)."""
+    A, B, C = m["yield_stress"], m.get("jc_B", 0.0), m.get("jc_C", 0.0)
+    hard = A + B * np.power(np.maximum(eps, 0.0), m["n_hard"])
+    rfac = 1.0 + C * np.log(np.maximum(rate / RATE_REF, 1.0))
+    Tm = m.get("T_melt", 0.0)
+    if Tm > 0.0:
+        Ts = np.clip((T - T_REF) / (Tm - T_REF), 0.0, 1.0)
+        tfac = 1.0 - Ts ** m["jc_m"]
+    else:
+        tfac = 1.0
+    return hard * rfac * tfac
+
+
+def temperature(p, pref, rho, m):
+    """Phase temperature from the thermal energy of Section 2.2,
+    E_t = C_V (T - T0 theta_D(rho)), with the Romenskii Debye temperature
+    theta_D = eta^Gamma0 and T0 = T_REF: under the Mie-Grueneisen form the
+    thermal energy per unit mass is e_t = (p - p_ref) / (rho Gamma0), taken
+    non-negative (the cold curve is the zero-temperature bound), so
+    T = e_t / C_V + T_REF eta^Gamma0.  A material without C_V has no
+    temperature (returned as T_REF)."""
+    cv = m.get("C_V", 0.0)
+    if cv <= 0.0:
+        return np.full_like(np.asarray(p, dtype=float), T_REF)
+    g = m["Gamma0"]
+    et = np.maximum(p - pref, 0.0) / (rho * g)
+    return et / cv + T_REF * (rho / m["rho0"]) ** g

@@ -62,7 +62,7 @@ class Solver:
         self._accumulate(b1, dt / 6.0)
         self._accumulate(b2, dt / 6.0)
         self._accumulate(b3, dt * (2.0 / 3.0))
-        self.U = source_step(U3, self.phi0, g, L, o)
+        self.U = source_step(U3, self.phi0, g, L, o, dt)
         if getattr(o, "seed_nu", 0.0) > 0.0:
             self.U = seed_void(self.U, g, L, o.seed_nu)
         self.t += dt

@@ -18,7 +18,9 @@ the paper is silent on the splitting).  Readings:
     shear stiffness and take no part in the sums; a cell whose mixture
     modulus is zero carries no elastic distortion (Vbar is reset to the
     identity, the stress does not depend on it) and does no plastic work
-    (Delta eps_p = 0, so no damage either).
+    (Delta eps_p = 0, so no damage either).  A trace solid in a cell that
+    another solid stiffens takes no share of the increment either: its
+    plastic strain and damage stand.
   * damage (Section 2.2 Bonora rate with the Pirondi-Bonora gate, Section 3.1
     RK4): gate frozen at the start of the step (p < p_gate, eps_p^n above the
     triaxiality-dependent threshold, Delta eps_p > 0, D < D_crit); triaxiality
@@ -32,10 +34,11 @@ the paper is silent on the splitting).  Readings:
 import numpy as np
 
 from .closures import (solid_shear_modulus, triaxiality, eps_threshold,
-                       bonora_dD_deps, is_critical)
+                       bonora_dD_deps, is_critical, jc_active, jc_flow_stress,
+                       temperature)
 from .scheme import _critical
 from .kinematics import hencky, stretch_from_log
-from .mixture import cons_to_prim, closure_density, PHI_TRACE
+from .mixture import cons_to_prim, closure_density, PHI_TRACE, material_terms
 
 
 def phi0_at(X, phi0, geom):
@@ -95,15 +98,37 @@ def damage_rk4(D, eps0, deps, R, m):
     return cl(D + h / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4))
 
 
-def source_step(U, phi0, geom, layout, opts):
-    """Plastic return, damage and Vbar re-symmetrisation on U (in place)."""
+# bisection steps of the Johnson-Cook return: each halves the bracket
+# [0, sqrt(2/3) J], so 200 of them reach the double-precision root
+JC_BISECTIONS = 200
+
+
+def _mixture_yield(P, mats, solids, pert, opts, dgam, dt, temps):
+    """Y_mix(Delta eps_p) = sum over live solids of
+    phi_l (1 - D_l) phi0 sigma_Y,l(eps_l + Delta, Delta/dt, T_l), zero for a
+    critical solid (the yield vanishes once D >= D_crit)."""
+    Y = np.zeros_like(dgam)
+    for l in solids:
+        m = mats[l]
+        live = P.phi[l] >= PHI_TRACE
+        ok = live & ~_critical(P.D[l], m, opts)
+        rate = dgam / dt if dt is not None and dt > 0 else np.zeros_like(dgam)
+        sy = jc_flow_stress(P.eps[l] + dgam, rate, temps[l], m)
+        Y = Y + np.where(ok, P.phi[l] * (1.0 - P.D[l]) * pert * sy, 0.0)
+    return Y
+
+
+def source_step(U, phi0, geom, layout, opts, dt=None):
+    """Plastic return, damage and Vbar re-symmetrisation on U (in place).
+    dt, the step's time step, sets the plastic strain rate of a
+    rate-dependent yield (Johnson-Cook c3); without it the rate term is
+    off."""
     L = layout
     mats = L.mats
     P = cons_to_prim(U, L)
     pert = phi0_at(P.X, phi0, geom)
     _, h, Q = hencky(P.V)
     J = np.sqrt(np.sum(h * h, axis=0))
-    Ymix = np.zeros_like(J)
     Gmix = np.zeros_like(J)
     for l in L.solids:
         m = mats[l]
@@ -111,14 +136,37 @@ def source_step(U, phi0, geom, layout, opts):
         w = 1.0 - P.D[l]
         Gt = solid_shear_modulus(P.rho_l[l], m)
         Gmix = Gmix + np.where(live, P.phi[l] * w * Gt, 0.0)
-        sy = np.where(~_critical(P.D[l], m, opts), pert * m["yield_stress"], 0.0)
-        Ymix = Ymix + np.where(live, P.phi[l] * w * sy, 0.0)
     pos = Gmix > 0
-    Jmax = np.where(pos, Ymix / (np.sqrt(6.0) * np.where(pos, Gmix, 1.0)),
-                    0.0)
-    yielding = J > Jmax
-    scale = np.where(yielding, Jmax / np.where(yielding, J, 1.0), 1.0)
-    deps = np.where(yielding & pos, np.sqrt(2.0 / 3.0) * (J - Jmax), 0.0)
+    # temperatures of the state entering the return, frozen over it
+    terms = material_terms(P.rho_l, P.D, P.J2, mats, P.phi)
+    temps = {l: temperature(P.p, terms[l][1], P.rho_l[l], mats[l])
+             for l in L.solids}
+    zero = np.zeros_like(J)
+    Y0 = _mixture_yield(P, mats, L.solids, pert, opts, zero, dt, temps)
+    yielding = pos & (np.sqrt(6.0) * Gmix * J > Y0)
+    dmax = np.sqrt(2.0 / 3.0) * J
+    if any(jc_active(mats[l]) for l in L.solids):
+        # yield rising with Delta (hardening, rate): the residual
+        # f(Delta) = sqrt6 G (J - sqrt(3/2) Delta) - Y_mix(Delta) falls from
+        # f(0) > 0 to f(sqrt(2/3) J) = -Y_mix <= 0; bisect for its root
+        lo = np.zeros_like(J)
+        hi = np.where(yielding, dmax, 0.0)
+        for _ in range(JC_BISECTIONS):
+            mid = 0.5 * (lo + hi)
+            f = (np.sqrt(6.0) * Gmix * (J - np.sqrt(1.5) * mid)
+                 - _mixture_yield(P, mats, L.solids, pert, opts, mid, dt, temps))
+            lo = np.where(f > 0.0, mid, lo)
+            hi = np.where(f > 0.0, hi, mid)
+        deps = np.where(yielding, 0.5 * (lo + hi), 0.0)
+        Jnew = J - np.sqrt(1.5) * deps
+    else:
+        Jmax = np.where(pos, Y0 / (np.sqrt(6.0) * np.where(pos, Gmix, 1.0)), 0.0)
+        deps = np.where(yielding, np.sqrt(2.0 / 3.0) * (J - Jmax), 0.0)
+        Jnew = Jmax
+    # no stiffness: the distortion is dropped (no plastic work)
+    yielding = yielding | (~pos & (J > 0.0))
+    Jnew = np.where(pos, Jnew, 0.0)
+    scale = np.where(yielding, Jnew / np.where(yielding, J, 1.0), 1.0)
     Vn = stretch_from_log(h * scale[None], Q)
     for q, (i, j) in enumerate(L.vcomps):
         U[L.vbar[q]] = Vn[i, j]
@@ -127,8 +175,11 @@ def source_step(U, phi0, geom, layout, opts):
         mass = U[L.mass[l]]
         eps_n = P.eps[l]
         D_n = P.D[l]
-        sig_eq = (1.0 - D_n) * pert * m["yield_stress"]
-        gate = (P.p < m["p_gate"]) & (deps > 0) & ~_critical(D_n, m, opts)
+        # a trace solid does no plastic work: its histories stand
+        dl = np.where(P.phi[l] >= PHI_TRACE, deps, 0.0)
+        rate = dl / dt if dt is not None and dt > 0 else np.zeros_like(dl)
+        sig_eq = (1.0 - D_n) * pert * jc_flow_stress(eps_n + dl, rate, temps[l], m)
+        gate = (P.p < m["p_gate"]) & (dl > 0) & ~_critical(D_n, m, opts)
         ok = sig_eq > 0
         R = triaxiality(P.p, np.where(ok, sig_eq, 1.0),
                         closure_density(P.phi[l], P.rho_l[l], m), m)
@@ -138,8 +189,8 @@ def source_step(U, phi0, geom, layout, opts):
         Dnew = D_n.copy()
         g1 = gate & ok
         if np.any(g1):
-            Dnew[g1] = damage_rk4(D_n[g1], eps_n[g1], deps[g1], R[g1], m)
+            Dnew[g1] = damage_rk4(D_n[g1], eps_n[g1], dl[g1], R[g1], m)
         Dnew[gate & ~ok] = m["D_crit"]
-        U[L.eps[l]] = mass * (eps_n + deps)
+        U[L.eps[l]] = mass * (eps_n + dl)
         U[L.dmg[l]] = mass * Dnew
     return U

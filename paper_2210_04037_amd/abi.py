@@ -34,7 +34,8 @@ class FvMaterial(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32)] + [
         (n, ctypes.c_double) for n in (
             "rho0", "K0", "alpha", "G0", "beta", "Gamma0", "yield_", "D_crit",
-            "D0", "eps_th", "eps_c", "bonora_alpha", "n_hard", "p_gate")]
+            "D0", "eps_th", "eps_c", "bonora_alpha", "n_hard", "p_gate",
+            "jc_B", "jc_C", "jc_m", "T_melt", "C_V")]
 
 
 class FvOptions(ctypes.Structure):
@@ -149,6 +150,8 @@ def material_array(mats):
                     "p_gate"):
             setattr(a, key, float(m[key]))
         a.yield_ = float(m["yield_stress"])
+        for key in ("jc_B", "jc_C", "jc_m", "T_melt", "C_V"):
+            setattr(a, key, float(m.get(key, 0.0)))
     return arr
 
 

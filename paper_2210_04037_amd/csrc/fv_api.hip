@@ -119,12 +119,14 @@ static int validate(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
       const fv_material& m = mats[l];
       if (!(m.rho0 > 0 && m.K0 > 0 && m.alpha > 0 && m.G0 >= 0 && m.Gamma0 > 0 &&
             m.D_crit > m.D0 && m.D_crit < 1 && m.eps_c > m.eps_th && m.eps_th > 0 &&
-            m.bonora_alpha > 0 && m.n_hard > 0 && m.yield >= 0)) {
+            m.bonora_alpha > 0 && m.n_hard > 0 && m.yield >= 0 && m.jc_B >= 0 &&
+            m.jc_C >= 0 && m.T_melt >= 0 &&
+            (m.T_melt == 0 || (m.T_melt > 300.0 && m.jc_m > 0 && m.C_V > 0)))) {
         msg = "invalid solid constants"; return FV_EINVAL;
       }
     } else if (!(mats[l].Gamma0 > 0)) { msg = "gas needs Gamma0 > 0"; return FV_EINVAL; }
   }
-  if (ns > 1) { msg = "at most one solid"; return FV_EINVAL; }
+  if (ns == 2 && grids[0].dim == 3) { msg = "two solids are compiled for 1D and 2D only"; return FV_EINVAL; }
   if (opt->precision != FV_FP64 && opt->precision != FV_FP32_BULK) { msg = "bad precision"; return FV_EINVAL; }
   if (!(opt->cfl > 0 && opt->cfl <= 1)) { msg = "cfl must be in (0, 1]"; return FV_EINVAL; }
   if (!(opt->phi_floor > 0 && opt->phi_floor < 0.5)) { msg = "phi_floor must be in (0, 0.5)"; return FV_EINVAL; }
@@ -224,6 +226,8 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
     q.Gamma0 = m.Gamma0; q.yield = m.yield; q.Dcrit = m.D_crit; q.D0 = m.D0;
     q.eps_th = m.eps_th; q.eps_c = m.eps_c; q.balpha = m.bonora_alpha;
     q.nhard = m.n_hard; q.pgate = m.p_gate;
+    q.jcB = m.jc_B; q.jcC = m.jc_C; q.jcm = m.jc_m; q.Tmelt = m.T_melt; q.CV = m.C_V;
+    q.jc = q.kind == 0 && (m.jc_B != 0.0 || m.jc_C != 0.0 || m.T_melt > 0.0);
     q.invGamma = 1.0 / m.Gamma0;
     auto small_int = [](double v) {
       const double r = std::round(v);

@@ -72,9 +72,10 @@ struct MatP {
   int kind;       // 0 solid (Romenskii), 1 ideal gas
   int alpha_i;    // alpha as a small integer, else 0
   int beta1_i;    // beta + 1 as a small integer, else 0
-  int pad_;
+  int jc;         // the yield depends on strain, rate or temperature
   double rho0, K0, alpha, G0, beta, Gamma0;
   double yield, Dcrit, D0, eps_th, eps_c, balpha, nhard, pgate;
+  double jcB, jcC, jcm, Tmelt, CV;   // Johnson-Cook c2, c3, m, T_melt, C_V
   // host-derived constants
   // Critical level of the Section 3.1 test D >= D_crit, which holds up to the
   // rounding of the advected ratio (phi rho D)/(phi rho) of a clamped cell:
@@ -576,6 +577,51 @@ template <class C> FV_HD C weno3_left(C qm, C q0, C q1, C eps) {
   const C a0 = (C)(1.0 / 3.0) / ((eps + b0) * (eps + b0));
   const C a1 = (C)(2.0 / 3.0) / ((eps + b1) * (eps + b1));
   return (a0 * p0 + a1 * p1) / (a0 + a1);
+}
+
+// ----------------------------------------------------------------------------
+// Johnson-Cook plasticity: the law of Johnson and Cook (1983) with the
+// constants of the paper's plasticity table (the paper names the law and
+// tabulates c1..C_V without printing it).  Reference rate 1/s (slower rates
+// keep the quasi-static yield) and reference temperature 300 K, of the law
+// and of the thermal energy C_V (T - T_ref theta_D(rho)) of Section 2.2.
+// ----------------------------------------------------------------------------
+constexpr double JC_T_REF = 300.0;
+constexpr double JC_RATE_REF = 1.0;
+
+// Phase temperature: thermal energy per unit mass (p - p_ref)/(rho Gamma0)
+// of the Mie-Grueneisen form, non-negative, over C_V, plus T_ref eta^Gamma0
+// (the Romenskii Debye temperature).
+FV_HD double jc_temperature(const MatP& m, double p, double pref, double rho) {
+  if (!(m.CV > 0.0)) return JC_T_REF;
+  const double et = (p - pref > 0.0 ? p - pref : 0.0) / (rho * m.Gamma0);
+  return et / m.CV + JC_T_REF * pow(rho / m.rho0, m.Gamma0);
+}
+
+// Flow stress at plastic strain eps_n + dg, rate dg/dt and temperature T;
+// *dY receives its derivative in dg (the rate term's where the rate
+// exceeds the reference, the hardening term's where the strain is positive).
+FV_HD double jc_yield(const MatP& m, double eps_n, double dg, double dt, double T, double* dY) {
+  const double x = eps_n + dg > 0.0 ? eps_n + dg : 0.0;
+  double hard = m.yield, dhard = 0.0;
+  if (m.jcB != 0.0) {
+    const double xn = pow(x, m.nhard);
+    hard += m.jcB * xn;
+    if (x > 0.0) dhard = m.jcB * m.nhard * xn / x;
+  }
+  double rf = 1.0, drf = 0.0;
+  if (m.jcC != 0.0 && dt > 0.0) {
+    const double r = dg / dt / JC_RATE_REF;
+    if (r > 1.0) { rf = 1.0 + m.jcC * log(r); drf = m.jcC / dg; }
+  }
+  double tf = 1.0;
+  if (m.Tmelt > 0.0) {
+    double ts = (T - JC_T_REF) / (m.Tmelt - JC_T_REF);
+    ts = ts < 0.0 ? 0.0 : (ts > 1.0 ? 1.0 : ts);
+    tf = 1.0 - pow(ts, m.jcm);
+  }
+  if (dY) *dY = (dhard * rf + hard * drf) * tf;
+  return hard * rf * tf;
 }
 
 // ----------------------------------------------------------------------------

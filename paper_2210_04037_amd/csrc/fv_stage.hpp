@@ -323,7 +323,7 @@ struct Stage {
   // ---------------------------------------------------------------- phase 2
   struct Side {
     C phi[NM], rho_l[NM], eps[NS > 0 ? NS : 1], D[NS > 0 ? NS : 1];
-    C u[3], p, H[3][3], V[3][3];
+    C u[3], p, H[3][3];
     C rho, rhoE, c, G, t[3];
     C Uc[NC];
   };
@@ -340,7 +340,7 @@ struct Stage {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) { s.H[i][j] = 0; s.V[i][j] = 0; }
+      for (int j = 0; j < 3; ++j) s.H[i][j] = 0;
 #pragma unroll
     for (int q = 0; q < L::NH; ++q) {
       const int i = hk_i<DIM>(q), j = hk_j<DIM>(q);
@@ -349,8 +349,6 @@ struct Stage {
     }
     const C tr = (s.H[0][0] + s.H[1][1] + s.H[2][2]) / (C)3;
     s.H[0][0] -= tr; s.H[1][1] -= tr; s.H[2][2] -= tr;
-#pragma unroll
-    for (int q = 0; q < L::NV; ++q) s.V[vb_i<DIM>(q)][vb_j<DIM>(q)] = w[L::R_V + q];
     // face EOS: energy from the reconstructed pressure
     const C J2 = J2_of<DIM, C>(s.H);
     Mix<NM, NS, C> mx;
@@ -422,9 +420,11 @@ struct Stage {
     const Params& P = cx.P;
     const IDX NCELL = wstride;
     const C* W = sm;
+    // the rows the face states need; the stretch rows (the last NV) are
+    // reconstructed below, only on the side the face takes them from
     C wl[L::NR], wr[L::NR];
 #pragma unroll
-    for (int v = 0; v < L::NR; ++v) {
+    for (int v = 0; v < L::R_V; ++v) {
       const C qm = W[v * NCELL + cm], q0 = W[v * NCELL + c0];
       const C q1 = W[v * NCELL + c1], q2 = W[v * NCELL + c2];
       wl[v] = q0 + (C)0.5 * van_leer(q0 - qm, q1 - q0);
@@ -487,28 +487,17 @@ struct Stage {
     C ut[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) ut[k] = SL > (C)0 ? sL.u[k] : (SR < (C)0 ? sR.u[k] : ut2[k]);
-    // upwinded geometric face values
+    // upwinded geometric face values: the volume fractions here; the
+    // stretch and the coordinates once the side they come from is known
     const bool up = uf > tie, dn = uf < -tie;
     C phif[NM], Vf[L::NV], Xf[DIM];
 #pragma unroll
     for (int l = 0; l < NM; ++l)
       phif[l] = up ? sL.phi[l] : (dn ? sR.phi[l] : (C)0.5 * (sL.phi[l] + sR.phi[l]));
-#pragma unroll
-    for (int q = 0; q < L::NV; ++q) {
-      const C vl = wl[L::R_V + q], vr = wr[L::R_V + q];
-      Vf[q] = up ? vl : (dn ? vr : (C)0.5 * (vl + vr));
-    }
-    const C ext = (C)(I.dx[a] * I.n[a]);
-    const C weps = cst<C>(P.weno_eps, P.f_weno_eps) * ext * ext;
-    C XL[DIM], XR[DIM];
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      const C xm = W[(L::W_X + k) * NCELL + cm], x0 = W[(L::W_X + k) * NCELL + c0];
-      const C x1 = W[(L::W_X + k) * NCELL + c1], x2 = W[(L::W_X + k) * NCELL + c2];
-      XL[k] = weno3_left(xm, x0, x1, weps);
-      XR[k] = weno3_left(x2, x1, x0, weps);
-      Xf[k] = up ? XL[k] : (dn ? XR[k] : (C)0.5 * (XL[k] + XR[k]));
-    }
+    // side of the stretch and coordinate values: 0 left, 1 right, 2 the
+    // mean of both, 3 none (an opened or closed face, whose neighbours use
+    // their own centre values)
+    int pick = up ? 0 : (dn ? 1 : 2);
     // one-sided free-surface velocities
     const C usL = unL - sL.t[a] / (sL.rho * sL.c);
     const C usR = unR + sR.t[a] / (sR.rho * sR.c);
@@ -533,6 +522,7 @@ struct Stage {
         // opened faces store the shared volume-fraction flux in Q_PHI
 #pragma unroll
         for (int l = 0; l < NM; ++l) phif[l] = sL.phi[l] * oL + sR.phi[l] * oR;
+        pick = 3;
       }
     } else if ((lo_b && I.bc[a][0] == BC_FREE) || (hi_b && I.bc[a][1] == BC_FREE)) {
       const Side& sK = lo_b ? sR : sL;
@@ -547,16 +537,55 @@ struct Stage {
         for (int k = 0; k < 3; ++k) ut[k] = sK.u[k];
 #pragma unroll
         for (int l = 0; l < NM; ++l) phif[l] = sK.phi[l];
-#pragma unroll
-        for (int q = 0; q < L::NV; ++q) Vf[q] = lo_b ? wr[L::R_V + q] : wl[L::R_V + q];
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) Xf[k] = lo_b ? XR[k] : XL[k];
+        pick = lo_b ? 1 : 0;
       } else {
         os = 1;
 #pragma unroll
         for (int q = 0; q < NC; ++q) F[q] = 0;
 #pragma unroll
         for (int l = 0; l < NM; ++l) phif[l] = 0;
+        pick = 3;
+      }
+    }
+    // The left value of a stencil (qm, q0 | q1, q2) is q0 + vl(q0-qm, q1-q0)/2
+    // and the right one q1 - vl(q1-q0, q2-q1)/2; van Leer's mean is
+    // symmetric and odd, so the right value is the left formula on the
+    // mirrored stencil (q2, q1, q0), bit for bit, and one pass over the
+    // picked stencil serves either side.  The mean takes the right side in
+    // a second pass.
+    {
+      const bool rt = pick == 1;
+      const IDX ia = rt ? c2 : cm, ib = rt ? c1 : c0, ic = rt ? c0 : c1;
+      const C ext = (C)(I.dx[a] * I.n[a]);
+      const C weps = cst<C>(P.weno_eps, P.f_weno_eps) * ext * ext;
+#pragma unroll
+      for (int q = 0; q < L::NV; ++q) Vf[q] = 0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) Xf[k] = 0;
+      if (pick != 3) {
+#pragma unroll
+        for (int q = 0; q < L::NV; ++q) {
+          const C qa = W[(L::R_V + q) * NCELL + ia], qb = W[(L::R_V + q) * NCELL + ib];
+          const C qc = W[(L::R_V + q) * NCELL + ic];
+          Vf[q] = qb + (C)0.5 * van_leer(qb - qa, qc - qb);
+        }
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+          Xf[k] = weno3_left(W[(L::W_X + k) * NCELL + ia], W[(L::W_X + k) * NCELL + ib],
+                             W[(L::W_X + k) * NCELL + ic], weps);
+      }
+      if (pick == 2) {
+#pragma unroll
+        for (int q = 0; q < L::NV; ++q) {
+          const C q0 = W[(L::R_V + q) * NCELL + c0], q1 = W[(L::R_V + q) * NCELL + c1];
+          const C q2 = W[(L::R_V + q) * NCELL + c2];
+          Vf[q] = (C)0.5 * (Vf[q] + (q1 - (C)0.5 * van_leer(q1 - q0, q2 - q1)));
+        }
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+          Xf[k] = (C)0.5 * (Xf[k] + weno3_left(W[(L::W_X + k) * NCELL + c2],
+                                                W[(L::W_X + k) * NCELL + c1],
+                                                W[(L::W_X + k) * NCELL + c0], weps));
       }
     }
     // outward boundary flux accumulation, RK3 weights 1/6, 1/6, 2/3
@@ -852,7 +881,7 @@ struct Stage {
   }
 
   // Returns the cell's CFL sum  sum_a (|u_a| + c)/dx_a  after the source step.
-  FV_HD static double source_and_cfl(const Params& P, const Inst& I, double* U) {
+  FV_HD static double source_and_cfl(const Params& P, const Inst& I, double* U, double dt) {
     double phi[NM], mass[NM], rho_l[NM], eps[NS > 0 ? NS : 1], D[NS > 0 ? NS : 1];
     double rho = 0;
 #pragma unroll
@@ -875,86 +904,154 @@ struct Stage {
     double V[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
     for (int q = 0; q < L::NV; ++q) V[vb_i<DIM>(q)][vb_j<DIM>(q)] = U[L::VB + q];
-    double H[3][3];
-    // 3D: the eigen-decomposition of V V^T is kept, so that the return (a
-    // scaling of dev H) rebuilds the stretch from the same eigenvectors
-    double Qe[3][3], he[3];
-    if constexpr (DIM == 3) {
-      double B[3][3];
+    double H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double Dn[NS > 0 ? NS : 1];
+    // A cell whose solids are all traces has no shear stiffness: its
+    // distortion is dropped (the stretch becomes the identity, on which
+    // the stress does not depend) and it does no plastic work, so the
+    // histories stand.  The Hencky strain, the perturbation gather and
+    // the return are skipped there (most of a gas- or void-filled grid).
+    bool live = false;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) live = live || phi[s] >= PHI_TRACE;
+    if (live) {
+      // 3D: the eigen-decomposition of V V^T is kept, so that the return (a
+      // scaling of dev H) rebuilds the stretch from the same eigenvectors
+      double Qe[3][3], he[3];
+      if constexpr (DIM == 3) {
+        double B[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            B[i][j] = V[i][0] * V[j][0] + V[i][1] * V[j][1] + V[i][2] * V[j][2];
+        sym3_eig(B, Qe);
+        half_log_eigs3<double>(V, B, he);
+        const double mm = (he[0] + he[1] + he[2]) / 3.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) he[k] -= mm;
+        sym3_compose(Qe, he, H);
+      } else {
+        hencky<DIM, double>(V, H);
+      }
+      const double J2 = J2_of<DIM, double>(H);
+      Mix<NM, NS, double> mx;
+      mix_terms<NM, NS, double>(P, phi, rho_l, D, J2, mx);
+      const double p = mix_pressure<NM, NS, double>(P, phi, mx, rho_e);
+      double X[3] = {0, 0, 0};
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) X[k] = U[L::XC + k];
+      const double pert = phi0_gather(I, X);
+      // radial return of dev H to the perturbed mixture yield surface; trace
+      // solids have no stiffness and take no part; with no mixture modulus the
+      // distortion carries no stress and is dropped, with no plastic work
+      double Ymix = 0, Gm = 0;
+      bool jc = false;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const MatP& m = P.mat[s];
+        if (!(phi[s] >= PHI_TRACE)) continue;
+        const double w = 1.0 - D[s];
+        Gm += phi[s] * w * shear_modulus_undamaged<double>(m, rho_l[s]);
+        const double sy = D[s] < crit_level(m) ? pert * m.yield : 0.0;
+        Ymix += phi[s] * w * sy;
+        jc = jc || m.jc;
+      }
+      const double J = DIM == 3 ? sqrt(he[0] * he[0] + he[1] * he[1] + he[2] * he[2]) : sqrt(J2);
+      double scale = 1.0, deps = 0.0;
+      // phase temperatures of the entering state, frozen over the return
+      double Tl[NS > 0 ? NS : 1];
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        Tl[s] = jc ? jc_temperature(P.mat[s], p, mx.t[s].pref, rho_l[s]) : JC_T_REF;
+      if (!jc) {
+        const double Jmax = Gm > 0.0 ? Ymix / (sqrt(6.0) * Gm) : 0.0;
+        if (J > Jmax) {
+          scale = Jmax / J;
+          if (Gm > 0.0) deps = sqrt(2.0 / 3.0) * (J - Jmax);
+        }
+      } else if (Gm > 0.0) {
+        // Johnson-Cook: solve sqrt6 G (J - sqrt(3/2) d) = Y_mix(d), the yield
+        // at the end of the step (strain eps + d, rate d/dt).  The residual
+        // falls in d; at the constant-yield increment it is already <= 0, so
+        // the root lies in [0, that increment]: Newton steps kept inside
+        // the bracket, bisection where one would leave it.
+        auto ymix = [&](double dg, double* dY) {
+          double y = 0.0, dy = 0.0;
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            const MatP& m = P.mat[s];
+            if (!(phi[s] >= PHI_TRACE) || !(D[s] < crit_level(m))) continue;
+            double d1;
+            const double f = phi[s] * (1.0 - D[s]) * pert;
+            y += f * jc_yield(m, eps[s], dg, dt, Tl[s], &d1);
+            dy += f * d1;
+          }
+          *dY = dy;
+          return y;
+        };
+        double dY0;
+        const double Y0 = ymix(0.0, &dY0);
+        const double s6G = sqrt(6.0) * Gm;
+        if (s6G * J > Y0) {
+          double lo = 0.0, hi = sqrt(2.0 / 3.0) * (J - Y0 / s6G), x = hi;
+          for (int it = 0; it < 100; ++it) {
+            double dY;
+            const double f = s6G * (J - sqrt(1.5) * x) - ymix(x, &dY);
+            if (f > 0.0) lo = x; else hi = x;
+            double xn = x - f / (-3.0 * Gm - dY);
+            if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+            const bool done = fabs(xn - x) <= 1e-15 * x || hi - lo <= 1e-15 * hi;
+            x = xn;
+            if (done) break;
+          }
+          deps = x;
+          scale = (J - sqrt(1.5) * x) / J;
+        }
+      } else if (J > 0.0) {
+        scale = 0.0;
+      }
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
-          B[i][j] = V[i][0] * V[j][0] + V[i][1] * V[j][1] + V[i][2] * V[j][2];
-      sym3_eig(B, Qe);
-      half_log_eigs3<double>(V, B, he);
-      const double mm = (he[0] + he[1] + he[2]) / 3.0;
+        for (int j = 0; j < 3; ++j) H[i][j] *= scale;
+      double Vn[3][3];
+      if constexpr (DIM == 3) {
+        double e[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) he[k] -= mm;
-      sym3_compose(Qe, he, H);
-    } else {
-      hencky<DIM, double>(V, H);
-    }
-    const double J2 = J2_of<DIM, double>(H);
-    Mix<NM, NS, double> mx;
-    mix_terms<NM, NS, double>(P, phi, rho_l, D, J2, mx);
-    const double p = mix_pressure<NM, NS, double>(P, phi, mx, rho_e);
-    double X[3] = {0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) X[k] = U[L::XC + k];
-    const double pert = phi0_gather(I, X);
-    // radial return of dev H to the perturbed mixture yield surface; trace
-    // solids have no stiffness and take no part; with no mixture modulus the
-    // distortion carries no stress and is dropped, with no plastic work
-    double Ymix = 0, Gm = 0;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const MatP& m = P.mat[s];
-      if (!(phi[s] >= PHI_TRACE)) continue;
-      const double w = 1.0 - D[s];
-      Gm += phi[s] * w * shear_modulus_undamaged<double>(m, rho_l[s]);
-      const double sy = D[s] < crit_level(m) ? pert * m.yield : 0.0;
-      Ymix += phi[s] * w * sy;
-    }
-    const double Jmax = Gm > 0.0 ? Ymix / (sqrt(6.0) * Gm) : 0.0;
-    const double J = DIM == 3 ? sqrt(he[0] * he[0] + he[1] * he[1] + he[2] * he[2]) : sqrt(J2);
-    double scale = 1.0, deps = 0.0;
-    if (J > Jmax) {
-      scale = Jmax / J;
-      if (Gm > 0.0) deps = sqrt(2.0 / 3.0) * (J - Jmax);
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) H[i][j] *= scale;
-    double Vn[3][3];
-    if constexpr (DIM == 3) {
-      double e[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) e[k] = exp(scale * he[k]);
-      sym3_compose(Qe, e, Vn);
-    } else {
-      stretch_from_log<DIM, double>(H, Vn);
-    }
-#pragma unroll
-    for (int q = 0; q < L::NV; ++q) U[L::VB + q] = Vn[vb_i<DIM>(q)][vb_j<DIM>(q)];
-    double Dn[NS > 0 ? NS : 1];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const MatP& m = P.mat[s];
-      const double seq = (1.0 - D[s]) * pert * m.yield;
-      bool gate = (p < m.pgate) && (deps > 0.0) && (D[s] < crit_level(m));
-      const bool ok = seq > 0.0;
-      const double R = ok ? triaxiality(m, p, seq, closure_density(m, phi[s], rho_l[s])) : 1.0;
-      if (gate) {
-        const double thr = eps_threshold(m, R);
-        gate = (eps[s] > thr) || !ok;
+        for (int k = 0; k < 3; ++k) e[k] = exp(scale * he[k]);
+        sym3_compose(Qe, e, Vn);
+      } else {
+        stretch_from_log<DIM, double>(H, Vn);
       }
-      Dn[s] = D[s];
-      if (gate) Dn[s] = ok ? damage_rk4(m, D[s], eps[s], deps, R) : m.Dcrit;
-      const double ms = U[L::MASS + s];
-      U[L::HIST + 2 * s] = ms * (eps[s] + deps);
-      U[L::HIST + 2 * s + 1] = ms * Dn[s];
+#pragma unroll
+      for (int q = 0; q < L::NV; ++q) U[L::VB + q] = Vn[vb_i<DIM>(q)][vb_j<DIM>(q)];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const MatP& m = P.mat[s];
+        // a trace solid does no plastic work: its histories stand
+        const double dl = phi[s] >= PHI_TRACE ? deps : 0.0;
+        const double seq = (1.0 - D[s]) * pert *
+                         (jc ? jc_yield(m, eps[s], dl, dt, Tl[s], nullptr) : m.yield);
+        bool gate = (p < m.pgate) && (dl > 0.0) && (D[s] < crit_level(m));
+        const bool ok = seq > 0.0;
+        const double R = ok ? triaxiality(m, p, seq, closure_density(m, phi[s], rho_l[s])) : 1.0;
+        if (gate) {
+          const double thr = eps_threshold(m, R);
+          gate = (eps[s] > thr) || !ok;
+        }
+        Dn[s] = D[s];
+        if (gate) Dn[s] = ok ? damage_rk4(m, D[s], eps[s], dl, R) : m.Dcrit;
+        const double ms = U[L::MASS + s];
+        U[L::HIST + 2 * s] = ms * (eps[s] + dl);
+        U[L::HIST + 2 * s + 1] = ms * Dn[s];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < L::NV; ++q)
+        U[L::VB + q] = vb_i<DIM>(q) == vb_j<DIM>(q) ? 1.0 : 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) Dn[s] = D[s];
     }
     // CFL sum on the new state, in the policy precision C
     C phic[NM], rlc[NM], Dc[NS > 0 ? NS : 1];
@@ -1073,7 +1170,7 @@ struct Stage {
 #pragma unroll
     for (int l = 0; l < NM; ++l) Un[L::PHI + l] = m_clamp(Un[L::PHI + l], cx.P.phi_floor, 1.0);
     double cfl = 0;
-    if (cx.stage == 3) cfl = source_and_cfl(cx.P, I, Un);
+    if (cx.stage == 3) cfl = source_and_cfl(cx.P, I, Un, (double)cx.dt);
     double rho = 0;
     bool nan = false;
 #pragma unroll

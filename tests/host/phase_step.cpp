@@ -39,6 +39,8 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
     q.Gamma0 = m.Gamma0; q.yield = m.yield; q.Dcrit = m.D_crit; q.D0 = m.D0;
     q.eps_th = m.eps_th; q.eps_c = m.eps_c; q.balpha = m.bonora_alpha;
     q.nhard = m.n_hard; q.pgate = m.p_gate;
+    q.jcB = m.jc_B; q.jcC = m.jc_C; q.jcm = m.jc_m; q.Tmelt = m.T_melt; q.CV = m.C_V;
+    q.jc = q.kind == 0 && (m.jc_B != 0.0 || m.jc_C != 0.0 || m.T_melt > 0.0);
     q.invGamma = 1.0 / m.Gamma0;
     auto small_int = [](double v) {
       const double r = std::round(v);
@@ -351,14 +353,20 @@ int main(int argc, char** argv) {
   std::fclose(f);
   int ns = 0;
   for (int l = 0; ok && l < nm; ++l) ns += m[l].kind == FV_MAT_SOLID;
-  if (!ok || ns != 1) {
+  if (!ok || ns < 1 || ns > 2 || (ns == 2 && (nm != 2 || g.dim == 3))) {
     std::fprintf(stderr, "phase_step: bad input\n");
     return 2;
   }
   Run r;
   const double* P = prim.data();
   const double* Z = phi0.data();
-  if (g.dim == 1 && nm == 1) {
+  if (ns == 2 && g.dim == 1) {
+    setup<1, 2, 2>(r, &g, m, &o, P, Z);
+    step_tiles<1, 2, 2, 16, 1>(r, nsteps);
+  } else if (ns == 2) {
+    setup<2, 2, 2>(r, &g, m, &o, P, Z);
+    step_tiles<2, 2, 2, 8, 4>(r, nsteps);
+  } else if (g.dim == 1 && nm == 1) {
     setup<1, 1, 1>(r, &g, m, &o, P, Z);
     step_tiles<1, 1, 1, 16, 1>(r, nsteps);
   } else if (g.dim == 1) {

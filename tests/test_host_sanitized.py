@@ -93,7 +93,8 @@ def _assert_matches_oracle(case, steps, t, flag, U, L):
     ("spall1d", 12), ("ring2d", 4), ("ring2d_wide", 3), ("ring2d_spare", 3),
     ("ring2d_spare14", 3),
     ("shell3d", 2),
-    ("impact3d", 2), ("disk2d", 40)])
+    ("impact3d", 2), ("disk2d", 40), ("alcube1d", 120), ("alcube2d", 30),
+    ("disk2d_jc", 30)])
 def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
     tile_x = 0
     if which == "spall1d":
@@ -113,6 +114,14 @@ def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
         case = F.make_case(3, n=10)
     elif which == "disk2d":
         case = F.expanding_disk(20)            # void around the disk: seeding
+    elif which == "alcube1d":
+        # two solids, Johnson-Cook hardening and rate terms (both), damage
+        case = F.al_cube_spall(1, n=40, v=550.0)
+    elif which == "alcube2d":
+        case = F.al_cube_spall(2, n=20, ny=5, v=550.0)
+    elif which == "disk2d_jc":
+        # Johnson-Cook with thermal softening (304L row)
+        case = F.expanding_disk(20, mat=F.STEEL_304L_JC)
     else:
         case = F.make_case(5, n=9)
     t, flag, U, L = _run(exe, tmp_path, case, steps, tile_x)

@@ -15,7 +15,8 @@ to zero there).  What that fixes independently of the oracle's own code:
     its distortion;
   * the source step leaves such a cell with no elastic distortion and does
     no plastic work there, so neither the plastic strain nor the damage of
-    the trace moves.
+    the trace moves; a trace solid in a cell that another solid stiffens
+    takes no share of that solid's plastic increment.
 """
 import numpy as np
 import pytest
@@ -135,3 +136,27 @@ def test_source_step_returns_a_live_solid_to_its_yield_surface():
     assert np.sqrt(P1.J2[0, 0, 0]) == pytest.approx(Jmax, rel=1e-9)
     assert P1.eps[0][0, 0, 0] - P0.eps[0][0, 0, 0] == pytest.approx(
         np.sqrt(2.0 / 3.0) * (J0 - Jmax), rel=1e-9)
+
+
+def test_trace_solid_takes_no_share_of_another_solids_plastic_work():
+    """Two solids (the spallation test's aluminium and copper): the copper
+    at a trace fraction in a yielding aluminium cell keeps its plastic
+    strain and damage while the aluminium's grow by the return's increment."""
+    al, cu = dict(F.AL_H32, jc_B=0.0, jc_C=0.0), dict(F.CUBE, jc_C=0.0, p_gate=1e30)
+    h = np.array([2e-2, -1.2e-2, -0.8e-2])
+    case = F.uniform_case(1, (2, 1, 1), [cu, al], [1e-8, 1.0 - 1e-8],
+                          [cu["rho0"], al["rho0"]], [0.0], -2.0e9,
+                          bc="periodic", vbar=np.diag(np.exp(h)).tolist())
+    L = Layout(1, case.mats)
+    case.prim[L.eps[0]] = 0.5
+    case.prim[L.dmg[0]] = 0.3
+    opts = Options(cfl=case.cfl)
+    U = prim_to_cons(case.prim.copy(), L, opts)
+    geom = Geometry(case.dim, case.n, case.lo, case.hi, case.bc)
+    P0 = cons_to_prim(U, L)
+    P1 = cons_to_prim(source_step(U.copy(), case.phi0, geom, L, opts), L)
+    J0 = np.sqrt(np.sum(h * h))
+    d_al = np.sqrt(2.0 / 3.0) * (J0 - al["yield_stress"] / (np.sqrt(6.0) * al["G0"]))
+    assert P1.eps[1][0, 0, 0] - P0.eps[1][0, 0, 0] == pytest.approx(d_al, rel=1e-6)
+    assert P1.eps[0][0, 0, 0] == pytest.approx(P0.eps[0][0, 0, 0], rel=1e-14)
+    assert P1.D[0][0, 0, 0] == pytest.approx(P0.D[0][0, 0, 0], rel=1e-14)
