@@ -13,9 +13,8 @@ input, and the per-field L1 error of the FP32-bulk run against the FP64 run.
 The same JSON line carries the 2D expanding ring at 1024^2 (both forms, plus
 a window timed after fracture: the run restarts from its state at 20 us),
 the batched ensemble of 64 rings of uneven sizes in one context (FP32-bulk,
-beside a loop of the same members run one context at a time), the 400^2
-expanding disk in void with Lagrangian seeding and the 800^2 Al-on-CuBe
-spallation test with Johnson-Cook plasticity (both forms).
+beside a loop of the same members run one context at a time) and the 400^2
+expanding disk in void with Lagrangian seeding (both forms).
 
 Prints one JSON line: cell-updates/s, the roofline of the dominant (stage)
 kernel and the CPU oracle timed on a bounded window of the headline
@@ -477,14 +476,6 @@ def make_workload(name, n=None, members=64):
                 "(0.2 mm, 5%)")
         x0 = int(ne * (0.5 + 0.4292 * 0.7071)) - 48     # on the ring, 45 deg
         return cases, desc, ((x0, x0, 0), 96)
-    if name == "alcube":
-        ne = n or 800
-        cases = [F.al_cube_spall(2, n=ne)]
-        desc = (f"2D Al-on-CuBe spallation {ne}x{ne} over an 11 mm square "
-                "(the paper's quasi-1D test): Al-H32 flyer 2 mm at 400 m/s on "
-                "a CuBe target, Johnson-Cook hardening and rate terms, Bonora "
-                "damage in the copper, yield perturbation U(0.95, 1.05)")
-        return cases, desc, None
     if name == "disk":
         ne = n or 400
         cases = [F.expanding_disk(ne)]
@@ -609,8 +600,7 @@ def main():
                          "full size)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="impact3d",
-                    choices=["impact3d", "ring", "ensemble", "shell3d", "disk",
-                             "alcube"],
+                    choices=["impact3d", "ring", "ensemble", "shell3d", "disk"],
                     help="headline workload: impact3d, the 512^3 plate impact "
                          "(default, the largest single-GPU workload); ring: "
                          "the 1024^2 expanding ring; ensemble: 64 seeded "
@@ -693,9 +683,9 @@ def main():
     del cases
     if not args.only and head == "impact3d":
         others = {}
-        for name in ("ring", "ensemble", "disk", "alcube"):
+        for name in ("ring", "ensemble", "disk"):
             c2, d2, _ = make_workload(name, None, args.members)
-            m = measure(name, c2, d2, args, compare=name in ("ring", "disk", "alcube")
+            m = measure(name, c2, d2, args, compare=name in ("ring", "disk")
                         and not args.no_compare,
                         post_fracture=(args.post_fracture if name == "ring"
                                        and args.post_fracture > 0 else None))

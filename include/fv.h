@@ -28,7 +28,8 @@
  *   Vbar components: 1D (11, 22, 33); 2D (11, 12, 21, 22, 33); 3D all nine,
  *   row-major.  The void fraction is 1 - sum phi_l (not stored).  Element
  *   type: double for FV_FP64, float for FV_FP32_BULK.  Materials: solids
- *   first (at most one), then at most one gas; N <= 2.
+ *   first, then at most one gas; N <= 2.  Two solids (and no gas) are
+ *   compiled for 1D only; fv_init refuses them in 2D and 3D (FV_EINVAL).
  */
 #ifndef FV_H
 #define FV_H

@@ -126,7 +126,7 @@ static int validate(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
       }
     } else if (!(mats[l].Gamma0 > 0)) { msg = "gas needs Gamma0 > 0"; return FV_EINVAL; }
   }
-  if (ns == 2 && grids[0].dim == 3) { msg = "two solids are compiled for 1D and 2D only"; return FV_EINVAL; }
+  if (ns == 2 && grids[0].dim != 1) { msg = "two solids are compiled for 1D only"; return FV_EINVAL; }
   if (opt->precision != FV_FP64 && opt->precision != FV_FP32_BULK) { msg = "bad precision"; return FV_EINVAL; }
   if (!(opt->cfl > 0 && opt->cfl <= 1)) { msg = "cfl must be in (0, 1]"; return FV_EINVAL; }
   if (!(opt->phi_floor > 0 && opt->phi_floor < 0.5)) { msg = "phi_floor must be in (0, 0.5)"; return FV_EINVAL; }

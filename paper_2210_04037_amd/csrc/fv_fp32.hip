@@ -27,15 +27,10 @@ bool select_ops_fp32(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t
     FV_VAR(1, 2, 1, float, float, 64, 1)
     return true;
   }
-  // two solids (Section 4.1: an aluminium flyer on a copper target)
+  // two solids (Section 4.1: an aluminium flyer on a copper target), 1D
   if (dim == 1 && nm == 2 && ns == 2) {
     FV_VAR(1, 2, 2, float, float, 256, 1)
     FV_VAR(1, 2, 2, float, float, 128, 1)
-    return true;
-  }
-  if (dim == 2 && nm == 2 && ns == 2) {
-    FV_VARN(2, 2, 2, float, float, 16, 14, 256)
-    FV_VAR(2, 2, 2, float, float, 32, 8)
     return true;
   }
   if (dim == 2 && nm == 1 && ns == 1) {

@@ -363,6 +363,10 @@ int main(int argc, char** argv) {
   if (ns == 2 && g.dim == 1) {
     setup<1, 2, 2>(r, &g, m, &o, P, Z);
     step_tiles<1, 2, 2, 16, 1>(r, nsteps);
+  } else if (ns == 2 && tx == 16) {
+    // the FP64 default shape: 16 x 15 cells on 256 threads
+    setup<2, 2, 2>(r, &g, m, &o, P, Z);
+    step_tiles<2, 2, 2, 16, 15, 256>(r, nsteps);
   } else if (ns == 2) {
     setup<2, 2, 2>(r, &g, m, &o, P, Z);
     step_tiles<2, 2, 2, 8, 4>(r, nsteps);
