@@ -143,6 +143,8 @@ class Case:
     meta: dict = field(default_factory=dict)
     # void-fraction threshold of the Lagrangian seeding (0: off)
     seed_nu: float = 0.0
+    # THINC steepness of the volume-fraction reconstruction (0: MUSCL)
+    thinc_beta: float = 0.0
 
     @property
     def dx(self):

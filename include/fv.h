@@ -124,7 +124,12 @@ typedef struct {
  * void fraction 1 - sum phi_l exceeds seed_nu (and has a void-fraction
  * gradient) takes Lagrangian coordinates extrapolated from the point 1.5
  * cells towards the material, X(p) - (p - c); 0 turns it off (the default
- * of the workloads surrounded by gas), values in [0, 1). */
+ * of the workloads surrounded by gas), values in [0, 1).  thinc_beta: THINC
+ * interface sharpening of the volume fractions (Xiao, Honma and Kono 2005;
+ * the paper uses it for its ring): in cells where a volume fraction is
+ * monotone between its neighbours, its face values come from the tanh
+ * profile of steepness thinc_beta that keeps the cell average; 0 (the
+ * default) keeps MUSCL, values in [0, 10]. */
 typedef struct {
   int32_t precision;
   double cfl;
@@ -134,6 +139,7 @@ typedef struct {
   int32_t tile[3];
   int32_t use_graph;
   double seed_nu;
+  double thinc_beta;
 } fv_options;
 
 /* Number of state fields S for a dimension and material list (the first

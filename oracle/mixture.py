@@ -36,8 +36,10 @@ C_MIN2 = 1.0e-6       # floor on c^2 [m^2/s^2]
 
 class Options:
     def __init__(self, phi_floor=1.0e-8, cfl=0.6, weno_eps=1.0e-6,
-                 crit_rel_tol=None, seed_nu=0.0):
+                 crit_rel_tol=None, seed_nu=0.0, thinc_beta=0.0):
         self.phi_floor = phi_floor
+        # THINC steepness for the volume fractions (0: MUSCL)
+        self.thinc_beta = thinc_beta
         self.cfl = cfl
         self.weno_eps = weno_eps
         # void-fraction threshold of the Lagrangian seeding (0: off)

@@ -21,7 +21,8 @@ class Solver:
     def __init__(self, case, opts=None):
         self.case = case
         self.opts = opts or Options(cfl=case.cfl,
-                                    seed_nu=getattr(case, "seed_nu", 0.0))
+                                    seed_nu=getattr(case, "seed_nu", 0.0),
+                                    thinc_beta=getattr(case, "thinc_beta", 0.0))
         self.layout = Layout(case.dim, case.mats)
         self.geom = Geometry(case.dim, case.n, case.lo, case.hi, case.bc)
         self.U = prim_to_cons(case.prim.copy(), self.layout, self.opts)

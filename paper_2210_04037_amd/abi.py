@@ -43,7 +43,7 @@ class FvOptions(ctypes.Structure):
                 ("phi_floor", ctypes.c_double), ("weno_eps", ctypes.c_double),
                 ("phi_fp64_cut", ctypes.c_double),
                 ("tile", ctypes.c_int32 * 3), ("use_graph", ctypes.c_int32),
-                ("seed_nu", ctypes.c_double)]
+                ("seed_nu", ctypes.c_double), ("thinc_beta", ctypes.c_double)]
 
 
 class FvFragment(ctypes.Structure):
@@ -156,7 +156,8 @@ def material_array(mats):
 
 
 def options_struct(precision="fp64", cfl=0.6, phi_floor=1e-8, weno_eps=1e-6,
-                   phi_fp64_cut=1e-6, tile=None, use_graph=False, seed_nu=0.0):
+                   phi_fp64_cut=1e-6, tile=None, use_graph=False, seed_nu=0.0,
+                   thinc_beta=0.0):
     o = FvOptions()
     o.precision = PRECISIONS[precision]
     o.cfl = cfl
@@ -169,6 +170,7 @@ def options_struct(precision="fp64", cfl=0.6, phi_floor=1e-8, weno_eps=1e-6,
             o.tile[k] = int(v)
     o.use_graph = 1 if use_graph else 0
     o.seed_nu = float(seed_nu)
+    o.thinc_beta = float(thinc_beta)
     return o
 
 

@@ -132,6 +132,7 @@ static int validate(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
   if (!(opt->phi_floor > 0 && opt->phi_floor < 0.5)) { msg = "phi_floor must be in (0, 0.5)"; return FV_EINVAL; }
   if (!(opt->weno_eps > 0)) { msg = "weno_eps must be > 0"; return FV_EINVAL; }
   if (!(opt->seed_nu >= 0 && opt->seed_nu < 1)) { msg = "seed_nu must be in [0, 1)"; return FV_EINVAL; }
+  if (!(opt->thinc_beta >= 0 && opt->thinc_beta <= 10)) { msg = "thinc_beta must be in [0, 10]"; return FV_EINVAL; }
   if (opt->tile[2] < FV_SCHED_BY_INSTANCE || opt->tile[2] > FV_SCHED_INTERLEAVED) {
     msg = "tile[2] must be a block schedule (0, 1 or 2)"; return FV_EINVAL;
   }
@@ -245,6 +246,7 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
   P.c_min2 = 1.0e-6;
   P.phi_fp64_cut = opt->phi_fp64_cut;
   P.seed_nu = opt->seed_nu;
+  P.thinc_beta = opt->thinc_beta;
   set_float_constants(P);
 }
 

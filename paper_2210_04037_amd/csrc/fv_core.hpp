@@ -100,7 +100,11 @@ struct Params {
   double c_min2;
   double phi_fp64_cut;
   double seed_nu;      // void fraction above which X is reseeded (0: off)
+  // THINC sharpening of the volume fractions: steepness (0: MUSCL), with
+  // tanh(beta) and 1/cosh(beta) formed on the host
+  double thinc_beta, thinc_tb, thinc_sech;
   float f_weno_eps, f_c_min2, f_phi_fp64_cut, f_pad;
+  float f_thinc_beta, f_thinc_tb, f_thinc_sech, f_pad2;
 };
 
 // Host: the derived constants of a solid, from its own fields.
@@ -122,6 +126,11 @@ inline void set_float_constants(Params& P) {
   P.f_weno_eps = (float)P.weno_eps;
   P.f_c_min2 = (float)P.c_min2;
   P.f_phi_fp64_cut = (float)P.phi_fp64_cut;
+  P.thinc_tb = P.thinc_beta > 0.0 ? tanh(P.thinc_beta) : 0.0;
+  P.thinc_sech = P.thinc_beta > 0.0 ? 1.0 / cosh(P.thinc_beta) : 0.0;
+  P.f_thinc_beta = (float)P.thinc_beta;
+  P.f_thinc_tb = (float)P.thinc_tb;
+  P.f_thinc_sech = (float)P.thinc_sech;
 }
 
 // A parameter in the closure precision C: the double itself, or its float
@@ -566,6 +575,32 @@ FV_HD void stretch_from_log(const C H[3][3], C V[3][3]) {
 template <class C> FV_HD C van_leer(C dm, C dp) {
   const C pr = dm * dp;
   return pr > (C)0 ? (C)2 * pr / (dm + dp) : (C)0;
+}
+
+// THINC (Xiao, Honma and Kono 2005): in a cell whose value q0 lies strictly
+// between its neighbours qm and q1, the profile q_min + (dq/2)(1 + theta
+// tanh(beta (x - x_c))) over the unit cell with the cell average q0.  With
+// C = (q0 - q_min)/dq, B = exp(theta beta (2C - 1)) and
+// A = (B sech(beta) - 1)/tanh(beta), the lower-face value is
+// q_min + (dq/2)(1 + theta A) and the upper-face value
+// q_min + (dq/2)(1 + theta (tanh(beta) + A)/(1 + A tanh(beta))).  Returns
+// false where the profile is not used (not monotone, or C within 1e-6 of
+// 0 or 1).
+constexpr double THINC_EPS = 1.0e-6;
+
+template <class C>
+FV_HD bool thinc_cell(C qm, C q0, C q1, C beta, C tb, C sech, C* lower, C* upper) {
+  if (!((q1 - q0) * (q0 - qm) > (C)0)) return false;
+  const C qmin = m_min(qm, q1);
+  const C dq = m_abs(q1 - qm);
+  const C cn = (q0 - qmin) / dq;
+  if (!(cn > (C)THINC_EPS && cn < (C)1 - (C)THINC_EPS)) return false;
+  const C th = q1 >= qm ? (C)1 : (C)-1;
+  const C B = m_exp(th * beta * ((C)2 * cn - (C)1));
+  const C A = (B * sech - (C)1) / tb;
+  if (lower) *lower = qmin + (C)0.5 * dq * ((C)1 + th * A);
+  if (upper) *upper = qmin + (C)0.5 * dq * ((C)1 + th * (tb + A) / ((C)1 + A * tb));
+  return true;
 }
 
 // face value from the left (upwind cell q0; stencil qm, q0, q1)

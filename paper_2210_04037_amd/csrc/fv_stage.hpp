@@ -430,6 +430,20 @@ struct Stage {
       wl[v] = q0 + (C)0.5 * van_leer(q0 - qm, q1 - q0);
       wr[v] = q1 - (C)0.5 * van_leer(q1 - q0, q2 - q1);
     }
+    // THINC sharpening of the volume fractions (the first NM rows): the
+    // upper face of the cell below and the lower face of the cell above
+    if (P.thinc_beta > 0.0) {
+      const C beta = cst<C>(P.thinc_beta, P.f_thinc_beta);
+      const C tb = cst<C>(P.thinc_tb, P.f_thinc_tb), sh = cst<C>(P.thinc_sech, P.f_thinc_sech);
+#pragma unroll
+      for (int v = 0; v < NM; ++v) {
+        const C qm = W[v * NCELL + cm], q0 = W[v * NCELL + c0];
+        const C q1 = W[v * NCELL + c1], q2 = W[v * NCELL + c2];
+        C t;
+        if (thinc_cell<C>(qm, q0, q1, beta, tb, sh, nullptr, &t)) wl[v] = t;
+        if (thinc_cell<C>(q0, q1, q2, beta, tb, sh, &t, nullptr)) wr[v] = t;
+      }
+    }
     Side sL, sR;
     unpack_side(P, wl, a, sL);
     unpack_side(P, wr, a, sR);

@@ -38,7 +38,8 @@ class GpuSolver:
         self.mat_arr = abi.material_array(self.mats)
         self.opt = abi.options_struct(precision, cfl or c0.cfl, phi_floor,
                                       weno_eps, phi_fp64_cut, tile, use_graph,
-                                      getattr(c0, "seed_nu", 0.0))
+                                      getattr(c0, "seed_nu", 0.0),
+                                      getattr(c0, "thinc_beta", 0.0))
         self.S = lib.fv_state_fields(self.dim, len(self.mats), self.mat_arr)
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         self.states, self.phi0s = [], []

@@ -58,6 +58,7 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
   P.c_min2 = 1.0e-6;
   P.phi_fp64_cut = opt->phi_fp64_cut;
   P.seed_nu = opt->seed_nu;
+  P.thinc_beta = opt->thinc_beta;
   set_float_constants(P);
 }
 

@@ -48,7 +48,8 @@ def _write_input(path, case, steps, tile_x):
         f.write(np.int32(len(case.mats)).tobytes())
         f.write(bytes(abi.material_array(case.mats)))
         f.write(bytes(abi.options_struct("fp64", case.cfl,
-                                         seed_nu=getattr(case, "seed_nu", 0.0))))
+                                         seed_nu=getattr(case, "seed_nu", 0.0),
+                                         thinc_beta=getattr(case, "thinc_beta", 0.0))))
         f.write(np.int64(L.S).tobytes())
         f.write(np.int64(ncell).tobytes())
         f.write(np.int32(steps).tobytes())
@@ -94,7 +95,7 @@ def _assert_matches_oracle(case, steps, t, flag, U, L):
     ("ring2d_spare14", 3),
     ("shell3d", 2),
     ("impact3d", 2), ("disk2d", 40), ("alcube1d", 120), ("alcube2d", 30),
-    ("disk2d_jc", 30)])
+    ("disk2d_jc", 30), ("ring2d_thinc", 6), ("spall1d_thinc", 40)])
 def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
     tile_x = 0
     if which == "spall1d":
@@ -119,6 +120,13 @@ def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
         case = F.al_cube_spall(1, n=40, v=550.0)
     elif which == "alcube2d":
         case = F.al_cube_spall(2, n=20, ny=5, v=550.0)
+    elif which == "ring2d_thinc":
+        case = F.make_case(2, n=35)            # 16 x 14 tiles, THINC on
+        case.thinc_beta = 1.6
+        tile_x = 14
+    elif which == "spall1d_thinc":
+        case = F.make_case(1, n=45)
+        case.thinc_beta = 1.6
     elif which == "disk2d_jc":
         # Johnson-Cook with thermal softening (304L row)
         case = F.expanding_disk(20, mat=F.STEEL_304L_JC)
