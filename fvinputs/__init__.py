@@ -18,7 +18,7 @@ from .configs import (  # noqa: F401
     vbar_components,
     prim_field_names, CONFIG_SEEDS, mass_edges, DEGENERATE_GRIDS,
     degenerate_case, spall_strip, expanding_disk, STEEL_304L, STEEL_304L_JC,
-    CUBE, AL_H32, al_cube_spall,
+    CUBE, AL_H32, al_cube_spall, UNB, unb_ring, UNB_DRIVER,
 )
 from .fields import (  # noqa: F401
     uniform_field, gaussian_field, lognormal_field, inclusion_field,

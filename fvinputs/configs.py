@@ -71,6 +71,66 @@ AL_H32 = dict(
 STEEL_304L_JC = dict(STEEL_304L, jc_B=0.685e9, jc_C=0.097, jc_m=2.044,
                      T_melt=1689.0, C_V=468.6)
 
+# U-Nb of the paper's expanding ring (Section 4.3), from its Appendix A rows:
+# the Romenskii-Steinberg table (rho0, K0, G0, G_p, alpha and the
+# Burakovsky-Preston Gamma0 (in the role of Gamma_infinity), Gamma1, Gamma2,
+# gamma), the Johnson-Cook table (c1..C_V) and the simplified damage law of
+# the ring section (Ddot0 = 0.15, D_crit = 0.1).  beta, the Romenskii shear
+# exponent, is not used by the Steinberg modulus; the Bonora constants are
+# placeholders the simplified law does not read.
+UNB = dict(
+    kind="solid", rho0=17411.0, K0=111.27e9, alpha=1.105, G0=26.34e9,
+    beta=0.0, Gamma0=0.5, G_p=1.1226, Gamma1=1.056, Gamma2=1.068,
+    gamma_bp=3.843, yield_stress=0.780e9, jc_B=0.253e9, jc_C=0.012,
+    n_hard=0.22, jc_m=1.0, T_melt=1710.0, C_V=115.0, D_crit=0.1, D0=0.0,
+    Ddot0=0.15, eps_th=0.08, eps_c=0.16, bonora_alpha=1.0, p_gate=0.0,
+)
+
+
+# The driver profile of the paper's ring (Section 4.3): 210 m/s reached at
+# 17.5 us, 160 m/s at 35 us, arrested at 20 mm.
+UNB_RING_R = (17.185e-3, 17.945e-3)
+UNB_DRIVER = (UNB_RING_R[0], 210.0, 160.0, 17.5e-6, 35.0e-6, 20.0e-3)
+
+
+def unb_ring(dim=2, n=300, nz=8, t_end=50.0e-6, corr_len=0.2e-3, seed=None,
+             thinc_beta=0.0, mat=None, driver=UNB_DRIVER):
+    """The paper's expanding U-Nb ring (Section 4.3) without AMR: a ring of
+    radii 17.185-17.945 mm about the z axis in void, at rest and at zero
+    pressure, driven by the imposed-velocity driver (UNB_DRIVER), CFL 0.3,
+    50 us, Gaussian yield perturbation of mean 1 and std 0.167, transmissive
+    sides, Lagrangian seeding of void cells.  dim 3 is the paper's slab
+    [-30, 30]^2 x [-0.8, 0.8] mm with a square cross-section (|z| <= 0.38
+    mm) on n x n x nz cells; dim 2 the plane cross-section on n x n cells.
+    The paper gives no correlation length for the perturbation: 0.2 mm
+    here, as for the copper rings.  `mat` replaces U-Nb and `driver` the
+    driver (None: off)."""
+    r0, r1 = UNB_RING_R
+    lo = (-0.03, -0.03, -0.0008 if dim == 3 else 0.0)
+    hi = (0.03, 0.03, 0.0008 if dim == 3 else 1.0)
+    grid = (n, n, nz if dim == 3 else 1)
+    mats = [dict(UNB if mat is None else mat)]
+
+    def ind(X, Y, Z):
+        r = np.sqrt(X * X + Y * Y)
+        inside = (r >= r0) & (r <= r1)
+        return inside & (np.abs(Z) <= 0.38e-3) if dim == 3 else inside
+
+    def vel(X, Y, Z):
+        return [np.zeros_like(X) for _ in range(dim)]
+
+    frac, u = _subsample(dim, grid, lo, hi, ind, vel, mats[0]["rho0"], 1.0e-30)
+    prim = _assemble(dim, mats, frac, u, 0.0, grid, lo, hi)
+    d = (hi[0] - lo[0]) / n
+    shp = (grid[2], grid[1], grid[0])
+    sd = CONFIG_SEEDS[2] + 500 + dim if seed is None else seed
+    dxs = (((hi[2] - lo[2]) / grid[2]) if dim == 3 else 1.0, d, d)
+    phi0 = gaussian_field(shp, dxs, corr_len, 0.167, sd)
+    bc = (("transmissive",) * 2,) * 3
+    return Case(f"unbring{dim}d", dim, grid, lo, hi, bc, mats, prim, phi0,
+                t_end, cfl=0.3, seed_nu=0.99, thinc_beta=thinc_beta,
+                driver=driver)
+
 
 def al_cube_spall(dim=1, n=None, flyer=2.0e-3, v=400.0, a=0.05, t_end=5.0e-6,
                   seed=None, ny=None):
@@ -145,6 +205,8 @@ class Case:
     seed_nu: float = 0.0
     # THINC steepness of the volume-fraction reconstruction (0: MUSCL)
     thinc_beta: float = 0.0
+    # imposed-velocity driver (r_in, v0, v1, t0, t1, r_max) or None
+    driver: tuple = None
 
     @property
     def dx(self):

@@ -100,13 +100,21 @@ typedef struct {
  * with the rate the step's plastic increment over dt and T from the thermal
  * energy C_V (T - 300 K eta^Gamma0) of Section 2.2.  jc_B = jc_C = 0 and
  * T_melt = 0 give the constant yield; T_melt > 300 K needs jc_m > 0 and
- * C_V > 0, and negative jc_B or jc_C are rejected (FV_EINVAL).  Gas:
- * Gamma0 = gamma - 1; the other fields are ignored. */
+ * C_V > 0, and negative jc_B or jc_C are rejected (FV_EINVAL).  The U-Nb
+ * closures of the paper's ring (Section 2.3, Appendix A): G_p > 0 selects
+ * the Steinberg shear modulus G0 + G_p p_c eta^(-1/3) instead of
+ * G0 eta^(beta+1); Gamma1 or Gamma2 nonzero selects the Burakovsky-Preston
+ * Grueneisen function Gamma0 + Gamma1 eta^(-1/3) + Gamma2 eta^(-gamma_bp)
+ * (gamma_bp > 0) with its Debye temperature; Ddot0 > 0 selects the
+ * simplified damage law dD/deps_p = Ddot0 (1 - D), without gate, instead
+ * of the Bonora law (Section 4.3).  Zero keeps the Romenskii and Bonora
+ * forms.  Gas: Gamma0 = gamma - 1; the other fields are ignored. */
 typedef struct {
   int32_t kind;
   double rho0, K0, alpha, G0, beta, Gamma0;
   double yield, D_crit, D0, eps_th, eps_c, bonora_alpha, n_hard, p_gate;
   double jc_B, jc_C, jc_m, T_melt, C_V;
+  double G_p, Gamma1, Gamma2, gamma_bp, Ddot0;
 } fv_material;
 
 /* Run options.  cfl: Courant number of the CFL reduction.  phi_floor:
@@ -129,7 +137,14 @@ typedef struct {
  * the paper uses it for its ring): in cells where a volume fraction is
  * monotone between its neighbours, its face values come from the tanh
  * profile of steepness thinc_beta that keeps the cell average; 0 (the
- * default) keeps MUSCL, values in [0, 10]. */
+ * default) keeps MUSCL, values in [0, 10].  driver: the imposed-velocity
+ * driver of the paper's ring (Section 4.3), {r_in, v0, v1, t0, t1, r_max}
+ * in SI units: the driver surface starts at radius r_in about the z axis
+ * and moves with the radial speed v0 t/t0 (t < t0), linear from v0 to v1
+ * (t0 < t < t1), v1 afterwards, until it reaches r_max; after each step
+ * every cell of a live solid whose centre lies behind it takes at least
+ * that radial speed, the kinetic energy added going into the total energy.
+ * r_max = 0 (the default) turns it off; it needs dim >= 2. */
 typedef struct {
   int32_t precision;
   double cfl;
@@ -140,6 +155,7 @@ typedef struct {
   int32_t use_graph;
   double seed_nu;
   double thinc_beta;
+  double driver[6];
 } fv_options;
 
 /* Number of state fields S for a dimension and material list (the first

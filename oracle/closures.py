@@ -16,42 +16,75 @@ Readings of garbled or silent passages:
 import numpy as np
 
 
-def solid_cold(rho, m):
+def solid_cold(rho, m, second=False):
     """Romenskii cold compression (Section 2.3, Romenskii EOS):
     e_c = K0/(2 rho0 alpha^2) (eta^alpha - 1)^2, eta = rho/rho0.
-    Returns (rho*e_c, p_c = rho^2 de_c/drho, rho * dp_c/drho)."""
+    Returns (rho*e_c, p_c = rho^2 de_c/drho, rho * dp_c/drho), and with
+    `second` also rho^2 d2p_c/drho2; with p_c = (K0/alpha)(eta^(2a+1) -
+    eta^(a+1)) the derivatives are eta-derivatives:
+    rho p_c' = (K0/a)((2a+1) eta^(2a+1) - (a+1) eta^(a+1)),
+    rho^2 p_c'' = (K0/a)((2a+1) 2a eta^(2a+1) - (a+1) a eta^(a+1))."""
     K0, rho0, a = m["K0"], m["rho0"], m["alpha"]
     eta = rho / rho0
     ea = eta ** a
     rho_ec = rho * K0 / (2.0 * rho0 * a * a) * (ea - 1.0) ** 2
     pc = (K0 / a) * eta ** (a + 1.0) * (ea - 1.0)
     rho_dpc = (K0 / a) * eta ** (a + 1.0) * ((2.0 * a + 1.0) * ea - (a + 1.0))
-    return rho_ec, pc, rho_dpc
+    if not second:
+        return rho_ec, pc, rho_dpc
+    r2 = (K0 / a) * eta ** (a + 1.0) * ((2.0 * a + 1.0) * 2.0 * a * ea - (a + 1.0) * a)
+    return rho_ec, pc, rho_dpc, r2
+
+
+def steinberg(m):
+    """Whether a solid takes the Steinberg shear modulus (G_p given)."""
+    return m.get("G_p", 0.0) > 0.0
+
+
+def shear_terms(rho, m):
+    """Shear modulus G~ and its density derivatives rho G~' and rho^2 G~''.
+    Romenskii (Section 2.3): G~ = G0 eta^(beta+1), so rho G~' = (beta+1) G~
+    and rho^2 G~'' = (beta+1) beta G~.  Steinberg (Section 2.3, the U-Nb
+    ring): G~ = G0 + G_p p_c(rho) eta^(-1/3), whose derivatives follow from
+    those of the cold pressure:
+    rho G~' = G_p eta^(-1/3) (rho p_c' - p_c/3),
+    rho^2 G~'' = G_p eta^(-1/3) (rho^2 p_c'' - (2/3) rho p_c' + (4/9) p_c)."""
+    if not steinberg(m):
+        b1 = m["beta"] + 1.0
+        G = m["G0"] * (rho / m["rho0"]) ** b1
+        return G, b1 * G, b1 * (b1 - 1.0) * G
+    _, pc, rdpc, r2 = solid_cold(rho, m, second=True)
+    e3 = (rho / m["rho0"]) ** (-1.0 / 3.0)
+    Gp = m["G_p"]
+    G = m["G0"] + Gp * pc * e3
+    return (G, Gp * e3 * (rdpc - pc / 3.0),
+            Gp * e3 * (r2 - (2.0 / 3.0) * rdpc + (4.0 / 9.0) * pc))
 
 
 def solid_shear_modulus(rho, m):
-    """Romenskii shear modulus G = G0 eta^(beta+1) (Section 2.3)."""
-    return m["G0"] * (rho / m["rho0"]) ** (m["beta"] + 1.0)
+    """Shear modulus G~ (Romenskii or Steinberg form, Section 2.3)."""
+    return shear_terms(rho, m)[0]
 
 
 def ref_terms(rho, J2, D, m):
     """Reference (zero-temperature) terms of one material for the
     Mie-Grueneisen form: rho*e_ref, p_ref, rho*dp_ref/drho and the degraded
-    shear modulus G = (1-D) G~ (Sections 2.2, 2.3).
+    shear modulus G = (1-D) G~ (Sections 2.2, 2.3).  With the shear energy
+    e_s = G~ J^2 / rho of Section 2.2:
 
-    e_ref = (1-D)(e~_c + G~ J^2 / rho);  p_ref = (1-D)(p~_c + beta G~ J^2)
-    since rho^2 d(G~ J^2/rho)/drho = beta G~ J^2 for the Romenskii modulus.
-    Gas: all zero."""
+    e_ref = (1-D)(e~_c + G~ J^2 / rho),
+    p_ref = rho^2 de_ref/drho = (1-D)(p~_c + (rho G~' - G~) J^2),
+    rho dp_ref/drho = (1-D)(rho p~_c' + rho^2 G~'' J^2)
+    (for the Romenskii modulus rho G~' - G~ = beta G~).  Gas: all zero."""
     if m["kind"] != "solid":
         z = np.zeros_like(rho)
         return z, z, z, z
     rho_ec, pc, rho_dpc = solid_cold(rho, m)
-    Gt = solid_shear_modulus(rho, m)
-    b = m["beta"]
+    Gt, rG1, r2G2 = shear_terms(rho, m)
     w = 1.0 - D
     rho_eref = w * (rho_ec + Gt * J2)
-    pref = w * (pc + b * Gt * J2)
-    rho_dpref = w * (rho_dpc + b * (b + 1.0) * Gt * J2)
+    pref = w * (pc + (rG1 - Gt) * J2)
+    rho_dpref = w * (rho_dpc + r2G2 * J2)
     return rho_eref, pref, rho_dpref, w * Gt
 
 
@@ -78,8 +111,48 @@ def is_critical(D, m, rel_tol=CRIT_REL_TOL):
     return D >= m["D_crit"] * (1.0 - rel_tol)
 
 
-def gruneisen(m):
-    return m["Gamma0"]
+def burakovsky_preston(m):
+    """Whether a material takes the Burakovsky-Preston Grueneisen function
+    (Gamma1 or Gamma2 given)."""
+    return m.get("Gamma1", 0.0) != 0.0 or m.get("Gamma2", 0.0) != 0.0
+
+
+def gruneisen(m, rho=None):
+    """Grueneisen function.  Romenskii (and gases): the constant Gamma0.
+    Burakovsky-Preston (Section 2.3, with the Steinberg modulus):
+    Gamma = Gamma0 + Gamma1 eta^(-1/3) + Gamma2 eta^(-gamma), Gamma0 in the
+    role of Gamma_infinity."""
+    if rho is None or not burakovsky_preston(m):
+        return m["Gamma0"] if rho is None else np.full_like(np.asarray(rho, dtype=float), m["Gamma0"])
+    eta = rho / m["rho0"]
+    return (m["Gamma0"] + m["Gamma1"] * eta ** (-1.0 / 3.0)
+            + m["Gamma2"] * eta ** (-m["gamma_bp"]))
+
+
+def gruneisen_dlog(m, rho):
+    """rho Gamma'(rho) / Gamma: zero for a constant Gamma; for
+    Burakovsky-Preston (-Gamma1 eta^(-1/3)/3 - gamma Gamma2 eta^(-gamma))
+    / Gamma."""
+    if not burakovsky_preston(m):
+        return np.zeros_like(np.asarray(rho, dtype=float))
+    eta = rho / m["rho0"]
+    d = (-m["Gamma1"] * eta ** (-1.0 / 3.0) / 3.0
+         - m["gamma_bp"] * m["Gamma2"] * eta ** (-m["gamma_bp"]))
+    return d / gruneisen(m, rho)
+
+
+def debye_theta(m, rho):
+    """Non-dimensional Debye temperature theta_D (Section 2.3): eta^Gamma0
+    (Romenskii), or eta^Gamma0 exp[3 Gamma1 (1 - eta^(-1/3)) + (Gamma2 /
+    gamma)(1 - eta^(-gamma))] (Burakovsky-Preston), whose logarithmic
+    derivative is the Grueneisen function."""
+    eta = rho / m["rho0"]
+    th = eta ** m["Gamma0"]
+    if burakovsky_preston(m):
+        g = m["gamma_bp"]
+        th = th * np.exp(3.0 * m["Gamma1"] * (1.0 - eta ** (-1.0 / 3.0))
+                         + (m["Gamma2"] / g) * (1.0 - eta ** (-g)))
+    return th
 
 
 def poisson_ratio(m):
@@ -185,15 +258,14 @@ def jc_flow_stress(eps, rate, T, m):
 
 def temperature(p, pref, rho, m):
     """Phase temperature from the thermal energy of Section 2.2,
-    E_t = C_V (T - T0 theta_D(rho)), with the Romenskii Debye temperature
-    theta_D = eta^Gamma0 and T0 = T_REF: under the Mie-Grueneisen form the
-    thermal energy per unit mass is e_t = (p - p_ref) / (rho Gamma0), taken
-    non-negative (the cold curve is the zero-temperature bound), so
-    T = e_t / C_V + T_REF eta^Gamma0.  A material without C_V has no
+    E_t = C_V (T - T0 theta_D(rho)) with T0 = T_REF: under the Mie-Grueneisen
+    form the thermal energy per unit mass is e_t = (p - p_ref)/(rho Gamma),
+    taken non-negative (the cold curve is the zero-temperature bound), so
+    T = e_t / C_V + T_REF theta_D(rho).  A material without C_V has no
     temperature (returned as T_REF)."""
     cv = m.get("C_V", 0.0)
     if cv <= 0.0:
         return np.full_like(np.asarray(p, dtype=float), T_REF)
-    g = m["Gamma0"]
+    g = gruneisen(m, rho)
     et = np.maximum(p - pref, 0.0) / (rho * g)
-    return et / cv + T_REF * (rho / m["rho0"]) ** g
+    return et / cv + T_REF * debye_theta(m, rho)

@@ -20,7 +20,8 @@ paper's mechanical and thermal equilibrium assumption (Section 2.1):
     guard cells emptied to near vacuum).
   * sound speed: the frozen (Allaire) mixture bulk speed scaled by (1 - nu),
     plus the shear contribution, c^2 = c_b^2 + (4/3) G_mix / rho; each
-    phase's thermal term (Gamma+1)(p - p_ref) enters non-negative (a state
+    phase's thermal term (Gamma + 1 + rho Gamma'/Gamma)(p - p_ref) enters
+    non-negative (a state
     below the cold curve, as a gas fraction pulled into tension in a mixed
     cell, must not drive the wave-speed estimate to zero).
 Parity of the mixture rule itself is unpinned against the paper (it is not
@@ -28,7 +29,7 @@ printed there); the single-material limit is pinned.
 """
 import numpy as np
 
-from .closures import ref_terms, gruneisen
+from .closures import ref_terms, gruneisen, gruneisen_dlog
 from .kinematics import full_vbar, hencky, J2_of
 
 C_MIN2 = 1.0e-6       # floor on c^2 [m^2/s^2]
@@ -71,18 +72,44 @@ def closure_density(phi_l, rho_l, m):
     return np.where(phi_l < PHI_TRACE, m["rho0"], rho_l)
 
 
+class Terms(tuple):
+    """(rho e_ref, p_ref, rho dp_ref/drho, G) of one material, carrying its
+    Grueneisen share as attributes: inv_gamma = 1/Gamma(rho_l) and
+    g1 = Gamma + 1 + rho Gamma'/Gamma, the factor of the thermal pressure in
+    rho c^2 (d/drho of p = p_ref + rho Gamma (e - e_ref) along an isentrope,
+    with p_ref = rho^2 de_ref/drho, gives rho c^2 = rho p_ref' +
+    (Gamma + 1 + rho Gamma'/Gamma)(p - p_ref))."""
+    pass
+
+
 def material_terms(rho_l, D_l, J2, mats, phi=None):
-    """Per-material (rho e_ref, p_ref, rho dp_ref/drho, G) lists; zero for a
-    trace material (phi < PHI_TRACE)."""
+    """Per-material (rho e_ref, p_ref, rho dp_ref/drho, G) lists with their
+    Grueneisen shares (see Terms); zero reference terms for a trace material
+    (phi < PHI_TRACE), whose Grueneisen function is taken at the reference
+    density."""
     out = []
     for l, m in enumerate(mats):
         D = D_l[l] if l in D_l else np.zeros_like(J2)
         t = ref_terms(rho_l[l], J2, D, m)
+        rg = rho_l[l]
         if phi is not None:
             live = phi[l] >= PHI_TRACE
             t = tuple(np.where(live, v, 0.0) for v in t)
+            rg = np.where(live, rho_l[l], m["rho0"])
+        t = Terms(t)
+        g = gruneisen(m, rg)
+        t.inv_gamma = 1.0 / g
+        t.g1 = g + 1.0 + gruneisen_dlog(m, rg)
         out.append(t)
     return out
+
+
+def _inv_gamma(t, m):
+    return getattr(t, "inv_gamma", 1.0 / gruneisen(m))
+
+
+def _g1(t, m):
+    return getattr(t, "g1", gruneisen(m) + 1.0)
 
 
 def pressure_from_energy(phi, terms, rho_e, mats):
@@ -90,22 +117,22 @@ def pressure_from_energy(phi, terms, rho_e, mats):
     rho e - sum phi rho e_ref is taken non-negative (the cold curve is the
     zero-temperature bound; below it the state is numerical, as in cells
     emptied to near vacuum or a gas fraction pulled into tension)."""
-    xi = sum(phi[l] / gruneisen(m) for l, m in enumerate(mats))
+    xi = sum(phi[l] * _inv_gamma(terms[l], m) for l, m in enumerate(mats))
     th = rho_e.copy()
     cold = np.zeros_like(rho_e)
     for l, m in enumerate(mats):
         rho_eref, pref, _, _ = terms[l]
         th = th - phi[l] * rho_eref
-        cold = cold + phi[l] * pref / gruneisen(m)
+        cold = cold + phi[l] * pref * _inv_gamma(terms[l], m)
     return (np.maximum(th, 0.0) + cold) / xi
 
 
 def energy_from_pressure(phi, terms, p, mats):
-    xi = sum(phi[l] / gruneisen(m) for l, m in enumerate(mats))
+    xi = sum(phi[l] * _inv_gamma(terms[l], m) for l, m in enumerate(mats))
     rho_e = xi * p
     for l, m in enumerate(mats):
         rho_eref, pref, _, _ = terms[l]
-        rho_e = rho_e + phi[l] * rho_eref - phi[l] * pref / gruneisen(m)
+        rho_e = rho_e + phi[l] * rho_eref - phi[l] * pref * _inv_gamma(terms[l], m)
     return rho_e
 
 
@@ -117,16 +144,15 @@ def solid_fraction(phi):
 
 def sound_speed(phi, rho_l, terms, p, rho, mats):
     """Longitudinal mixture sound speed (see module docstring)."""
-    xi = sum(phi[l] / gruneisen(m) for l, m in enumerate(mats))
+    xi = sum(phi[l] * _inv_gamma(terms[l], m) for l, m in enumerate(mats))
     acc = np.zeros_like(p)
     Gmix = np.zeros_like(p)
     for l, m in enumerate(mats):
         _, pref, rho_dpref, G = terms[l]
-        g = gruneisen(m)
         # thermal part taken non-negative: a state below the cold curve is
         # not physical and must not pull the wave-speed estimate to zero
-        acc = acc + phi[l] / g * (rho_dpref
-                                  + (g + 1.0) * np.maximum(p - pref, 0.0))
+        acc = acc + phi[l] * _inv_gamma(terms[l], m) * (
+            rho_dpref + _g1(terms[l], m) * np.maximum(p - pref, 0.0))
         Gmix = Gmix + phi[l] * G
     # acc = sum phi_l xi_l rho_l c_l^2 (with rho_l c_l^2 = rho_l p_ref' +
     # (Gamma_l + 1)(p - p_ref,l)); bulk c^2 = (1-nu) acc / (xi rho)

@@ -12,6 +12,7 @@ from .layout import Layout
 from .mixture import Options, prim_to_cons, cons_to_prim
 from .scheme import Geometry, rhs, clamp_phi, dt_inverse
 from .source import source_step
+from .driver import apply_driver
 from .seeding import seed_void
 from .totals import interior_totals, boundary_totals
 from . import fragments as _frag
@@ -64,6 +65,8 @@ class Solver:
         self._accumulate(b2, dt / 6.0)
         self._accumulate(b3, dt * (2.0 / 3.0))
         self.U = source_step(U3, self.phi0, g, L, o, dt)
+        self.U = apply_driver(self.U, g, L, getattr(self.case, "driver", None),
+                              self.t + dt)
         if getattr(o, "seed_nu", 0.0) > 0.0:
             self.U = seed_void(self.U, g, L, o.seed_nu)
         self.t += dt

@@ -28,6 +28,9 @@ the paper is silent on the splitting).  Readings:
     (1-D) phi sigma_Y, frozen over the step; classical RK4 in eps_p from
     eps_p^n to eps_p^n + Delta eps_p (eps_p linear in time over the step),
     every stage argument and the result clamped to [0, D_crit].
+  * the simplified damage law of the U-Nb ring (Section 4.3),
+    dD/deps_p = Ddot0 (1 - D), has no gate: it runs with the same RK4 on
+    any plastic increment of a live solid below D_crit.
   * Vbar is rebuilt as the symmetric unimodular stretch Q exp(h) Q^T.
   * Total energy is unchanged, so the dissipated elastic energy becomes heat.
 """
@@ -80,11 +83,21 @@ def phi0_at(X, phi0, geom):
     return lerp(g[0], g[1], wts[2])
 
 
+def simplified_law(m):
+    """Whether a solid takes the simplified damage law of the U-Nb ring
+    (Section 4.3): dD/dt = Ddot0 (1 - D) deps_p/dt, Ddot0 given."""
+    return m.get("Ddot0", 0.0) > 0.0
+
+
 def damage_rk4(D, eps0, deps, R, m):
-    """Classical RK4 for dD/d(eps_p) from eps0 over deps, clamped."""
+    """Classical RK4 for dD/d(eps_p) from eps0 over deps, clamped: the
+    Bonora rate, or Ddot0 (1 - D) for the simplified law (zero once
+    critical, like the Bonora rate)."""
     Dc = m["D_crit"]
 
     def f(Dv, e):
+        if simplified_law(m):
+            return np.where(Dv >= Dc, 0.0, m["Ddot0"] * (1.0 - Dv))
         return bonora_dD_deps(Dv, e, R, m)
 
     def cl(v):
@@ -179,18 +192,24 @@ def source_step(U, phi0, geom, layout, opts, dt=None):
         dl = np.where(P.phi[l] >= PHI_TRACE, deps, 0.0)
         rate = dl / dt if dt is not None and dt > 0 else np.zeros_like(dl)
         sig_eq = (1.0 - D_n) * pert * jc_flow_stress(eps_n + dl, rate, temps[l], m)
-        gate = (P.p < m["p_gate"]) & (dl > 0) & ~_critical(D_n, m, opts)
+        # the simplified law has no gate: damage grows with any plastic
+        # increment of a live, not yet critical solid
+        open_p = True if simplified_law(m) else (P.p < m["p_gate"])
+        gate = open_p & (dl > 0) & ~_critical(D_n, m, opts)
         ok = sig_eq > 0
         R = triaxiality(P.p, np.where(ok, sig_eq, 1.0),
                         closure_density(P.phi[l], P.rho_l[l], m), m)
         R = np.where(ok, R, 1.0)
-        thr = eps_threshold(R, m)
-        gate = gate & ((eps_n > thr) | ~ok)
+        if not simplified_law(m):
+            thr = eps_threshold(R, m)
+            gate = gate & ((eps_n > thr) | ~ok)
         Dnew = D_n.copy()
-        g1 = gate & ok
+        # the simplified law needs no triaxiality: it integrates wherever
+        # the gate is open
+        g1 = gate & (ok | simplified_law(m))
         if np.any(g1):
             Dnew[g1] = damage_rk4(D_n[g1], eps_n[g1], dl[g1], R[g1], m)
-        Dnew[gate & ~ok] = m["D_crit"]
+        Dnew[gate & ~ok & (not simplified_law(m))] = m["D_crit"]
         U[L.eps[l]] = mass * (eps_n + dl)
         U[L.dmg[l]] = mass * Dnew
     return U

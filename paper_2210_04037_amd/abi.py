@@ -35,7 +35,8 @@ class FvMaterial(ctypes.Structure):
         (n, ctypes.c_double) for n in (
             "rho0", "K0", "alpha", "G0", "beta", "Gamma0", "yield_", "D_crit",
             "D0", "eps_th", "eps_c", "bonora_alpha", "n_hard", "p_gate",
-            "jc_B", "jc_C", "jc_m", "T_melt", "C_V")]
+            "jc_B", "jc_C", "jc_m", "T_melt", "C_V",
+            "G_p", "Gamma1", "Gamma2", "gamma_bp", "Ddot0")]
 
 
 class FvOptions(ctypes.Structure):
@@ -43,7 +44,8 @@ class FvOptions(ctypes.Structure):
                 ("phi_floor", ctypes.c_double), ("weno_eps", ctypes.c_double),
                 ("phi_fp64_cut", ctypes.c_double),
                 ("tile", ctypes.c_int32 * 3), ("use_graph", ctypes.c_int32),
-                ("seed_nu", ctypes.c_double), ("thinc_beta", ctypes.c_double)]
+                ("seed_nu", ctypes.c_double), ("thinc_beta", ctypes.c_double),
+                ("driver", ctypes.c_double * 6)]
 
 
 class FvFragment(ctypes.Structure):
@@ -150,14 +152,15 @@ def material_array(mats):
                     "p_gate"):
             setattr(a, key, float(m[key]))
         a.yield_ = float(m["yield_stress"])
-        for key in ("jc_B", "jc_C", "jc_m", "T_melt", "C_V"):
+        for key in ("jc_B", "jc_C", "jc_m", "T_melt", "C_V",
+                    "G_p", "Gamma1", "Gamma2", "gamma_bp", "Ddot0"):
             setattr(a, key, float(m.get(key, 0.0)))
     return arr
 
 
 def options_struct(precision="fp64", cfl=0.6, phi_floor=1e-8, weno_eps=1e-6,
                    phi_fp64_cut=1e-6, tile=None, use_graph=False, seed_nu=0.0,
-                   thinc_beta=0.0):
+                   thinc_beta=0.0, driver=None):
     o = FvOptions()
     o.precision = PRECISIONS[precision]
     o.cfl = cfl
@@ -171,6 +174,9 @@ def options_struct(precision="fp64", cfl=0.6, phi_floor=1e-8, weno_eps=1e-6,
     o.use_graph = 1 if use_graph else 0
     o.seed_nu = float(seed_nu)
     o.thinc_beta = float(thinc_beta)
+    if driver is not None:
+        for k, v in enumerate(driver):
+            o.driver[k] = float(v)
     return o
 
 

@@ -121,7 +121,9 @@ static int validate(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
             m.D_crit > m.D0 && m.D_crit < 1 && m.eps_c > m.eps_th && m.eps_th > 0 &&
             m.bonora_alpha > 0 && m.n_hard > 0 && m.yield >= 0 && m.jc_B >= 0 &&
             m.jc_C >= 0 && m.T_melt >= 0 &&
-            (m.T_melt == 0 || (m.T_melt > 300.0 && m.jc_m > 0 && m.C_V > 0)))) {
+            (m.T_melt == 0 || (m.T_melt > 300.0 && m.jc_m > 0 && m.C_V > 0)) &&
+            m.G_p >= 0 && m.Ddot0 >= 0 &&
+            ((m.Gamma1 == 0 && m.Gamma2 == 0) || m.gamma_bp > 0))) {
         msg = "invalid solid constants"; return FV_EINVAL;
       }
     } else if (!(mats[l].Gamma0 > 0)) { msg = "gas needs Gamma0 > 0"; return FV_EINVAL; }
@@ -133,6 +135,14 @@ static int validate(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
   if (!(opt->weno_eps > 0)) { msg = "weno_eps must be > 0"; return FV_EINVAL; }
   if (!(opt->seed_nu >= 0 && opt->seed_nu < 1)) { msg = "seed_nu must be in [0, 1)"; return FV_EINVAL; }
   if (!(opt->thinc_beta >= 0 && opt->thinc_beta <= 10)) { msg = "thinc_beta must be in [0, 10]"; return FV_EINVAL; }
+  {
+    const double* d = opt->driver;
+    if (d[5] != 0.0 && !(grids[0].dim >= 2 && d[0] >= 0 && d[5] > d[0] && d[3] > 0 &&
+                         d[4] > d[3] && d[1] == d[1] && d[2] == d[2])) {
+      msg = "driver needs dim >= 2, 0 <= r_in < r_max, 0 < t0 < t1";
+      return FV_EINVAL;
+    }
+  }
   if (opt->tile[2] < FV_SCHED_BY_INSTANCE || opt->tile[2] > FV_SCHED_INTERLEAVED) {
     msg = "tile[2] must be a block schedule (0, 1 or 2)"; return FV_EINVAL;
   }
@@ -229,6 +239,9 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
     q.nhard = m.n_hard; q.pgate = m.p_gate;
     q.jcB = m.jc_B; q.jcC = m.jc_C; q.jcm = m.jc_m; q.Tmelt = m.T_melt; q.CV = m.C_V;
     q.jc = q.kind == 0 && (m.jc_B != 0.0 || m.jc_C != 0.0 || m.T_melt > 0.0);
+    q.Gp = m.G_p; q.G1 = m.Gamma1; q.G2 = m.Gamma2; q.gbp = m.gamma_bp; q.Ddot0 = m.Ddot0;
+    q.stein = q.kind == 0 && m.G_p > 0.0;
+    q.bp = q.kind == 0 && (m.Gamma1 != 0.0 || m.Gamma2 != 0.0);
     q.invGamma = 1.0 / m.Gamma0;
     auto small_int = [](double v) {
       const double r = std::round(v);
@@ -247,6 +260,7 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
   P.phi_fp64_cut = opt->phi_fp64_cut;
   P.seed_nu = opt->seed_nu;
   P.thinc_beta = opt->thinc_beta;
+  for (int k = 0; k < 6; ++k) P.drv[k] = opt->driver[k];
   set_float_constants(P);
 }
 

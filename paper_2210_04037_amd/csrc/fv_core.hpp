@@ -43,6 +43,8 @@ FV_HD double m_sqrt(double x) { return sqrt(x); }
 FV_HD float m_sqrt(float x) { return sqrtf(x); }
 FV_HD double m_log(double x) { return log(x); }
 FV_HD float m_log(float x) { return logf(x); }
+FV_HD double m_cbrt(double x) { return cbrt(x); }
+FV_HD float m_cbrt(float x) { return cbrtf(x); }
 FV_HD double m_exp(double x) { return exp(x); }
 FV_HD float m_exp(float x) { return expf(x); }
 FV_HD double m_pow(double x, double y) { return pow(x, y); }
@@ -76,6 +78,11 @@ struct MatP {
   double rho0, K0, alpha, G0, beta, Gamma0;
   double yield, Dcrit, D0, eps_th, eps_c, balpha, nhard, pgate;
   double jcB, jcC, jcm, Tmelt, CV;   // Johnson-Cook c2, c3, m, T_melt, C_V
+  // Steinberg modulus G0 + Gp p_c eta^(-1/3) (stein), Burakovsky-Preston
+  // Grueneisen Gamma0 + G1 eta^(-1/3) + G2 eta^(-gbp) (bp), simplified damage
+  // law dD/deps = Ddot0 (1 - D) (Ddot0 > 0)
+  double Gp, G1, G2, gbp, Ddot0;
+  int stein, bp;
   // host-derived constants
   // Critical level of the Section 3.1 test D >= D_crit, which holds up to the
   // rounding of the advected ratio (phi rho D)/(phi rho) of a clamped cell:
@@ -90,6 +97,7 @@ struct MatP {
   // closures: the kernels read them as arguments in scalar registers instead
   // of converting the doubles per wave (the same rounding either way)
   float f_rho0, f_K0, f_alpha, f_G0, f_beta, f_Gamma0, f_invGamma, f_Dcrit_eff;
+  float f_Gp, f_G1, f_G2, f_gbp;
 };
 
 struct Params {
@@ -103,6 +111,9 @@ struct Params {
   // THINC sharpening of the volume fractions: steepness (0: MUSCL), with
   // tanh(beta) and 1/cosh(beta) formed on the host
   double thinc_beta, thinc_tb, thinc_sech;
+  // imposed-velocity driver of the ring (Section 4.3): inner radius, v0, v1,
+  // t0, t1, r_max (r_max = 0: off)
+  double drv[6];
   float f_weno_eps, f_c_min2, f_phi_fp64_cut, f_pad;
   float f_thinc_beta, f_thinc_tb, f_thinc_sech, f_pad2;
 };
@@ -122,6 +133,7 @@ inline void set_float_constants(Params& P) {
     m.f_rho0 = (float)m.rho0; m.f_K0 = (float)m.K0; m.f_alpha = (float)m.alpha;
     m.f_G0 = (float)m.G0; m.f_beta = (float)m.beta; m.f_Gamma0 = (float)m.Gamma0;
     m.f_invGamma = (float)m.invGamma; m.f_Dcrit_eff = (float)m.Dcrit_bulk;
+    m.f_Gp = (float)m.Gp; m.f_G1 = (float)m.G1; m.f_G2 = (float)m.G2; m.f_gbp = (float)m.gbp;
   }
   P.f_weno_eps = (float)P.weno_eps;
   P.f_c_min2 = (float)P.c_min2;
@@ -221,8 +233,37 @@ template <int DIM> FV_HD int hk_j(int q) {
 // modulus G~ = G0 eta^(beta+1).  Gas: all zero.  Solids come first in a
 // material list (checked when a context is made), so material l is a solid
 // exactly when l < NS and the kernels decide the kind at compile time.
+// invG = 1/Gamma(rho) and g1 = Gamma + 1 + rho Gamma'/Gamma (the factor of
+// the thermal pressure in rho c^2) carry the Grueneisen function per cell.
 template <class C>
-struct RefT { C rho_eref, pref, rho_dpref, G; };
+struct RefT { C rho_eref, pref, rho_dpref, G, invG, g1; };
+
+// Shear modulus and its density derivatives rho G' and rho^2 G''.
+// Romenskii: G0 eta^(beta+1), (beta+1) G, (beta+1) beta G.  Steinberg
+// (Section 2.3): G0 + Gp p_c eta^(-1/3), from the cold pressure and its
+// derivatives, rho G' = Gp eta^(-1/3)(rho p_c' - p_c/3) and
+// rho^2 G'' = Gp eta^(-1/3)(rho^2 p_c'' - (2/3) rho p_c' + (4/9) p_c), with
+// rho^2 p_c'' = (K0/a) eta^(a+1) ((2a+1) 2a eta^a - (a+1) a).
+template <class C>
+FV_HD void shear_terms(const MatP& m, C eta, C ea, C ea1, C pc, C rho_dpc, C* G, C* rG1,
+                       C* r2G2) {
+  if (!m.stein) {
+    const C b = cst<C>(m.beta, m.f_beta);
+    const C Gt = cst<C>(m.G0, m.f_G0) * powi_or(eta, b + (C)1, m.beta1_i);
+    *G = Gt;
+    *rG1 = (b + (C)1) * Gt;
+    *r2G2 = (b + (C)1) * b * Gt;
+    return;
+  }
+  const C a = cst<C>(m.alpha, m.f_alpha);
+  const C K0 = cst<C>(m.K0, m.f_K0);
+  const C r2 = K0 / a * ea1 * (((C)2 * a + (C)1) * (C)2 * a * ea - (a + (C)1) * a);
+  const C e3 = (C)1 / m_cbrt(eta);
+  const C Gp = cst<C>(m.Gp, m.f_Gp);
+  *G = cst<C>(m.G0, m.f_G0) + Gp * pc * e3;
+  *rG1 = Gp * e3 * (rho_dpc - pc / (C)3);
+  *r2G2 = Gp * e3 * (r2 - (C)(2.0 / 3.0) * rho_dpc + (C)(4.0 / 9.0) * pc);
+}
 
 template <class C>
 FV_HD RefT<C> solid_ref_terms(const MatP& m, C rho, C J2, C D) {
@@ -236,20 +277,46 @@ FV_HD RefT<C> solid_ref_terms(const MatP& m, C rho, C J2, C D) {
   const C rho_ec = rho * K0 / ((C)2 * rho0 * a * a) * (ea - (C)1) * (ea - (C)1);
   const C pc = K0 / a * ea1 * (ea - (C)1);
   const C rho_dpc = K0 / a * ea1 * (((C)2 * a + (C)1) * ea - (a + (C)1));
-  const C b = cst<C>(m.beta, m.f_beta);
-  const C Gt = cst<C>(m.G0, m.f_G0) * powi_or(eta, b + (C)1, m.beta1_i);
+  C Gt, rG1, r2G2;
+  shear_terms<C>(m, eta, ea, ea1, pc, rho_dpc, &Gt, &rG1, &r2G2);
   const C w = (C)1 - D;
   r.rho_eref = w * (rho_ec + Gt * J2);
-  r.pref = w * (pc + b * Gt * J2);
-  r.rho_dpref = w * (rho_dpc + b * (b + (C)1) * Gt * J2);
+  r.pref = w * (pc + (rG1 - Gt) * J2);
+  r.rho_dpref = w * (rho_dpc + r2G2 * J2);
   r.G = w * Gt;
   return r;
 }
 
 template <class C>
 FV_HD C shear_modulus_undamaged(const MatP& m, C rho) {
-  return cst<C>(m.G0, m.f_G0) *
-         powi_or(rho / cst<C>(m.rho0, m.f_rho0), cst<C>(m.beta, m.f_beta) + (C)1, m.beta1_i);
+  if (!m.stein)
+    return cst<C>(m.G0, m.f_G0) *
+           powi_or(rho / cst<C>(m.rho0, m.f_rho0), cst<C>(m.beta, m.f_beta) + (C)1, m.beta1_i);
+  const C a = cst<C>(m.alpha, m.f_alpha);
+  const C eta = rho / cst<C>(m.rho0, m.f_rho0);
+  const C ea = powi_or(eta, a, m.alpha_i);
+  const C pc = cst<C>(m.K0, m.f_K0) / a * ea * eta * (ea - (C)1);
+  return cst<C>(m.G0, m.f_G0) + cst<C>(m.Gp, m.f_Gp) * pc / m_cbrt(eta);
+}
+
+// Grueneisen share of a material at phasic density rho: sets invG and g1 of
+// its reference terms (constants unless Burakovsky-Preston:
+// Gamma = Gamma0 + G1 eta^(-1/3) + G2 eta^(-gbp),
+// rho Gamma' = -G1 eta^(-1/3)/3 - gbp G2 eta^(-gbp)).
+template <class C>
+FV_HD void gamma_terms(const MatP& m, C rho, RefT<C>& t) {
+  if (!m.bp) {
+    t.invG = cst<C>(m.invGamma, m.f_invGamma);
+    t.g1 = cst<C>(m.Gamma0, m.f_Gamma0) + (C)1;
+    return;
+  }
+  const C eta = rho / cst<C>(m.rho0, m.f_rho0);
+  const C e3 = (C)1 / m_cbrt(eta);
+  const C eg = m_pow(eta, -cst<C>(m.gbp, m.f_gbp));
+  const C g1t = cst<C>(m.G1, m.f_G1) * e3, g2t = cst<C>(m.G2, m.f_G2) * eg;
+  const C gam = cst<C>(m.Gamma0, m.f_Gamma0) + g1t + g2t;
+  t.invG = (C)1 / gam;
+  t.g1 = gam + (C)1 + (-g1t / (C)3 - cst<C>(m.gbp, m.f_gbp) * g2t) / gam;
 }
 
 // ----------------------------------------------------------------------------
@@ -290,12 +357,15 @@ FV_HD void mix_terms(const Params& P, const C* phi, const C* rho_l, const C* D,
   mx.xi = 0;
 #pragma unroll
   for (int l = 0; l < NM; ++l) {
-    if (l < NS && phi[l] >= (C)PHI_TRACE) {
+    const bool live = l < NS && phi[l] >= (C)PHI_TRACE;
+    if (live) {
       mx.t[l] = solid_ref_terms<C>(P.mat[l], rho_l[l], J2, D[l < NS ? l : 0]);
     } else {
       mx.t[l].rho_eref = 0; mx.t[l].pref = 0; mx.t[l].rho_dpref = 0; mx.t[l].G = 0;
     }
-    mx.xi += phi[l] * cst<C>(P.mat[l].invGamma, P.mat[l].f_invGamma);
+    // a trace takes its Grueneisen function at the reference density
+    gamma_terms<C>(P.mat[l], live ? rho_l[l] : cst<C>(P.mat[l].rho0, P.mat[l].f_rho0), mx.t[l]);
+    mx.xi += phi[l] * mx.t[l].invG;
   }
 }
 
@@ -308,7 +378,7 @@ FV_HD C mix_pressure(const Params& P, const C* phi, const Mix<NM, NS, C>& mx,
 #pragma unroll
   for (int l = 0; l < NM; ++l) {
     th = th - phi[l] * mx.t[l].rho_eref;
-    cold = cold + phi[l] * mx.t[l].pref * cst<C>(P.mat[l].invGamma, P.mat[l].f_invGamma);
+    cold = cold + phi[l] * mx.t[l].pref * mx.t[l].invG;
   }
   return (m_max(th, (C)0) + cold) / mx.xi;
 }
@@ -319,7 +389,7 @@ FV_HD C mix_energy(const Params& P, const C* phi, const Mix<NM, NS, C>& mx, C p)
 #pragma unroll
   for (int l = 0; l < NM; ++l)
     re = re + phi[l] * mx.t[l].rho_eref -
-         phi[l] * mx.t[l].pref * cst<C>(P.mat[l].invGamma, P.mat[l].f_invGamma);
+         phi[l] * mx.t[l].pref * mx.t[l].invG;
   return re;
 }
 
@@ -339,11 +409,10 @@ FV_HD C mix_sound(const Params& P, const C* phi, const Mix<NM, NS, C>& mx, C p,
   Gmix = 0;
 #pragma unroll
   for (int l = 0; l < NM; ++l) {
-    const C g = cst<C>(P.mat[l].Gamma0, P.mat[l].f_Gamma0);
     // thermal term non-negative: a state below the cold curve (a gas
     // fraction pulled into tension) must not collapse the wave speed
-    acc += phi[l] * cst<C>(P.mat[l].invGamma, P.mat[l].f_invGamma) *
-           (mx.t[l].rho_dpref + (g + (C)1) * m_max(p - mx.t[l].pref, (C)0));
+    acc += phi[l] * mx.t[l].invG *
+           (mx.t[l].rho_dpref + mx.t[l].g1 * m_max(p - mx.t[l].pref, (C)0));
     Gmix += phi[l] * mx.t[l].G;
   }
   const C cb2 = solid_frac<NM>(phi) * acc / (mx.xi * rho);
@@ -615,6 +684,30 @@ template <class C> FV_HD C weno3_left(C qm, C q0, C q1, C eps) {
 }
 
 // ----------------------------------------------------------------------------
+// Imposed-velocity driver of the ring (Section 4.3): the radial speed
+// v_r(t) = v0 t/t0 (t < t0), v0 + (v1 - v0)(t - t0)/(t1 - t0) (t0 < t < t1),
+// v1 afterwards; the driver surface starts at the ring's inner radius and
+// moves with v_r, R_d(t) = r_in + the integral of v_r, until it reaches
+// r_max.  drv = {r_in, v0, v1, t0, t1, r_max}.
+// ----------------------------------------------------------------------------
+FV_HD double driver_speed(const double* d, double t) {
+  if (t < d[3]) return d[1] * t / d[3];
+  if (t < d[4]) return d[1] + (d[2] - d[1]) * (t - d[3]) / (d[4] - d[3]);
+  return d[2];
+}
+
+FV_HD double driver_radius(const double* d, double t) {
+  const double v0 = d[1], v1 = d[2], t0 = d[3], t1 = d[4];
+  if (t < t0) return d[0] + 0.5 * v0 * t * t / t0;
+  const double a = d[0] + 0.5 * v0 * t0;
+  if (t < t1) {
+    const double s = t - t0;
+    return a + v0 * s + 0.5 * (v1 - v0) * s * s / (t1 - t0);
+  }
+  return a + 0.5 * (v0 + v1) * (t1 - t0) + v1 * (t - t1);
+}
+
+// ----------------------------------------------------------------------------
 // Johnson-Cook plasticity: the law of Johnson and Cook (1983) with the
 // constants of the paper's plasticity table (the paper names the law and
 // tabulates c1..C_V without printing it).  Reference rate 1/s (slower rates
@@ -629,8 +722,17 @@ constexpr double JC_RATE_REF = 1.0;
 // (the Romenskii Debye temperature).
 FV_HD double jc_temperature(const MatP& m, double p, double pref, double rho) {
   if (!(m.CV > 0.0)) return JC_T_REF;
-  const double et = (p - pref > 0.0 ? p - pref : 0.0) / (rho * m.Gamma0);
-  return et / m.CV + JC_T_REF * pow(rho / m.rho0, m.Gamma0);
+  const double eta = rho / m.rho0;
+  double gam = m.Gamma0, th = pow(eta, m.Gamma0);
+  if (m.bp) {
+    // Burakovsky-Preston: Gamma(rho) and the Debye temperature
+    // eta^Gamma0 exp[3 G1 (1 - eta^(-1/3)) + (G2/gbp)(1 - eta^(-gbp))]
+    const double e3 = 1.0 / cbrt(eta), eg = pow(eta, -m.gbp);
+    gam = m.Gamma0 + m.G1 * e3 + m.G2 * eg;
+    th *= exp(3.0 * m.G1 * (1.0 - e3) + (m.G2 / m.gbp) * (1.0 - eg));
+  }
+  const double et = (p - pref > 0.0 ? p - pref : 0.0) / (rho * gam);
+  return et / m.CV + JC_T_REF * th;
 }
 
 // Flow stress at plastic strain eps_n + dg, rate dg/dt and temperature T;
@@ -681,13 +783,20 @@ FV_HD double bonora_rate(const MatP& m, double D, double eps, double R) {
 }
 
 // classical RK4 in eps_p over [eps0, eps0 + h], every argument clamped
+// dD/deps: the Bonora rate, or Ddot0 (1 - D) for the simplified law of the
+// U-Nb ring (Section 4.3); zero once critical either way
+FV_HD double damage_rate(const MatP& m, double D, double eps, double R) {
+  if (m.Ddot0 > 0.0) return D >= m.Dcrit ? 0.0 : m.Ddot0 * (1.0 - D);
+  return bonora_rate(m, D, eps, R);
+}
+
 FV_HD double damage_rk4(const MatP& m, double D, double eps0, double h, double R) {
   const double Dc = m.Dcrit;
   auto cl = [Dc](double v) { return v < 0.0 ? 0.0 : (v > Dc ? Dc : v); };
-  const double k1 = bonora_rate(m, D, eps0, R);
-  const double k2 = bonora_rate(m, cl(D + 0.5 * h * k1), eps0 + 0.5 * h, R);
-  const double k3 = bonora_rate(m, cl(D + 0.5 * h * k2), eps0 + 0.5 * h, R);
-  const double k4 = bonora_rate(m, cl(D + h * k3), eps0 + h, R);
+  const double k1 = damage_rate(m, D, eps0, R);
+  const double k2 = damage_rate(m, cl(D + 0.5 * h * k1), eps0 + 0.5 * h, R);
+  const double k3 = damage_rate(m, cl(D + 0.5 * h * k2), eps0 + 0.5 * h, R);
+  const double k4 = damage_rate(m, cl(D + h * k3), eps0 + h, R);
   return cl(D + h / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4));
 }
 

@@ -186,6 +186,7 @@ stage_kernel(const Inst* __restrict__ insts, const int2* __restrict__ block_tab,
     dts_set_dtinv(dts, 1 - q, 0.0);
   }
   cx.dt = (C)dt;
+  cx.tn = t + dt;
   if (has_a) St::template prims_of<int>(cx, UA, sm, TL::NCELL, tcA);
   if (has_h) St::template prims_of<int>(cx, UH, sm, TL::NCELL, tcH);
   for (int h = tid + NT; h < TL::NHALO; h += NT) St::load_cell(cx, sm, TL::halo_cell(h));
@@ -344,6 +345,7 @@ __device__ __forceinline__ bool setup3(const Inst& I, const Params& P, int stage
   cx.bx = 0;
   cx.by = 0;
   cx.dt = (C)dt;
+  cx.tn = t + dt;
   const T* U = (const T*)I.U;
   cx.base = U;
   cx.src = stage == 1 ? U : (stage == 2 ? (const T*)I.U1 : (const T*)I.U2);

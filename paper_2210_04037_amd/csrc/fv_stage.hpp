@@ -143,6 +143,7 @@ struct Stage {
     int parity;     // step & 1
     int bx, by;     // tile coordinates
     C dt;
+    double tn;      // time at the end of the step (t + dt)
     const T* src;   // stage input
     const T* base;  // U^n
     T* out;         // stage output
@@ -162,7 +163,7 @@ struct Stage {
 #pragma unroll
     for (int l = 0; l < NM; ++l) {
       rho += m_max((double)U[L::MASS + l], 0.0);
-      xi += (double)U[L::PHI + l] * P.mat[l].invGamma;
+      xi += (double)U[L::PHI + l] * (P.mat[l].bp ? (double)mx.t[l].invG : P.mat[l].invGamma);
     }
     double m2 = 0;
 #pragma unroll
@@ -172,7 +173,8 @@ struct Stage {
     for (int l = 0; l < NM; ++l) {
       const double ph = (double)U[L::PHI + l];
       th = th - ph * (double)mx.t[l].rho_eref;
-      cold = cold + ph * (double)mx.t[l].pref * P.mat[l].invGamma;
+      cold = cold + ph * (double)mx.t[l].pref *
+                        (P.mat[l].bp ? (double)mx.t[l].invG : P.mat[l].invGamma);
     }
     return (C)((m_max(th, 0.0) + cold) / xi);
   }
@@ -895,7 +897,8 @@ struct Stage {
   }
 
   // Returns the cell's CFL sum  sum_a (|u_a| + c)/dx_a  after the source step.
-  FV_HD static double source_and_cfl(const Params& P, const Inst& I, double* U, double dt) {
+  FV_HD static double source_and_cfl(const Params& P, const Inst& I, double* U, double dt,
+                                     int64_t g, double tn) {
     double phi[NM], mass[NM], rho_l[NM], eps[NS > 0 ? NS : 1], D[NS > 0 ? NS : 1];
     double rho = 0;
 #pragma unroll
@@ -1008,16 +1011,21 @@ struct Stage {
         const double Y0 = ymix(0.0, &dY0);
         const double s6G = sqrt(6.0) * Gm;
         if (s6G * J > Y0) {
+          // converged when the residual is at the rounding of the stress
+          // scale sqrt6 G J or the bracket at that of its bound; a small
+          // Newton step alone is no test (the hardening term's derivative
+          // grows without bound as eps_p + d goes to zero)
           double lo = 0.0, hi = sqrt(2.0 / 3.0) * (J - Y0 / s6G), x = hi;
-          for (int it = 0; it < 100; ++it) {
+          const double fscale = 1e-14 * s6G * J;
+          for (int it = 0; it < 200; ++it) {
             double dY;
             const double f = s6G * (J - sqrt(1.5) * x) - ymix(x, &dY);
+            if (fabs(f) <= fscale) break;
             if (f > 0.0) lo = x; else hi = x;
+            if (hi - lo <= 1e-15 * hi) { x = 0.5 * (lo + hi); break; }
             double xn = x - f / (-3.0 * Gm - dY);
             if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-            const bool done = fabs(xn - x) <= 1e-15 * x || hi - lo <= 1e-15 * hi;
             x = xn;
-            if (done) break;
           }
           deps = x;
           scale = (J - sqrt(1.5) * x) / J;
@@ -1047,15 +1055,18 @@ struct Stage {
         const double dl = phi[s] >= PHI_TRACE ? deps : 0.0;
         const double seq = (1.0 - D[s]) * pert *
                          (jc ? jc_yield(m, eps[s], dl, dt, Tl[s], nullptr) : m.yield);
-        bool gate = (p < m.pgate) && (dl > 0.0) && (D[s] < crit_level(m));
+        // the simplified law has no gate: any plastic increment of a live
+        // solid below D_crit
+        const bool simple = m.Ddot0 > 0.0;
+        bool gate = (simple || p < m.pgate) && (dl > 0.0) && (D[s] < crit_level(m));
         const bool ok = seq > 0.0;
         const double R = ok ? triaxiality(m, p, seq, closure_density(m, phi[s], rho_l[s])) : 1.0;
-        if (gate) {
+        if (gate && !simple) {
           const double thr = eps_threshold(m, R);
           gate = (eps[s] > thr) || !ok;
         }
         Dn[s] = D[s];
-        if (gate) Dn[s] = ok ? damage_rk4(m, D[s], eps[s], dl, R) : m.Dcrit;
+        if (gate) Dn[s] = (ok || simple) ? damage_rk4(m, D[s], eps[s], dl, R) : m.Dcrit;
         const double ms = U[L::MASS + s];
         U[L::HIST + 2 * s] = ms * (eps[s] + dl);
         U[L::HIST + 2 * s + 1] = ms * Dn[s];
@@ -1066,6 +1077,34 @@ struct Stage {
         U[L::VB + q] = vb_i<DIM>(q) == vb_j<DIM>(q) ? 1.0 : 0.0;
 #pragma unroll
       for (int s = 0; s < NS; ++s) Dn[s] = D[s];
+    }
+    // imposed-velocity driver (Section 4.3): a live solid behind the driver
+    // surface moves outward at least at the driver's speed; the kinetic
+    // energy this adds is the driver's work
+    if constexpr (DIM >= 2) {
+      if (P.drv[5] > 0.0 && live) {
+        const double Rd = driver_radius(P.drv, tn);
+        if (Rd < P.drv[5]) {
+          const int64_t ix = g % I.n[0], iy = (g / I.n[0]) % I.n[1];
+          const double x = I.lo[0] + ((double)ix + 0.5) * I.dx[0];
+          const double y = I.lo[1] + ((double)iy + 0.5) * I.dx[1];
+          const double r = sqrt(x * x + y * y);
+          const double vr = driver_speed(P.drv, tn);
+          if (r > 0.0 && r <= Rd) {
+            const double ur = (u[0] * x + u[1] * y) / r;
+            if (ur < vr) {
+              const double du = vr - ur;
+              const double ke0 = ke;
+              u[0] += du * x / r;
+              u[1] += du * y / r;
+              ke = 0.0;
+#pragma unroll
+              for (int k = 0; k < DIM; ++k) { U[L::MOM + k] = rho * u[k]; ke += u[k] * u[k]; }
+              U[L::ENE] += 0.5 * rho * (ke - ke0);
+            }
+          }
+        }
+      }
     }
     // CFL sum on the new state, in the policy precision C
     C phic[NM], rlc[NM], Dc[NS > 0 ? NS : 1];
@@ -1087,9 +1126,10 @@ struct Stage {
       double xi = 0, th = rho_e, cold = 0;
 #pragma unroll
       for (int l = 0; l < NM; ++l) {
-        xi += phi[l] * P.mat[l].invGamma;
+        const double ig = P.mat[l].bp ? (double)mx2.t[l].invG : P.mat[l].invGamma;
+        xi += phi[l] * ig;
         th -= phi[l] * (double)mx2.t[l].rho_eref;
-        cold += phi[l] * (double)mx2.t[l].pref * P.mat[l].invGamma;
+        cold += phi[l] * (double)mx2.t[l].pref * ig;
       }
       p2 = (C)((m_max(th, 0.0) + cold) / xi);
     }
@@ -1184,7 +1224,7 @@ struct Stage {
 #pragma unroll
     for (int l = 0; l < NM; ++l) Un[L::PHI + l] = m_clamp(Un[L::PHI + l], cx.P.phi_floor, 1.0);
     double cfl = 0;
-    if (cx.stage == 3) cfl = source_and_cfl(cx.P, I, Un, (double)cx.dt);
+    if (cx.stage == 3) cfl = source_and_cfl(cx.P, I, Un, (double)cx.dt, g, cx.tn);
     double rho = 0;
     bool nan = false;
 #pragma unroll

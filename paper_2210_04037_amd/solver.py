@@ -39,7 +39,8 @@ class GpuSolver:
         self.opt = abi.options_struct(precision, cfl or c0.cfl, phi_floor,
                                       weno_eps, phi_fp64_cut, tile, use_graph,
                                       getattr(c0, "seed_nu", 0.0),
-                                      getattr(c0, "thinc_beta", 0.0))
+                                      getattr(c0, "thinc_beta", 0.0),
+                                      getattr(c0, "driver", None))
         self.S = lib.fv_state_fields(self.dim, len(self.mats), self.mat_arr)
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         self.states, self.phi0s = [], []

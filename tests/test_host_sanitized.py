@@ -49,7 +49,8 @@ def _write_input(path, case, steps, tile_x):
         f.write(bytes(abi.material_array(case.mats)))
         f.write(bytes(abi.options_struct("fp64", case.cfl,
                                          seed_nu=getattr(case, "seed_nu", 0.0),
-                                         thinc_beta=getattr(case, "thinc_beta", 0.0))))
+                                         thinc_beta=getattr(case, "thinc_beta", 0.0),
+                                         driver=getattr(case, "driver", None))))
         f.write(np.int64(L.S).tobytes())
         f.write(np.int64(ncell).tobytes())
         f.write(np.int32(steps).tobytes())
@@ -95,7 +96,8 @@ def _assert_matches_oracle(case, steps, t, flag, U, L):
     ("ring2d_spare14", 3),
     ("shell3d", 2),
     ("impact3d", 2), ("disk2d", 40), ("alcube1d", 120), ("alcube2d", 30),
-    ("disk2d_jc", 30), ("ring2d_thinc", 6), ("spall1d_thinc", 40)])
+    ("disk2d_jc", 30), ("ring2d_thinc", 6), ("spall1d_thinc", 40),
+    ("unb2d", 6), ("unb3d", 4)])
 def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
     tile_x = 0
     if which == "spall1d":
@@ -127,6 +129,15 @@ def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
     elif which == "spall1d_thinc":
         case = F.make_case(1, n=45)
         case.thinc_beta = 1.6
+    elif which == "unb2d":
+        # Steinberg modulus, Burakovsky-Preston Grueneisen, Johnson-Cook with
+        # thermal softening, the simplified damage law, the driver, seeding.
+        # Later, cells the driver leaves at volume fractions just above the
+        # trace threshold, at normal density, set the CFL step, and
+        # rounding-order differences flip the trace switch there.
+        case = F.unb_ring(2, n=40)
+    elif which == "unb3d":
+        case = F.unb_ring(3, n=24, nz=4)
     elif which == "disk2d_jc":
         # Johnson-Cook with thermal softening (304L row)
         case = F.expanding_disk(20, mat=F.STEEL_304L_JC)
