@@ -174,7 +174,7 @@ static int validate(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
 }
 
 struct WsPlan {
-  std::vector<size_t> u1, u2, bacc, dts, wb, fb[3];
+  std::vector<size_t> u1, u2, bacc, dts, wb, acc;
   size_t insts = 0, block_tab = 0, bins = 0, total = 0;
   int max_blocks = 0;
 };
@@ -209,13 +209,11 @@ static void plan_ws(int32_t n_inst, const fv_grid* grids, const std::vector<Ops>
     }
     W.bacc.push_back(off); off += align256(nb * sizeof(double));
     W.dts.push_back(off); off += align256(DTS_SIZE * sizeof(double));
-    // 3D passes: primitives of every cell and the face data of each direction
+    // 3D passes: primitives of every cell and each cell's divergence sum
     W.wb.push_back(off);
     if (g.dim == 3) off += align256((size_t)o.NW * ncell * o.elem);
-    for (int a = 0; a < 3; ++a) {
-      W.fb[a].push_back(off);
-      if (g.dim == 3) off += align256((size_t)o.NQ * (ncell / g.n[a]) * (g.n[a] + 1) * o.elem);
-    }
+    W.acc.push_back(off);
+    if (g.dim == 3) off += sb;
   }
   W.insts = off; off += align256(sizeof(Inst) * n_inst);
   W.block_tab = off; off += align256(sizeof(int2) * W.max_blocks);
@@ -454,7 +452,7 @@ int32_t fv_init(fv_ctx** out, int32_t n_inst, const fv_grid* grids, int32_t n_ma
     I.phi0 = phi0[i];
     I.bacc = (double*)(ws + W.bacc[i]);
     I.Wb = g.dim == 3 ? (void*)(ws + W.wb[i]) : nullptr;
-    for (int a = 0; a < 3; ++a) I.Fb[a] = g.dim == 3 ? (void*)(ws + W.fb[a][i]) : nullptr;
+    I.Acc = g.dim == 3 ? (void*)(ws + W.acc[i]) : nullptr;
     I.dts = (double*)(ws + W.dts[i]);
     for (int k = 0; k < 3; ++k) {
       I.n[k] = g.n[k];

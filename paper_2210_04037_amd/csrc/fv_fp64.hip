@@ -44,7 +44,10 @@ bool select_ops_fp64(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t
     FV_VARN(2, 2, 1, double, double, 32, 7, 256)
     FV_VARN(2, 2, 1, double, double, 16, 7, 128)
     FV_VAR(2, 2, 1, double, double, 16, 8)
-    FV_VAR(2, 2, 1, double, double, 32, 8)
+    // no 32 x 8 tile: that build of this kernel (256 VGPRs and 12 spilled to
+    // accumulation registers, the most of any shape) drifts from the oracle
+    // (4.7e-8 after 20 steps of the ring) while every other shape, from the
+    // same source, agrees with it to 1e-12 and bitwise with each other
     return true;
   }
   if (dim == 3 && nm == 1 && ns == 1) {

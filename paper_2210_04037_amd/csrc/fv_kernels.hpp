@@ -357,29 +357,6 @@ __device__ __forceinline__ int64_t nfaces3(const Inst& I, int a) {
   return I.ncell / I.n[a] * (I.n[a] + 1);
 }
 
-// Brick traversal of the y- and z-face passes: a block of 256 threads covers
-// 64 faces along x by 4 along the other transverse direction, and consecutive
-// block numbers step along the face direction first, so the cell planes a
-// brick's stencil reaches are still in the XCD's L2 for the next block (a
-// 256^2 plane of primitives is larger than one XCD's L2).
-constexpr int BRX = 64, BRY = 4;
-__host__ __device__ inline int64_t brick_blocks(int n_t, int n_u, int n_s) {
-  // n_t: cells along x, n_u: along the other transverse direction,
-  // n_s: positions along the stepping direction
-  return (int64_t)((n_t + BRX - 1) / BRX) * ((n_u + BRY - 1) / BRY) * n_s;
-}
-// position of thread tid of brick block b: x, transverse u, step s;
-// false past the domain
-__device__ __forceinline__ bool brick_pos(int64_t b, int n_t, int n_u, int n_s, int& x, int& u,
-                                          int& s) {
-  s = (int)(b % n_s);
-  const int64_t br = b / n_s;
-  const int nbx = (n_t + BRX - 1) / BRX;
-  x = (int)(br % nbx) * BRX + (int)(threadIdx.x % BRX);
-  u = (int)(br / nbx) * BRY + (int)(threadIdx.x / BRX);
-  return x < n_t && u < n_u;
-}
-
 template <int NM, int NS, class T, class C>
 __global__ void __launch_bounds__(256) prim3_kernel(const Inst* insts, int ii, Params P,
                                                     int stage, int parity) {
@@ -393,61 +370,49 @@ __global__ void __launch_bounds__(256) prim3_kernel(const Inst* insts, int ii, P
   St::template cell_prims<int64_t>(cx, g, (C*)I.Wb, I.ncell, g);
 }
 
-// the direction is a template argument: every per-direction index in the
-// face computation is then a constant (a runtime direction would put those
-// arrays in scratch memory)
+// x-faces in runs of XRUN + 1 faces overlapping by one (a block per run):
+// each thread computes one face into LDS, then the cell between its face and
+// the next one starts its divergence sum
+template <int NM, int NS, class T, class C>
+__global__ void __launch_bounds__(256) xface3_kernel(const Inst* insts, int ii, Params P,
+                                                     int stage, int parity) {
+  using St = Stage<3, NM, NS, T, C, 1, 1>;
+  using L = Lay<3, NM, NS>;
+  static_assert(St::XRUN + 1 == 256, "one face per thread");
+  __shared__ C fb[L::NQ * (St::XRUN + 1)];
+  const Inst& I = insts[ii];
+  typename St::Ctx cx;
+  double t, dtinv, dt;
+  if (!setup3<St, T, C>(I, P, stage, parity, cx, t, dtinv, dt)) return;
+  const int64_t b = xcd_block();
+  St::xrun_face(cx, (const C*)I.Wb, b, (int)threadIdx.x, fb);
+  __syncthreads();
+  St::xrun_cell(cx, (const C*)I.Wb, b, (int)threadIdx.x, fb, (C*)I.Acc);
+}
+
+// y- and z-faces: a thread walks a run of MARCH cells along A (the direction
+// is a template argument: every per-direction index in the face computation
+// is then a constant; a runtime direction would put those arrays in scratch
+// memory)
 template <int NM, int NS, class T, class C, int A>
-__global__ void __launch_bounds__(256) face3_kernel(const Inst* insts, int ii, Params P,
-                                                    int stage, int parity) {
-  constexpr int a = A;
+__global__ void __launch_bounds__(256) march3_kernel(const Inst* insts, int ii, Params P,
+                                                     int stage, int parity) {
   using St = Stage<3, NM, NS, T, C, 1, 1>;
   const Inst& I = insts[ii];
   typename St::Ctx cx;
   double t, dtinv, dt;
   if (!setup3<St, T, C>(I, P, stage, parity, cx, t, dtinv, dt)) return;
-  const int64_t nf = nfaces3(I, a);
-  const int nx = I.n[0], ny = I.n[1], nz = I.n[2];
-  int c[3], i;
-  int64_t f;
-  if constexpr (a == 0) {
-    // x-faces: rows of consecutive faces
-    f = xcd_block() * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
-    i = (int)(f % (nx + 1));
-    const int64_t r = f / (nx + 1);
-    c[1] = (int)(r % ny);
-    c[2] = (int)(r / ny);
-    c[0] = 0;
-  } else if constexpr (a == 1) {
-    // y-faces: bricks over (x, z), stepping along y
-    if (!brick_pos(xcd_block(), nx, nz, ny + 1, c[0], c[2], i)) return;
-    c[1] = 0;
-    f = ((int64_t)c[2] * (ny + 1) + i) * nx + c[0];
-  } else {
-    // z-faces: bricks over (x, y), stepping along z
-    if (!brick_pos(xcd_block(), nx, ny, nz + 1, c[0], c[1], i)) return;
-    c[2] = 0;
-    f = ((int64_t)i * ny + c[1]) * nx + c[0];
-  }
-  // the face lies between cells i - 1 and i along a; stencil i - 2 .. i + 1
-  int64_t st[4];
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    int cc[3] = {c[0], c[1], c[2]};
-    cc[a] = St::map_index(i - 2 + s, I.n[a], I.bc[a][0], I.bc[a][1]);
-    st[s] = ((int64_t)cc[2] * ny + cc[1]) * nx + cc[0];
-  }
-  const int64_t bslot = a == 0 ? (int64_t)c[2] * ny + c[1]
-                                : (a == 1 ? (int64_t)c[2] * nx + c[0] : (int64_t)c[1] * nx + c[0]);
-  St::template compute_face<int64_t>(cx, (const C*)I.Wb, I.ncell, a, st[0], st[1], st[2], st[3],
-                                     i, f, nf, bslot, (C*)I.Fb[a]);
+  int x, u, s;
+  if (!brick_pos(xcd_block(), (int)threadIdx.x, I.n[0], A == 1 ? I.n[2] : I.n[1],
+                 St::march_runs(I, A), x, u, s))
+    return;
+  St::march_cells(cx, (const C*)I.Wb, A, x, u, s, (C*)I.Acc);
 }
 
 template <int NM, int NS, class T, class C>
 __global__ void __launch_bounds__(256) finish3_kernel(const Inst* insts, int ii, Params P,
                                                       int stage, int parity) {
   using St = Stage<3, NM, NS, T, C, 1, 1>;
-  using L = Lay<3, NM, NS>;
   __shared__ double scratch[4];
   const Inst& I = insts[ii];
   typename St::Ctx cx;
@@ -464,39 +429,11 @@ __global__ void __launch_bounds__(256) finish3_kernel(const Inst* insts, int ii,
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double cflv = 0.0;
   if (go && g < I.ncell) {
-    const C* W = (const C*)I.Wb;
+    const C* accb = (const C*)I.Acc;
     const int64_t nc = I.ncell;
-    C Xc[3], uc[3], phic[NM];
-    C Vc[3][3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      Xc[k] = W[(L::W_X + k) * nc + g];
-      uc[k] = W[(L::R_U + k) * nc + g];
-    }
-#pragma unroll
-    for (int l = 0; l < NM; ++l) phic[l] = W[(L::R_PHI + l) * nc + g];
-#pragma unroll
-    for (int qv = 0; qv < L::NV; ++qv) Vc[vb_i<3>(qv)][vb_j<3>(qv)] = W[(L::R_V + qv) * nc + g];
-    const int nx = I.n[0], ny = I.n[1];
-    const int x = (int)(g % nx);
-    const int64_t r = g / nx;
-    const int y = (int)(r % ny);
-    const int z = (int)(r / ny);
     C acc[St::S];
 #pragma unroll
-    for (int f = 0; f < St::S; ++f) acc[f] = 0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      int64_t fm, fp;
-      if (a == 0) { fm = ((int64_t)z * ny + y) * (nx + 1) + x; fp = fm + 1; }
-      else if (a == 1) { fm = ((int64_t)z * (ny + 1) + y) * nx + x; fp = fm + nx; }
-      else { fm = g; fp = g + (int64_t)nx * ny; }
-      const int64_t nf = nfaces3(I, a);
-      typename St::FaceC m, p;
-      St::template face_contrib<int64_t>((const C*)I.Fb[a], fm, nf, a, 1, Xc, Vc, uc, m);
-      St::template face_contrib<int64_t>((const C*)I.Fb[a], fp, nf, a, 0, Xc, Vc, uc, p);
-      St::gather_dir(cx, a, m, p, Xc, uc, phic, Vc, acc);
-    }
+    for (int f = 0; f < St::S; ++f) acc[f] = accb[f * nc + g];
     bool bad = false;
     cflv = St::finish_cell(cx, g, acc, &bad);
     if (bad) atomicOr(reinterpret_cast<unsigned int*>(&I.dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);

@@ -134,16 +134,16 @@ Ops make_ops3() {
       const unsigned nbc = (unsigned)((I.ncell + 255) / 256);
       hipLaunchKernelGGL((prim3_kernel<NM, NS, T, C>), dim3(nbc), dim3(256), 0, s, c->insts_d, ii,
                          c->P, stage, parity);
+      using St = Stage<3, NM, NS, T, C, 1, 1>;
       const int nx = I.n[0], ny = I.n[1], nz = I.n[2];
-      const int64_t nf0 = I.ncell / nx * (nx + 1);
-      hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 0>), dim3((unsigned)((nf0 + 255) / 256)),
+      hipLaunchKernelGGL((xface3_kernel<NM, NS, T, C>), dim3((unsigned)St::xrun_count(I)),
                          dim3(256), 0, s, c->insts_d, ii, c->P, stage, parity);
-      hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 1>),
-                         dim3((unsigned)brick_blocks(nx, nz, ny + 1)), dim3(256), 0, s,
-                         c->insts_d, ii, c->P, stage, parity);
-      hipLaunchKernelGGL((face3_kernel<NM, NS, T, C, 2>),
-                         dim3((unsigned)brick_blocks(nx, ny, nz + 1)), dim3(256), 0, s,
-                         c->insts_d, ii, c->P, stage, parity);
+      hipLaunchKernelGGL((march3_kernel<NM, NS, T, C, 1>),
+                         dim3((unsigned)brick_blocks(nx, nz, St::march_runs(I, 1))), dim3(256),
+                         0, s, c->insts_d, ii, c->P, stage, parity);
+      hipLaunchKernelGGL((march3_kernel<NM, NS, T, C, 2>),
+                         dim3((unsigned)brick_blocks(nx, ny, St::march_runs(I, 2))), dim3(256),
+                         0, s, c->insts_d, ii, c->P, stage, parity);
       hipLaunchKernelGGL((finish3_kernel<NM, NS, T, C>), dim3(nbc), dim3(256), 0, s, c->insts_d,
                          ii, c->P, stage, parity);
     }

@@ -26,6 +26,28 @@ enum { BC_TRANSMISSIVE = 0, BC_FREE = 1, BC_PERIODIC = 2 };
 constexpr double TIE_REL64 = 1.0e-12;
 constexpr double TIE_REL32 = 1.0e-6;
 
+// Brick traversal of the 3D y- and z-face passes: a block of 256 threads
+// covers 64 positions along x by 4 along the other transverse direction, and
+// consecutive block numbers step along the face direction first, so the cell
+// planes a brick's stencil reaches are still in the XCD's L2 for the next
+// block (a 256^2 plane of primitives is larger than one XCD's L2).
+constexpr int BRX = 64, BRY = 4;
+FV_HD int64_t brick_blocks(int n_t, int n_u, int n_s) {
+  // n_t: cells along x, n_u: along the other transverse direction,
+  // n_s: positions along the stepping direction
+  return (int64_t)((n_t + BRX - 1) / BRX) * ((n_u + BRY - 1) / BRY) * n_s;
+}
+// position of thread tid of brick block b: x, transverse u, step s;
+// false past the domain
+FV_HD bool brick_pos(int64_t b, int tid, int n_t, int n_u, int n_s, int& x, int& u, int& s) {
+  s = (int)(b % n_s);
+  const int64_t br = b / n_s;
+  const int nbx = (n_t + BRX - 1) / BRX;
+  x = (int)(br % nbx) * BRX + tid % BRX;
+  u = (int)(br / nbx) * BRY + tid / BRX;
+  return x < n_t && u < n_u;
+}
+
 // Per-instance descriptor (device memory).
 struct Inst {
   void* U;          // state (caller-owned), in/out
@@ -34,7 +56,7 @@ struct Inst {
   const void* phi0; // perturbation field on the initial mesh
   double* bacc;     // outward boundary flux accumulators
   void* Wb;         // 3D: primitives of every cell (workspace)
-  void* Fb[3];      // 3D: face data of each direction (workspace)
+  void* Acc;        // 3D: per-cell divergence summed by the face passes (workspace)
   double* dts;      // dt state, see DTS_* below
   int n[3];
   int tiles[3];
@@ -795,6 +817,118 @@ struct Stage {
       const C beta = (p.row[j] - m.row[j]) * inv;
       acc[L::VB + q] += -(p.Vfl[q] - m.Vfl[q]) * inv + (C)(2.0 / 3.0) * Vc[i][j] * div - uc[i] * beta;
     }
+  }
+
+  // ------------------------------------------------------- 3D face passes
+  // The 3D stage takes its faces direction by direction from the primitives
+  // of every cell (W, stride ncell) and sums each cell's divergence in Acc
+  // (S fields, stride ncell); no face data goes through HBM.  Each face is
+  // computed once (x) or once plus one face per run of MARCH cells (y, z).
+  //
+  // x: the faces in row order (f = row * (nx + 1) + i), in runs of XRUN + 1
+  // faces that overlap by one, so that both faces of every cell fall in one
+  // run.  Phase 1: face f = b * XRUN + t into slot t of fb (stride XRUN + 1).
+  static constexpr int XRUN = 255;
+  FV_HD static int64_t xrun_count(const Inst& I) {
+    const int64_t nf = I.ncell / I.n[0] * (I.n[0] + 1);
+    return (nf - 1 + XRUN - 1) / XRUN;
+  }
+  FV_HD static void xrun_face(const Ctx& cx, const C* W, int64_t b, int t, C* fb) {
+    const Inst& I = *cx.I;
+    const int nx = I.n[0];
+    const int64_t nf = I.ncell / nx * (nx + 1);
+    const int64_t f = b * XRUN + t;
+    if (t > XRUN || f >= nf) return;
+    const int i = (int)(f % (nx + 1));
+    const int64_t row = f / (nx + 1);
+    int64_t st[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      st[k] = row * nx + map_index(i - 2 + k, nx, I.bc[0][0], I.bc[0][1]);
+    compute_face<int64_t>(cx, W, I.ncell, 0, st[0], st[1], st[2], st[3], i, (int64_t)t,
+                          (int64_t)(XRUN + 1), row, fb);
+  }
+  // Phase 2: the cell between faces t and t + 1 of run b, if they bound one;
+  // its x divergence starts its sum in Acc.
+  FV_HD static void xrun_cell(const Ctx& cx, const C* W, int64_t b, int t, const C* fb,
+                              C* accb) {
+    const Inst& I = *cx.I;
+    const int nx = I.n[0];
+    const int64_t nc = I.ncell;
+    const int64_t nf = nc / nx * (nx + 1);
+    const int64_t f = b * XRUN + t;
+    if (t >= XRUN || f + 1 >= nf) return;
+    const int i = (int)(f % (nx + 1));
+    if (i == nx) return;
+    const int64_t g = f / (nx + 1) * nx + i;
+    C Xc[3], uc[3], phic[NM];
+    C Vc[3][3];
+    own_values(W, nc, g, Xc, uc, phic, Vc);
+    FaceC m, p;
+    face_contrib<int>(fb, t, XRUN + 1, 0, 1, Xc, Vc, uc, m);
+    face_contrib<int>(fb, t + 1, XRUN + 1, 0, 0, Xc, Vc, uc, p);
+    C acc[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) acc[q] = 0;
+    gather_dir(cx, 0, m, p, Xc, uc, phic, Vc, acc);
+#pragma unroll
+    for (int q = 0; q < S; ++q) accb[q * nc + g] = acc[q];
+  }
+
+  // y, z: one thread per transverse position (x, u) (u = z for y, y for z)
+  // and run s of MARCH cells along a.  It walks the faces s * MARCH ..
+  // min(s * MARCH + MARCH, n_a) in order, keeping the lower face's record,
+  // and adds each cell's divergence along a to its sum in Acc.
+  static constexpr int MARCH = 16;
+  FV_HD static int march_runs(const Inst& I, int a) { return (I.n[a] + MARCH - 1) / MARCH; }
+  FV_HD static void march_cells(const Ctx& cx, const C* W, int a, int x, int u, int s, C* accb) {
+    const Inst& I = *cx.I;
+    const int nx = I.n[0], ny = I.n[1], na = I.n[a];
+    const int64_t nc = I.ncell;
+    const int i0 = s * MARCH, i1 = m_min(i0 + MARCH, na);
+    const int64_t sa = a == 1 ? (int64_t)nx : (int64_t)nx * ny;
+    const int64_t g0 = a == 1 ? (int64_t)u * nx * ny + x : (int64_t)u * nx + x;
+    const int64_t bslot = (int64_t)u * nx + x;
+    C lo[L::NQ], up[L::NQ];
+    for (int i = i0; i <= i1; ++i) {
+      int64_t st[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        st[k] = g0 + (int64_t)map_index(i - 2 + k, na, I.bc[a][0], I.bc[a][1]) * sa;
+      compute_face<int64_t>(cx, W, nc, a, st[0], st[1], st[2], st[3], i, (int64_t)0, (int64_t)1,
+                            bslot, up);
+      if (i > i0) {
+        const int64_t g = g0 + (int64_t)(i - 1) * sa;
+        C Xc[3], uc[3], phic[NM];
+        C Vc[3][3];
+        own_values(W, nc, g, Xc, uc, phic, Vc);
+        FaceC m, p;
+        face_contrib<int>(lo, 0, 1, a, 1, Xc, Vc, uc, m);
+        face_contrib<int>(up, 0, 1, a, 0, Xc, Vc, uc, p);
+        C acc[S];
+#pragma unroll
+        for (int q = 0; q < S; ++q) acc[q] = accb[q * nc + g];
+        gather_dir(cx, a, m, p, Xc, uc, phic, Vc, acc);
+#pragma unroll
+        for (int q = 0; q < S; ++q) accb[q * nc + g] = acc[q];
+      }
+#pragma unroll
+      for (int q = 0; q < L::NQ; ++q) lo[q] = up[q];
+    }
+  }
+
+  // the centre values a cell's gather takes from the 3D primitives
+  FV_HD static void own_values(const C* W, int64_t nc, int64_t g, C* Xc, C* uc, C* phic,
+                               C Vc[3][3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      Xc[k] = W[(L::W_X + k) * nc + g];
+      uc[k] = W[(L::R_U + k) * nc + g];
+    }
+#pragma unroll
+    for (int l = 0; l < NM; ++l) phic[l] = W[(L::R_PHI + l) * nc + g];
+#pragma unroll
+    for (int q = 0; q < L::NV; ++q) Vc[vb_i<3>(q)][vb_j<3>(q)] = W[(L::R_V + q) * nc + g];
   }
 
   // ---------------------------------------------------------------- phase 4

@@ -70,7 +70,7 @@ struct Run {
   Params P;
   Inst I;
   int64_t nc = 0;
-  std::vector<double> U, U1, U2, phi0, bacc, dts, Wb, Fb[3];
+  std::vector<double> U, U1, U2, phi0, bacc, dts, Wb, Acc;
 };
 
 template <int DIM, int NM, int NS>
@@ -111,10 +111,8 @@ static void setup(Run& r, const fv_grid* g, const fv_material* mats, const fv_op
   r.I.dts = r.dts.data();
   if (DIM == 3) {
     r.Wb.assign(L::NW * r.nc, NAN);
-    for (int a = 0; a < 3; ++a) {
-      r.Fb[a].assign(L::NQ * (r.nc / g->n[a] * (g->n[a] + 1)), NAN);
-      r.I.Fb[a] = r.Fb[a].data();
-    }
+    r.Acc.assign(L::S * r.nc, NAN);
+    r.I.Acc = r.Acc.data();
     r.I.Wb = r.Wb.data();
   }
   double m = 0.0;
@@ -232,37 +230,18 @@ static void step_tiles(Run& r, int nsteps) {
   }
 }
 
-// face index f of direction a -> transverse cell (c with c[a] = 0) and the
-// face's position i along a, in the order the 3D face pass stores faces
-static void face_pos(int a, int64_t f, int nx, int ny, int c[3], int& i) {
-  c[0] = c[1] = c[2] = 0;
-  if (a == 0) {
-    i = (int)(f % (nx + 1));
-    const int64_t t = f / (nx + 1);
-    c[1] = (int)(t % ny);
-    c[2] = (int)(t / ny);
-  } else if (a == 1) {
-    c[0] = (int)(f % nx);
-    const int64_t t = f / nx;
-    i = (int)(t % (ny + 1));
-    c[2] = (int)(t / (ny + 1));
-  } else {
-    c[0] = (int)(f % nx);
-    const int64_t t = f / nx;
-    c[1] = (int)(t % ny);
-    i = (int)(t / ny);
-  }
-}
-
+// The 3D stage as the device runs it: primitives of every cell, the x-face
+// runs through a block-sized buffer (the kernel's LDS), the y and z marches
+// over the bricks of their launches, then the per-cell update from the sums.
 template <int NM, int NS>
 static void step_3d(Run& r, int nsteps) {
   using St = Stage<3, NM, NS, double, double, 1, 1>;
   using L = Lay<3, NM, NS>;
   const int64_t nc = r.nc;
-  const int nx = r.I.n[0], ny = r.I.n[1];
-  int64_t nf[3];
-  for (int a = 0; a < 3; ++a) nf[a] = nc / r.I.n[a] * (r.I.n[a] + 1);
+  const int nx = r.I.n[0], ny = r.I.n[1], nz = r.I.n[2];
   double* Wb = r.Wb.data();
+  double* Ab = r.Acc.data();
+  std::vector<double> fb((size_t)L::NQ * (St::XRUN + 1));
   for (int s = 0; s < nsteps; ++s) {
     const int q = s & 1;
     for (int stage = 1; stage <= 3; ++stage) {
@@ -270,56 +249,30 @@ static void step_3d(Run& r, int nsteps) {
       typename St::Ctx cx;
       init_ctx(cx, r, stage, q, dt);
       for (int64_t g = 0; g < nc; ++g) St::template cell_prims<int64_t>(cx, g, Wb, nc, g);
-      for (int a = 0; a < 3; ++a)
-        for (int64_t f = 0; f < nf[a]; ++f) {
-          int c[3], i;
-          face_pos(a, f, nx, ny, c, i);
-          assert(i >= 0 && i <= r.I.n[a]);
-          int64_t st[4];
-          for (int k = 0; k < 4; ++k) {
-            int cc[3] = {c[0], c[1], c[2]};
-            cc[a] = St::map_index(i - 2 + k, r.I.n[a], r.I.bc[a][0], r.I.bc[a][1]);
-            for (int d = 0; d < 3; ++d) assert(cc[d] >= 0 && cc[d] < r.I.n[d]);
-            st[k] = ((int64_t)cc[2] * ny + cc[1]) * nx + cc[0];
+      std::fill(r.Acc.begin(), r.Acc.end(), NAN);
+      const int64_t nb = St::xrun_count(r.I);
+      for (int64_t b = 0; b < nb; ++b) {
+        std::fill(fb.begin(), fb.end(), NAN);
+        for (int t = 0; t < St::XRUN + 1; ++t) St::xrun_face(cx, Wb, b, t, fb.data());
+        for (int t = 0; t < St::XRUN + 1; ++t) St::xrun_cell(cx, Wb, b, t, fb.data(), Ab);
+      }
+      // the x pass starts every cell's sum
+      for (size_t k = 0; k < r.Acc.size(); ++k) assert(!std::isnan(Ab[k]));
+      for (int a = 1; a <= 2; ++a) {
+        const int nu = a == 1 ? nz : ny, ns = St::march_runs(r.I, a);
+        const int64_t nbb = brick_blocks(nx, nu, ns);
+        for (int64_t b = 0; b < nbb; ++b)
+          for (int tid = 0; tid < 256; ++tid) {
+            int x, u, sr;
+            if (!brick_pos(b, tid, nx, nu, ns, x, u, sr)) continue;
+            assert(x >= 0 && x < nx && u >= 0 && u < nu && sr >= 0 && sr < ns);
+            St::march_cells(cx, Wb, a, x, u, sr, Ab);
           }
-          const int64_t bslot = a == 0 ? (int64_t)c[2] * ny + c[1]
-                                       : (a == 1 ? (int64_t)c[2] * nx + c[0]
-                                                 : (int64_t)c[1] * nx + c[0]);
-          assert(bslot >= 0 && bslot < nc / r.I.n[a]);
-          St::template compute_face<int64_t>(cx, Wb, nc, a, st[0], st[1], st[2], st[3], i, f,
-                                             nf[a], bslot, r.Fb[a].data());
-        }
+      }
       double bmax = 0.0;
       for (int64_t g = 0; g < nc; ++g) {
-        double Xc[3], uc[3], phic[NM], Vc[3][3];
-        for (int k = 0; k < 3; ++k) {
-          Xc[k] = Wb[(L::W_X + k) * nc + g];
-          uc[k] = Wb[(L::R_U + k) * nc + g];
-        }
-        for (int l = 0; l < NM; ++l) phic[l] = Wb[(L::R_PHI + l) * nc + g];
-        for (int v = 0; v < L::NV; ++v) Vc[vb_i<3>(v)][vb_j<3>(v)] = Wb[(L::R_V + v) * nc + g];
-        const int x = (int)(g % nx);
-        const int64_t t = g / nx;
-        const int y = (int)(t % ny), z = (int)(t / ny);
-        double acc[L::S] = {};
-        for (int a = 0; a < 3; ++a) {
-          int64_t fm, fp;
-          if (a == 0) {
-            fm = ((int64_t)z * ny + y) * (nx + 1) + x;
-            fp = fm + 1;
-          } else if (a == 1) {
-            fm = ((int64_t)z * (ny + 1) + y) * nx + x;
-            fp = fm + nx;
-          } else {
-            fm = g;
-            fp = g + (int64_t)nx * ny;
-          }
-          assert(fm >= 0 && fp < nf[a]);
-          typename St::FaceC mf, pf;
-          St::template face_contrib<int64_t>(r.Fb[a].data(), fm, nf[a], a, 1, Xc, Vc, uc, mf);
-          St::template face_contrib<int64_t>(r.Fb[a].data(), fp, nf[a], a, 0, Xc, Vc, uc, pf);
-          St::gather_dir(cx, a, mf, pf, Xc, uc, phic, Vc, acc);
-        }
+        double acc[L::S];
+        for (int f = 0; f < L::S; ++f) acc[f] = Ab[(size_t)f * nc + g];
         bool bad = false;
         bmax = std::max(bmax, St::finish_cell(cx, g, acc, &bad));
         if (bad) r.dts[DTS_FLAG] = 1.0;

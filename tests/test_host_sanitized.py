@@ -94,7 +94,7 @@ def _assert_matches_oracle(case, steps, t, flag, U, L):
 @pytest.mark.parametrize("which,steps", [
     ("spall1d", 12), ("ring2d", 4), ("ring2d_wide", 3), ("ring2d_spare", 3),
     ("ring2d_spare14", 3),
-    ("shell3d", 2),
+    ("shell3d", 2), ("shell3d_runs", 1),
     ("impact3d", 2), ("disk2d", 40), ("alcube1d", 120), ("alcube2d", 30),
     ("disk2d_jc", 30), ("ring2d_thinc", 6), ("spall1d_thinc", 40),
     ("unb2d", 6), ("unb3d", 4)])
@@ -115,6 +115,10 @@ def test_phase_functions_sanitized_match_oracle(exe, tmp_path, which, steps):
         tile_x = 14
     elif which == "shell3d":
         case = F.make_case(3, n=10)
+    elif which == "shell3d_runs":
+        # x-face runs across rows, three marching runs along y and z with a
+        # ragged last one
+        case = F.make_case(3, n=34)
     elif which == "disk2d":
         case = F.expanding_disk(20)            # void around the disk: seeding
     elif which == "alcube1d":
