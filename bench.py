@@ -373,7 +373,7 @@ def _kernel_key(name):
     return n.strip()
 
 
-STAGE_PASSES = ("stage_kernel", "prim3_kernel", "face3_kernel", "finish3_kernel")
+STAGE_PASSES = ("stage_kernel", "prim3_kernel", "xface3_kernel", "march3_kernel", "finish3_kernel")
 
 
 def _median(v):
