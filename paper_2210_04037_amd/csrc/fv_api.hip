@@ -89,10 +89,25 @@ static int hip_check(fv_ctx* c, hipError_t e, const char* what) {
 // Every compiled tile shape of the kernel set for this combination, the
 // default first.  set_attr: also raise each kernel's dynamic LDS limit (a HIP
 // runtime call; size-only queries skip it so that they run without a device)
-static bool select_ops(int dim, int nm, int ns, int prec, std::vector<Ops>& vars,
+static bool select_ops(int dim, int nm, int ns, bool ext, int prec, std::vector<Ops>& vars,
                        hipError_t& herr, bool set_attr = true) {
-  if (prec == FV_FP32_BULK) return select_ops_fp32(dim, nm, ns, vars, herr, set_attr);
-  return select_ops_fp64(dim, nm, ns, vars, herr, set_attr);
+  if (prec == FV_FP32_BULK) return select_ops_fp32(dim, nm, ns, ext, vars, herr, set_attr);
+  return select_ops_fp64(dim, nm, ns, ext, vars, herr, set_attr);
+}
+
+// Does the run need the kernels with the extended closures (a Johnson-Cook,
+// Steinberg, Burakovsky-Preston or simplified-damage row, THINC or the
+// driver)?  Runs without them take the build whose branches are compiled
+// out (the same results).
+static bool needs_ext(int n_mat, const fv_material* mats, const fv_options* opt) {
+  bool e = opt->thinc_beta > 0.0 || opt->driver[5] > 0.0;
+  for (int l = 0; l < n_mat; ++l) {
+    const fv_material& m = mats[l];
+    if (m.kind != FV_MAT_SOLID) continue;
+    e = e || m.jc_B != 0.0 || m.jc_C != 0.0 || m.T_melt > 0.0 || m.G_p > 0.0 ||
+        m.Gamma1 != 0.0 || m.Gamma2 != 0.0 || m.Ddot0 > 0.0;
+  }
+  return e;
 }
 
 // index of the tile shape asked for in the options (0, 0: the default)
@@ -380,7 +395,9 @@ size_t fv_workspace_bytes(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
   if (validate(n_inst, grids, n_mat, mats, opt, ns, msg) != FV_OK) return 0;
   std::vector<Ops> vars;
   hipError_t he;
-  if (!select_ops(grids[0].dim, n_mat, ns, opt->precision, vars, he, false)) return 0;
+  if (!select_ops(grids[0].dim, n_mat, ns, needs_ext(n_mat, mats, opt), opt->precision, vars,
+                  he, false))
+    return 0;
   if (pick_variant(vars, opt) < 0) return 0;
   WsPlan W;
   plan_ws(n_inst, grids, vars, W);
@@ -410,7 +427,8 @@ int32_t fv_init(fv_ctx** out, int32_t n_inst, const fv_grid* grids, int32_t n_ma
   c->precision = opt->precision;
   c->stream = (hipStream_t)stream;
   hipError_t he;
-  if (!select_ops(c->dim, n_mat, ns, opt->precision, c->vars, he)) {
+  if (!select_ops(c->dim, n_mat, ns, needs_ext(n_mat, mats, opt), opt->precision, c->vars,
+                  he)) {
     delete c;
     return fail(nullptr, FV_EINVAL, "unsupported dimension/material/precision combination");
   }

@@ -244,10 +244,12 @@ struct RefT { C rho_eref, pref, rho_dpref, G, invG, g1; };
 // derivatives, rho G' = Gp eta^(-1/3)(rho p_c' - p_c/3) and
 // rho^2 G'' = Gp eta^(-1/3)(rho^2 p_c'' - (2/3) rho p_c' + (4/9) p_c), with
 // rho^2 p_c'' = (K0/a) eta^(a+1) ((2a+1) 2a eta^a - (a+1) a).
-template <class C>
+// EXT false: a build for materials without the Steinberg, Burakovsky-Preston,
+// Johnson-Cook and simplified-damage rows (their branches compiled out).
+template <class C, bool EXT = true>
 FV_HD void shear_terms(const MatP& m, C eta, C ea, C ea1, C pc, C rho_dpc, C* G, C* rG1,
                        C* r2G2) {
-  if (!m.stein) {
+  if (!EXT || !m.stein) {
     const C b = cst<C>(m.beta, m.f_beta);
     const C Gt = cst<C>(m.G0, m.f_G0) * powi_or(eta, b + (C)1, m.beta1_i);
     *G = Gt;
@@ -265,7 +267,7 @@ FV_HD void shear_terms(const MatP& m, C eta, C ea, C ea1, C pc, C rho_dpc, C* G,
   *r2G2 = Gp * e3 * (r2 - (C)(2.0 / 3.0) * rho_dpc + (C)(4.0 / 9.0) * pc);
 }
 
-template <class C>
+template <class C, bool EXT = true>
 FV_HD RefT<C> solid_ref_terms(const MatP& m, C rho, C J2, C D) {
   RefT<C> r;
   const C a = cst<C>(m.alpha, m.f_alpha);
@@ -278,7 +280,7 @@ FV_HD RefT<C> solid_ref_terms(const MatP& m, C rho, C J2, C D) {
   const C pc = K0 / a * ea1 * (ea - (C)1);
   const C rho_dpc = K0 / a * ea1 * (((C)2 * a + (C)1) * ea - (a + (C)1));
   C Gt, rG1, r2G2;
-  shear_terms<C>(m, eta, ea, ea1, pc, rho_dpc, &Gt, &rG1, &r2G2);
+  shear_terms<C, EXT>(m, eta, ea, ea1, pc, rho_dpc, &Gt, &rG1, &r2G2);
   const C w = (C)1 - D;
   r.rho_eref = w * (rho_ec + Gt * J2);
   r.pref = w * (pc + (rG1 - Gt) * J2);
@@ -287,9 +289,9 @@ FV_HD RefT<C> solid_ref_terms(const MatP& m, C rho, C J2, C D) {
   return r;
 }
 
-template <class C>
+template <class C, bool EXT = true>
 FV_HD C shear_modulus_undamaged(const MatP& m, C rho) {
-  if (!m.stein)
+  if (!EXT || !m.stein)
     return cst<C>(m.G0, m.f_G0) *
            powi_or(rho / cst<C>(m.rho0, m.f_rho0), cst<C>(m.beta, m.f_beta) + (C)1, m.beta1_i);
   const C a = cst<C>(m.alpha, m.f_alpha);
@@ -303,9 +305,9 @@ FV_HD C shear_modulus_undamaged(const MatP& m, C rho) {
 // its reference terms (constants unless Burakovsky-Preston:
 // Gamma = Gamma0 + G1 eta^(-1/3) + G2 eta^(-gbp),
 // rho Gamma' = -G1 eta^(-1/3)/3 - gbp G2 eta^(-gbp)).
-template <class C>
+template <class C, bool EXT = true>
 FV_HD void gamma_terms(const MatP& m, C rho, RefT<C>& t) {
-  if (!m.bp) {
+  if (!EXT || !m.bp) {
     t.invG = cst<C>(m.invGamma, m.f_invGamma);
     t.g1 = cst<C>(m.Gamma0, m.f_Gamma0) + (C)1;
     return;
@@ -351,7 +353,7 @@ FV_HD C closure_density(const MatP& m, C phi_l, C rho_l) {
   return phi_l < (C)PHI_TRACE ? cst<C>(m.rho0, m.f_rho0) : rho_l;
 }
 
-template <int NM, int NS, class C>
+template <int NM, int NS, class C, bool EXT = true>
 FV_HD void mix_terms(const Params& P, const C* phi, const C* rho_l, const C* D,
                      C J2, Mix<NM, NS, C>& mx) {
   mx.xi = 0;
@@ -359,12 +361,13 @@ FV_HD void mix_terms(const Params& P, const C* phi, const C* rho_l, const C* D,
   for (int l = 0; l < NM; ++l) {
     const bool live = l < NS && phi[l] >= (C)PHI_TRACE;
     if (live) {
-      mx.t[l] = solid_ref_terms<C>(P.mat[l], rho_l[l], J2, D[l < NS ? l : 0]);
+      mx.t[l] = solid_ref_terms<C, EXT>(P.mat[l], rho_l[l], J2, D[l < NS ? l : 0]);
     } else {
       mx.t[l].rho_eref = 0; mx.t[l].pref = 0; mx.t[l].rho_dpref = 0; mx.t[l].G = 0;
     }
     // a trace takes its Grueneisen function at the reference density
-    gamma_terms<C>(P.mat[l], live ? rho_l[l] : cst<C>(P.mat[l].rho0, P.mat[l].f_rho0), mx.t[l]);
+    gamma_terms<C, EXT>(P.mat[l], live ? rho_l[l] : cst<C>(P.mat[l].rho0, P.mat[l].f_rho0),
+                        mx.t[l]);
     mx.xi += phi[l] * mx.t[l].invG;
   }
 }
@@ -785,18 +788,20 @@ FV_HD double bonora_rate(const MatP& m, double D, double eps, double R) {
 // classical RK4 in eps_p over [eps0, eps0 + h], every argument clamped
 // dD/deps: the Bonora rate, or Ddot0 (1 - D) for the simplified law of the
 // U-Nb ring (Section 4.3); zero once critical either way
+template <bool EXT = true>
 FV_HD double damage_rate(const MatP& m, double D, double eps, double R) {
-  if (m.Ddot0 > 0.0) return D >= m.Dcrit ? 0.0 : m.Ddot0 * (1.0 - D);
+  if (EXT && m.Ddot0 > 0.0) return D >= m.Dcrit ? 0.0 : m.Ddot0 * (1.0 - D);
   return bonora_rate(m, D, eps, R);
 }
 
+template <bool EXT = true>
 FV_HD double damage_rk4(const MatP& m, double D, double eps0, double h, double R) {
   const double Dc = m.Dcrit;
   auto cl = [Dc](double v) { return v < 0.0 ? 0.0 : (v > Dc ? Dc : v); };
-  const double k1 = damage_rate(m, D, eps0, R);
-  const double k2 = damage_rate(m, cl(D + 0.5 * h * k1), eps0 + 0.5 * h, R);
-  const double k3 = damage_rate(m, cl(D + 0.5 * h * k2), eps0 + 0.5 * h, R);
-  const double k4 = damage_rate(m, cl(D + h * k3), eps0 + h, R);
+  const double k1 = damage_rate<EXT>(m, D, eps0, R);
+  const double k2 = damage_rate<EXT>(m, cl(D + 0.5 * h * k1), eps0 + 0.5 * h, R);
+  const double k3 = damage_rate<EXT>(m, cl(D + 0.5 * h * k2), eps0 + 0.5 * h, R);
+  const double k4 = damage_rate<EXT>(m, cl(D + h * k3), eps0 + h, R);
   return cl(D + h / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4));
 }
 

@@ -7,7 +7,8 @@
 
 namespace fvk {
 
-bool select_ops_fp32(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t& herr,
+bool select_ops_fp32(int dim, int nm, int ns, bool ext, std::vector<Ops>& vars,
+                     hipError_t& herr,
                      bool set_attr) {
   herr = hipSuccess;
   vars.clear();

@@ -113,12 +113,12 @@ constexpr int stage_waves_per_eu() {
                                                                                           : 1;
 }
 
-template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH>
+template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH, int EXT>
 __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(
     stage_waves_per_eu<Stage<DIM, NM, NS, T, C, TX, TY, NTH>, DIM, C, NTH>())))
 stage_kernel(const Inst* __restrict__ insts, const int2* __restrict__ block_tab, Params P,
              int stage, int parity) {
-  using St = Stage<DIM, NM, NS, T, C, TX, TY, NTH>;
+  using St = Stage<DIM, NM, NS, T, C, TX, TY, NTH, EXT>;
   using TL = typename St::TL;
   constexpr int NT = NTH;
   extern __shared__ double smem_d[];

@@ -100,9 +100,9 @@ void common_ops(Ops& o) {
   };
 }
 
-template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH>
+template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH, int EXT>
 Ops make_ops() {
-  using St = Stage<DIM, NM, NS, T, C, TX, TY, NTH>;
+  using St = Stage<DIM, NM, NS, T, C, TX, TY, NTH, EXT>;
   Ops o;
   common_ops<DIM, NM, NS, T, C>(o);
   o.TX = TX;
@@ -110,7 +110,7 @@ Ops make_ops() {
   o.NT = NTH;
   o.smem = St::smem_bytes();
   o.stage = [](fv_ctx* c, int stage, int parity, hipStream_t s) {
-    hipLaunchKernelGGL((stage_kernel<DIM, NM, NS, T, C, TX, TY, NTH>), dim3(c->total_blocks),
+    hipLaunchKernelGGL((stage_kernel<DIM, NM, NS, T, C, TX, TY, NTH, EXT>), dim3(c->total_blocks),
                        dim3(NTH), St::smem_bytes(), s, c->insts_d,
                        c->n_inst == 1 ? (const int2*)nullptr : c->block_tab_d, c->P, stage,
                        parity);
@@ -151,21 +151,27 @@ Ops make_ops3() {
   return o;
 }
 
-template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH>
+template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH, int EXT>
 hipError_t set_smem_attr() {
-  using St = Stage<DIM, NM, NS, T, C, TX, TY, NTH>;
-  return hipFuncSetAttribute((const void*)&stage_kernel<DIM, NM, NS, T, C, TX, TY, NTH>,
+  using St = Stage<DIM, NM, NS, T, C, TX, TY, NTH, EXT>;
+  return hipFuncSetAttribute((const void*)&stage_kernel<DIM, NM, NS, T, C, TX, TY, NTH, EXT>,
                              hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)St::smem_bytes());
 }
 
 // one compiled tile shape of a kernel set (the first one listed is the
-// default); set_attr also raises the kernel's dynamic LDS limit, a runtime
+// default), in the build with the extended closures (ext) or the one
+// without; set_attr also raises the kernel's dynamic LDS limit, a runtime
 // call that size-only queries skip
-#define FV_VARN(D, M, S_, TT, CC, X, Y, N)                                 \
-  {                                                                        \
-    vars.push_back(make_ops<D, M, S_, TT, CC, X, Y, N>());                 \
-    if (set_attr && herr == hipSuccess) herr = set_smem_attr<D, M, S_, TT, CC, X, Y, N>(); \
+#define FV_VARN(D, M, S_, TT, CC, X, Y, N)                                          \
+  {                                                                                 \
+    if (ext) {                                                                      \
+      vars.push_back(make_ops<D, M, S_, TT, CC, X, Y, N, 1>());                     \
+      if (set_attr && herr == hipSuccess) herr = set_smem_attr<D, M, S_, TT, CC, X, Y, N, 1>(); \
+    } else {                                                                        \
+      vars.push_back(make_ops<D, M, S_, TT, CC, X, Y, N, 0>());                     \
+      if (set_attr && herr == hipSuccess) herr = set_smem_attr<D, M, S_, TT, CC, X, Y, N, 0>(); \
+    }                                                                               \
   }
 // a tile shape with one thread per interior cell
 #define FV_VAR(D, M, S_, TT, CC, X, Y) FV_VARN(D, M, S_, TT, CC, X, Y, (X) * (Y))
@@ -175,9 +181,11 @@ hipError_t set_smem_attr() {
 
 // kernel sets of each translation unit: every tile shape compiled for a
 // (dimension, materials, solids) combination
-bool select_ops_fp64(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t& herr,
-                     bool set_attr);
-bool select_ops_fp32(int dim, int nm, int ns, std::vector<Ops>& vars, hipError_t& herr,
-                     bool set_attr);
+// (ext: the run uses an extended closure, THINC or the driver; 1D and 2D
+// only, the 3D passes are built with them)
+bool select_ops_fp64(int dim, int nm, int ns, bool ext, std::vector<Ops>& vars,
+                     hipError_t& herr, bool set_attr);
+bool select_ops_fp32(int dim, int nm, int ns, bool ext, std::vector<Ops>& vars,
+                     hipError_t& herr, bool set_attr);
 
 }  // namespace fvk

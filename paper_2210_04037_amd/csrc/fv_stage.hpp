@@ -142,8 +142,13 @@ struct Tile {
   }
 };
 
-template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH = TX * TY>
+// EXT 0: the build for runs without the extended closures (Steinberg,
+// Burakovsky-Preston, Johnson-Cook, the simplified damage law), THINC and the
+// driver, whose branches are compiled out; results are the same bits.
+template <int DIM, int NM, int NS, class T, class C, int TX, int TY, int NTH = TX * TY,
+          int EXT = 1>
 struct Stage {
+  static constexpr bool kExt = EXT != 0;
   using L = Lay<DIM, NM, NS>;
   using TL = Tile<DIM, TX, TY, NTH>;
   static constexpr int S = L::S;
@@ -185,7 +190,7 @@ struct Stage {
 #pragma unroll
     for (int l = 0; l < NM; ++l) {
       rho += m_max((double)U[L::MASS + l], 0.0);
-      xi += (double)U[L::PHI + l] * (P.mat[l].bp ? (double)mx.t[l].invG : P.mat[l].invGamma);
+      xi += (double)U[L::PHI + l] * (kExt && P.mat[l].bp ? (double)mx.t[l].invG : P.mat[l].invGamma);
     }
     double m2 = 0;
 #pragma unroll
@@ -196,7 +201,7 @@ struct Stage {
       const double ph = (double)U[L::PHI + l];
       th = th - ph * (double)mx.t[l].rho_eref;
       cold = cold + ph * (double)mx.t[l].pref *
-                        (P.mat[l].bp ? (double)mx.t[l].invG : P.mat[l].invGamma);
+                        (kExt && P.mat[l].bp ? (double)mx.t[l].invG : P.mat[l].invGamma);
     }
     return (C)((m_max(th, 0.0) + cold) / xi);
   }
@@ -301,7 +306,7 @@ struct Stage {
     hencky<DIM, C>(V, H);
     const C J2 = J2_of<DIM, C>(H);
     Mix<NM, NS, C> mx;
-    mix_terms<NM, NS, C>(cx.P, phi, rho_l, D, J2, mx);
+    mix_terms<NM, NS, C, kExt>(cx.P, phi, rho_l, D, J2, mx);
     C p;
     bool island = false;
     if (sizeof(C) == 4) {
@@ -376,7 +381,7 @@ struct Stage {
     // face EOS: energy from the reconstructed pressure
     const C J2 = J2_of<DIM, C>(s.H);
     Mix<NM, NS, C> mx;
-    mix_terms<NM, NS, C>(P, s.phi, s.rho_l, s.D, J2, mx);
+    mix_terms<NM, NS, C, kExt>(P, s.phi, s.rho_l, s.D, J2, mx);
     C rho = 0;
 #pragma unroll
     for (int l = 0; l < NM; ++l) rho += s.phi[l] * s.rho_l[l];
@@ -456,7 +461,7 @@ struct Stage {
     }
     // THINC sharpening of the volume fractions (the first NM rows): the
     // upper face of the cell below and the lower face of the cell above
-    if (P.thinc_beta > 0.0) {
+    if (kExt && P.thinc_beta > 0.0) {
       const C beta = cst<C>(P.thinc_beta, P.f_thinc_beta);
       const C tb = cst<C>(P.thinc_tb, P.f_thinc_tb), sh = cst<C>(P.thinc_sech, P.f_thinc_sech);
 #pragma unroll
@@ -1087,7 +1092,7 @@ struct Stage {
       }
       const double J2 = J2_of<DIM, double>(H);
       Mix<NM, NS, double> mx;
-      mix_terms<NM, NS, double>(P, phi, rho_l, D, J2, mx);
+      mix_terms<NM, NS, double, kExt>(P, phi, rho_l, D, J2, mx);
       const double p = mix_pressure<NM, NS, double>(P, phi, mx, rho_e);
       double X[3] = {0, 0, 0};
 #pragma unroll
@@ -1103,10 +1108,10 @@ struct Stage {
         const MatP& m = P.mat[s];
         if (!(phi[s] >= PHI_TRACE)) continue;
         const double w = 1.0 - D[s];
-        Gm += phi[s] * w * shear_modulus_undamaged<double>(m, rho_l[s]);
+        Gm += phi[s] * w * shear_modulus_undamaged<double, kExt>(m, rho_l[s]);
         const double sy = D[s] < crit_level(m) ? pert * m.yield : 0.0;
         Ymix += phi[s] * w * sy;
-        jc = jc || m.jc;
+        jc = jc || (kExt && m.jc);
       }
       const double J = DIM == 3 ? sqrt(he[0] * he[0] + he[1] * he[1] + he[2] * he[2]) : sqrt(J2);
       double scale = 1.0, deps = 0.0;
@@ -1191,7 +1196,7 @@ struct Stage {
                          (jc ? jc_yield(m, eps[s], dl, dt, Tl[s], nullptr) : m.yield);
         // the simplified law has no gate: any plastic increment of a live
         // solid below D_crit
-        const bool simple = m.Ddot0 > 0.0;
+        const bool simple = kExt && m.Ddot0 > 0.0;
         bool gate = (simple || p < m.pgate) && (dl > 0.0) && (D[s] < crit_level(m));
         const bool ok = seq > 0.0;
         const double R = ok ? triaxiality(m, p, seq, closure_density(m, phi[s], rho_l[s])) : 1.0;
@@ -1200,7 +1205,7 @@ struct Stage {
           gate = (eps[s] > thr) || !ok;
         }
         Dn[s] = D[s];
-        if (gate) Dn[s] = (ok || simple) ? damage_rk4(m, D[s], eps[s], dl, R) : m.Dcrit;
+        if (gate) Dn[s] = (ok || simple) ? damage_rk4<kExt>(m, D[s], eps[s], dl, R) : m.Dcrit;
         const double ms = U[L::MASS + s];
         U[L::HIST + 2 * s] = ms * (eps[s] + dl);
         U[L::HIST + 2 * s + 1] = ms * Dn[s];
@@ -1215,7 +1220,7 @@ struct Stage {
     // imposed-velocity driver (Section 4.3): a live solid behind the driver
     // surface moves outward at least at the driver's speed; the kinetic
     // energy this adds is the driver's work
-    if constexpr (DIM >= 2) {
+    if constexpr (kExt && DIM >= 2) {
       if (P.drv[5] > 0.0 && live) {
         const double Rd = driver_radius(P.drv, tn);
         if (Rd < P.drv[5]) {
@@ -1248,7 +1253,7 @@ struct Stage {
     for (int s = 0; s < NS; ++s) Dc[s] = (C)Dn[s];
     const C J2n = (C)J2_of<DIM, double>(H);
     Mix<NM, NS, C> mx2;
-    mix_terms<NM, NS, C>(P, phic, rlc, Dc, J2n, mx2);
+    mix_terms<NM, NS, C, kExt>(P, phic, rlc, Dc, J2n, mx2);
     bool isl = false;
 #pragma unroll
     for (int l = 0; l < NM; ++l) isl = isl || phic[l] < cst<C>(P.phi_fp64_cut, P.f_phi_fp64_cut);
@@ -1260,7 +1265,7 @@ struct Stage {
       double xi = 0, th = rho_e, cold = 0;
 #pragma unroll
       for (int l = 0; l < NM; ++l) {
-        const double ig = P.mat[l].bp ? (double)mx2.t[l].invG : P.mat[l].invGamma;
+        const double ig = kExt && P.mat[l].bp ? (double)mx2.t[l].invG : P.mat[l].invGamma;
         xi += phi[l] * ig;
         th -= phi[l] * (double)mx2.t[l].rho_eref;
         cold += phi[l] * (double)mx2.t[l].pref * ig;
@@ -1320,7 +1325,7 @@ struct Stage {
     }
     const double J2 = J2_of<DIM, double>(H);
     Mix<NM, NS, double> mx;
-    mix_terms<NM, NS, double>(P, phi, rho_l, D, J2, mx);
+    mix_terms<NM, NS, double, kExt>(P, phi, rho_l, D, J2, mx);
     const double p = mix_pressure<NM, NS, double>(P, phi, mx, rho_e);
     double Gmix;
     const double c = mix_sound<NM, NS, double>(P, phi, mx, p, rho, Gmix);

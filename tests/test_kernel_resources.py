@@ -33,13 +33,18 @@ def fp32_asm(tmp_path_factory):
 
 
 def _kernel_info(asm, tx, ty, nth, nm):
+    """Largest VGPR, AGPR and scratch figures over the builds of one tile
+    shape (with and without the extended closures)."""
     name = (f"_ZN3fvk12stage_kernelILi2ELi{nm}ELi1EffLi{tx}ELi{ty}ELi{nth}E")
-    m = re.search(r"^(" + re.escape(name) + r"\S*):", asm, re.M)
-    assert m, f"no stage kernel {tx}x{ty}/{nth} (NM={nm}) in the FP32 unit"
-    end = asm.index(".Lfunc_end", m.end())
-    info = asm[end:end + 12000]
-    get = lambda k: int(re.search(r"; %s: (\d+)" % k, info).group(1))
-    return get("NumVgprs"), get("NumAgprs"), get("ScratchSize")
+    found = list(re.finditer(r"^(" + re.escape(name) + r"\S*):", asm, re.M))
+    assert len(found) == 2, f"stage kernel {tx}x{ty}/{nth} (NM={nm}): {len(found)} builds"
+    out = []
+    for m in found:
+        end = asm.index(".Lfunc_end", m.end())
+        info = asm[end:end + 12000]
+        get = lambda k: int(re.search(r"; %s: (\d+)" % k, info).group(1))
+        out.append((get("NumVgprs"), get("NumAgprs"), get("ScratchSize")))
+    return tuple(max(v[i] for v in out) for i in range(3))
 
 
 @pytest.mark.parametrize("nm", [1, 2])
