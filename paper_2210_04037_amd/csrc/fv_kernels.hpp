@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(256) prim3_kernel(const Inst* insts, int ii, P
   if (!setup3<St, T, C>(I, P, stage, parity, cx, t, dtinv, dt)) return;
   const int64_t g = xcd_block() * blockDim.x + threadIdx.x;
   if (g >= I.ncell) return;
-  St::template cell_prims<int64_t>(cx, g, (C*)I.Wb, I.ncell, g);
+  St::template cell_prims<int64_t, true>(cx, g, (C*)I.Wb, I.ncell, g);
 }
 
 // x-faces in runs of XRUN + 1 faces overlapping by one (a block per run):

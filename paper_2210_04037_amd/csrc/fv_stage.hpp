@@ -268,15 +268,18 @@ struct Stage {
 
   // Primitive and derived values of cell g of the stage input, stored at
   // W[v * wstride + tc] (an LDS tile, or a full-grid buffer in HBM).
-  template <class IDX>
+  // VXS (the 3D passes): the stretch and coordinate rows are not copied;
+  // the faces read them from the stage-input state, which holds the same
+  // values
+  template <class IDX, bool VXS = false>
   FV_HD static void cell_prims(const Ctx& cx, int64_t g, C* sm, IDX wstride, IDX tc) {
     C U[S];
     load_state(cx, cx.src, g, U);
-    prims_of<IDX>(cx, U, sm, wstride, tc);
+    prims_of<IDX, VXS>(cx, U, sm, wstride, tc);
   }
 
   // the same from the cell's stage-input values already in registers
-  template <class IDX>
+  template <class IDX, bool VXS = false>
   FV_HD static void prims_of(const Ctx& cx, const C* U, C* sm, IDX wstride, IDX tc) {
     C* W = sm;
     C phi[NM], rho_l[NM], mass[NM], D[NS > 0 ? NS : 1], eps[NS > 0 ? NS : 1];
@@ -340,10 +343,11 @@ struct Stage {
 #pragma unroll
     for (int q = 0; q < L::NH; ++q) W[(L::R_H + q) * NCELL + tc] = H[hk_i<DIM>(q)][hk_j<DIM>(q)];
 #pragma unroll
-    for (int q = 0; q < L::NV; ++q) W[(L::R_V + q) * NCELL + tc] = U[L::VB + q];
+    for (int q = 0; q < L::NV; ++q)
+      if (!VXS) W[(L::R_V + q) * NCELL + tc] = U[L::VB + q];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      W[(L::W_X + k) * NCELL + tc] = U[L::XC + k];
+      if (!VXS) W[(L::W_X + k) * NCELL + tc] = U[L::XC + k];
       W[(L::W_SIG + k) * NCELL + tc] = (C)2 * Gmix * H[k][k] - sf * p;
     }
     W[L::W_CRIT * NCELL + tc] = crit;
@@ -441,7 +445,7 @@ struct Stage {
 
   // Face a of the tile: W pointers of the four stencil cells (cm, c0 | c1, c2)
   // and the face's position relative to the domain boundary.
-  template <class IDX>
+  template <class IDX, bool VXS = false>
   FV_HD static void compute_face(const Ctx& cx, const C* sm, IDX wstride, int a, IDX cm,
                                  IDX c0, IDX c1, IDX c2, int gface, IDX fslot, IDX fstride,
                                  int64_t bslot, C* fb) {
@@ -449,6 +453,11 @@ struct Stage {
     const Params& P = cx.P;
     const IDX NCELL = wstride;
     const C* W = sm;
+    // stretch and coordinate rows: the primitives', or (VXS) the stage
+    // input's rows of the same cells and stride
+    static_assert(!VXS || sizeof(T) == sizeof(C), "state and compute types differ");
+    const C* VX = VXS ? (const C*)cx.src : sm;
+    constexpr int RV = VXS ? L::VB : L::R_V, RX = VXS ? L::XC : L::W_X;
     // the rows the face states need; the stretch rows (the last NV) are
     // reconstructed below, only on the side the face takes them from
     C wl[L::NR], wr[L::NR];
@@ -608,27 +617,27 @@ struct Stage {
       if (pick != 3) {
 #pragma unroll
         for (int q = 0; q < L::NV; ++q) {
-          const C qa = W[(L::R_V + q) * NCELL + ia], qb = W[(L::R_V + q) * NCELL + ib];
-          const C qc = W[(L::R_V + q) * NCELL + ic];
+          const C qa = VX[(RV + q) * NCELL + ia], qb = VX[(RV + q) * NCELL + ib];
+          const C qc = VX[(RV + q) * NCELL + ic];
           Vf[q] = qb + (C)0.5 * van_leer(qb - qa, qc - qb);
         }
 #pragma unroll
         for (int k = 0; k < DIM; ++k)
-          Xf[k] = weno3_left(W[(L::W_X + k) * NCELL + ia], W[(L::W_X + k) * NCELL + ib],
-                             W[(L::W_X + k) * NCELL + ic], weps);
+          Xf[k] = weno3_left(VX[(RX + k) * NCELL + ia], VX[(RX + k) * NCELL + ib],
+                             VX[(RX + k) * NCELL + ic], weps);
       }
       if (pick == 2) {
 #pragma unroll
         for (int q = 0; q < L::NV; ++q) {
-          const C q0 = W[(L::R_V + q) * NCELL + c0], q1 = W[(L::R_V + q) * NCELL + c1];
-          const C q2 = W[(L::R_V + q) * NCELL + c2];
+          const C q0 = VX[(RV + q) * NCELL + c0], q1 = VX[(RV + q) * NCELL + c1];
+          const C q2 = VX[(RV + q) * NCELL + c2];
           Vf[q] = (C)0.5 * (Vf[q] + (q1 - (C)0.5 * van_leer(q1 - q0, q2 - q1)));
         }
 #pragma unroll
         for (int k = 0; k < DIM; ++k)
-          Xf[k] = (C)0.5 * (Xf[k] + weno3_left(W[(L::W_X + k) * NCELL + c2],
-                                                W[(L::W_X + k) * NCELL + c1],
-                                                W[(L::W_X + k) * NCELL + c0], weps));
+          Xf[k] = (C)0.5 * (Xf[k] + weno3_left(VX[(RX + k) * NCELL + c2],
+                                                VX[(RX + k) * NCELL + c1],
+                                                VX[(RX + k) * NCELL + c0], weps));
       }
     }
     // outward boundary flux accumulation, RK3 weights 1/6, 1/6, 2/3
@@ -850,7 +859,7 @@ struct Stage {
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       st[k] = row * nx + map_index(i - 2 + k, nx, I.bc[0][0], I.bc[0][1]);
-    compute_face<int64_t>(cx, W, I.ncell, 0, st[0], st[1], st[2], st[3], i, (int64_t)t,
+    compute_face<int64_t, true>(cx, W, I.ncell, 0, st[0], st[1], st[2], st[3], i, (int64_t)t,
                           (int64_t)(XRUN + 1), row, fb);
   }
   // Phase 2: the cell between faces t and t + 1 of run b, if they bound one;
@@ -868,7 +877,7 @@ struct Stage {
     const int64_t g = f / (nx + 1) * nx + i;
     C Xc[3], uc[3], phic[NM];
     C Vc[3][3];
-    own_values(W, nc, g, Xc, uc, phic, Vc);
+    own_values(cx, W, nc, g, Xc, uc, phic, Vc);
     FaceC m, p;
     face_contrib<int>(fb, t, XRUN + 1, 0, 1, Xc, Vc, uc, m);
     face_contrib<int>(fb, t + 1, XRUN + 1, 0, 0, Xc, Vc, uc, p);
@@ -900,13 +909,14 @@ struct Stage {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         st[k] = g0 + (int64_t)map_index(i - 2 + k, na, I.bc[a][0], I.bc[a][1]) * sa;
-      compute_face<int64_t>(cx, W, nc, a, st[0], st[1], st[2], st[3], i, (int64_t)0, (int64_t)1,
+      compute_face<int64_t, true>(cx, W, nc, a, st[0], st[1], st[2], st[3], i, (int64_t)0,
+                                  (int64_t)1,
                             bslot, up);
       if (i > i0) {
         const int64_t g = g0 + (int64_t)(i - 1) * sa;
         C Xc[3], uc[3], phic[NM];
         C Vc[3][3];
-        own_values(W, nc, g, Xc, uc, phic, Vc);
+        own_values(cx, W, nc, g, Xc, uc, phic, Vc);
         FaceC m, p;
         face_contrib<int>(lo, 0, 1, a, 1, Xc, Vc, uc, m);
         face_contrib<int>(up, 0, 1, a, 0, Xc, Vc, uc, p);
@@ -923,17 +933,20 @@ struct Stage {
   }
 
   // the centre values a cell's gather takes from the 3D primitives
-  FV_HD static void own_values(const C* W, int64_t nc, int64_t g, C* Xc, C* uc, C* phic,
-                               C Vc[3][3]) {
+  // (the coordinates and the stretch from the stage input, as the 3D faces
+  // read them)
+  FV_HD static void own_values(const Ctx& cx, const C* W, int64_t nc, int64_t g, C* Xc, C* uc,
+                               C* phic, C Vc[3][3]) {
+    const C* Us = (const C*)cx.src;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      Xc[k] = W[(L::W_X + k) * nc + g];
+      Xc[k] = Us[(L::XC + k) * nc + g];
       uc[k] = W[(L::R_U + k) * nc + g];
     }
 #pragma unroll
     for (int l = 0; l < NM; ++l) phic[l] = W[(L::R_PHI + l) * nc + g];
 #pragma unroll
-    for (int q = 0; q < L::NV; ++q) Vc[vb_i<3>(q)][vb_j<3>(q)] = W[(L::R_V + q) * nc + g];
+    for (int q = 0; q < L::NV; ++q) Vc[vb_i<3>(q)][vb_j<3>(q)] = Us[(L::VB + q) * nc + g];
   }
 
   // ---------------------------------------------------------------- phase 4

@@ -248,7 +248,7 @@ static void step_3d(Run& r, int nsteps) {
       const double dt = stage_dt(r, stage, q);
       typename St::Ctx cx;
       init_ctx(cx, r, stage, q, dt);
-      for (int64_t g = 0; g < nc; ++g) St::template cell_prims<int64_t>(cx, g, Wb, nc, g);
+      for (int64_t g = 0; g < nc; ++g) St::template cell_prims<int64_t, true>(cx, g, Wb, nc, g);
       std::fill(r.Acc.begin(), r.Acc.end(), NAN);
       const int64_t nb = St::xrun_count(r.I);
       for (int64_t b = 0; b < nb; ++b) {
