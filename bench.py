@@ -683,9 +683,9 @@ def main():
     del cases
     if not args.only and head == "impact3d":
         others = {}
-        for name in ("ring", "ensemble", "disk"):
+        for name in ("ring", "ensemble", "disk", "shell3d"):
             c2, d2, _ = make_workload(name, None, args.members)
-            m = measure(name, c2, d2, args, compare=name in ("ring", "disk")
+            m = measure(name, c2, d2, args, compare=name in ("ring", "disk", "shell3d")
                         and not args.no_compare,
                         post_fracture=(args.post_fracture if name == "ring"
                                        and args.post_fracture > 0 else None))
