@@ -164,8 +164,8 @@ int32_t fv_state_fields(int32_t dim, int32_t n_mat, const fv_material* mats);
 
 /* Bytes of device workspace fv_init needs for these instances (two stage
  * copies of every state, boundary-flux accumulators, dt state, instance
- * tables, reduction bins; in 3D also the primitives of every cell and the
- * face data of each direction).  Returns 0 for invalid arguments. */
+ * tables, reduction bins; in 3D also the primitives of every cell and each
+ * cell's divergence sum).  Returns 0 for invalid arguments. */
 size_t fv_workspace_bytes(int32_t n_inst, const fv_grid* grids, int32_t n_mat,
                           const fv_material* mats, const fv_options* opt);
 
