@@ -373,9 +373,11 @@ __global__ void __launch_bounds__(256) prim3_kernel(const Inst* insts, int ii, P
 // x-faces in runs of XRUN + 1 faces overlapping by one (a block per run):
 // each thread computes one face into LDS, then the cell between its face and
 // the next one starts its divergence sum
+// (one material in FP32: bounded to five waves per SIMD, which costs the
+// compiler one register and no spill)
 template <int NM, int NS, class T, class C>
-__global__ void __launch_bounds__(256) xface3_kernel(const Inst* insts, int ii, Params P,
-                                                     int stage, int parity) {
+__global__ void __launch_bounds__(256, (sizeof(C) == 4 && NM == 1) ? 5 : 1)
+    xface3_kernel(const Inst* insts, int ii, Params P, int stage, int parity) {
   using St = Stage<3, NM, NS, T, C, 1, 1>;
   using L = Lay<3, NM, NS>;
   static_assert(St::XRUN + 1 == 256, "one face per thread");
