@@ -41,6 +41,8 @@ TRAFFIC_FILES = {
     "ring": os.path.join(PROFILE_DIR, "stage_kernel_ring1024.txt"),
     "impact3d": os.path.join(PROFILE_DIR, "stage_kernel_impact512.txt"),
     "shell3d": os.path.join(PROFILE_DIR, "stage_kernel_shell256.txt"),
+    "ensemble": os.path.join(PROFILE_DIR, "stage_kernel_ensemble64.txt"),
+    "disk": os.path.join(PROFILE_DIR, "stage_kernel_disk400.txt"),
 }
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2210_04037_amd", "csrc", f)
                   for f in ("fv_core.hpp", "fv_stage.hpp", "fv_kernels.hpp",
