@@ -39,7 +39,9 @@ The base finite-volume scheme is deferred by the paper to earlier work
     stages).  Volume fractions are clamped to [phi_floor, 1] after each stage.
 Parity of the flux scheme is unpinned against the paper beyond the invariants
 and exact solutions checked by the tests (uniform states, conservation,
-linear X transport, mirror symmetry, elastic wave speeds, convergence order).
+linear X transport, mirror symmetry, elastic wave speeds, convergence order,
+free-surface reflection, the shear Riemann problem, and the opened face's
+zero traction between separating critical halves).
 """
 import numpy as np
 

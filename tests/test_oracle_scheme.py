@@ -329,6 +329,39 @@ def test_opened_faces_carry_a_moving_fragment():
     assert np.allclose(mom, 50.0, rtol=1e-3)
 
 
+def test_opened_face_carries_no_traction():
+    """Closed form for the void-opening modifier (Section 3.1): a critically
+    damaged bar in tension whose halves separate at +-v.  The left half's
+    momentum changes only by the fluxes through its two ends, so the sum of
+    its cells' momentum rates times dx is F(left end) - F(centre).  The left
+    end is a boundary face (never opened) between equal states, whose flux is
+    the physical one, rho u^2 + p (no distortion); an opened centre face
+    carries no traction and, with both free surfaces moving apart, no
+    material, so the sum is exactly rho v^2 + p.  Without critical damage
+    the centre face transmits the tension and the sum differs."""
+    from oracle.scheme import rhs
+    v, eta, n = 30.0, 0.995, 40
+
+    def left_half_rate(D):
+        case = F.uniform_case(1, (n, 1, 1), [CU], [1.0], [8930.0 * eta], [0.0], -5.0e7,
+                              bc="transmissive")
+        L = Layout(1, case.mats)
+        case.prim[L.dmg[0]] = D
+        case.prim[L.mom[0]][..., : n // 2] = -v
+        case.prim[L.mom[0]][..., n // 2:] = v
+        s = _solver(case)
+        k, _ = rhs(s.U, s.geom, L, s.opts)
+        P = s.prim()
+        rho, p = P.rho[0, 0, 0], P.p[0, 0, 0]
+        assert p < 0.0                                    # in tension
+        return float(np.sum(k[L.mom[0]][..., : n // 2]) * s.geom.dx[0]), rho * v * v + p
+
+    got, want = left_half_rate(0.9)
+    assert got == pytest.approx(want, rel=1e-12, abs=1e-12 * abs(want))
+    closed, _ = left_half_rate(0.0)
+    assert abs(closed - want) > 1e-3 * abs(want)
+
+
 def test_volume_fraction_bounds_ring():
     case = F.make_case(2, n=32)
     s = _solver(case)
