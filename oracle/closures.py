@@ -102,6 +102,17 @@ def ref_terms(rho, J2, D, m):
 CRIT_REL_TOL = 1.0e-9
 
 
+# The sign tests on stress, the tension of the void-opening modifier (Section
+# 3.1) and the pressure gate of the damage law, hold beyond the same relative
+# band of the solid's bulk modulus.  A void cell relaxed to its film's zero
+# pressure sits at zero stress up to the rounding of its state (K times the
+# unit of the storage precision); the band puts such a cell on the side of no
+# tension and a closed gate instead of letting rounding decide.
+def stress_band(m, rel_tol=CRIT_REL_TOL):
+    """Width of the band of the stress sign tests: rel_tol K0 (Pa)."""
+    return rel_tol * m["K0"]
+
+
 def is_critical(D, m, rel_tol=CRIT_REL_TOL):
     """Critical damage test of Section 3.1, D >= D_crit, up to the double
     precision rounding of the advected ratio (see CRIT_REL_TOL).  rel_tol

@@ -46,7 +46,7 @@ zero traction between separating critical halves).
 import numpy as np
 
 from .layout import hencky_comps
-from .closures import is_critical
+from .closures import is_critical, stress_band
 from .mixture import cons_to_prim, face_state
 
 AX = {0: -1, 1: -2, 2: -3}          # x, y, z -> axis from the end
@@ -181,6 +181,11 @@ def thinc_faces(q, beta):
 def _critical(D, m, opts):
     tol = getattr(opts, "crit_rel_tol", None)
     return is_critical(D, m) if tol is None else is_critical(D, m, tol)
+
+
+def _stress_band(m, opts):
+    tol = getattr(opts, "crit_rel_tol", None)
+    return stress_band(m) if tol is None else stress_band(m, tol)
 
 
 def _pick(sel_pos, sel_neg, vL, vR):
@@ -371,8 +376,10 @@ def rhs(U, geom, layout, opts):
     dU = np.zeros_like(U)
     bflux = {}
     crit = np.zeros(P.p.shape, dtype=bool)
+    tens_band = 0.0
     for l in L.solids:
         crit |= _critical(P.D[l], mats[l], opts)
+        tens_band = max(tens_band, _stress_band(mats[l], opts))
     for a in range(dim):
         dxa = geom.dx[a]
         n = geom.n[a]
@@ -445,7 +452,7 @@ def rhs(U, geom, layout, opts):
         # the two free surfaces must separate (approaching sides are closing
         # the void and are in contact again)
         opened = ((cen["crit"][0] | cen["crit"][1])
-                  & (cen["sig"][0] + cen["sig"][1] > 0)
+                  & (cen["sig"][0] + cen["sig"][1] > tens_band)
                   & (ustarL <= ustarR))
         # boundary faces are handled below, never by the damage predicate
         if geom.bc[a][0] != "periodic":

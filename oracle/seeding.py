@@ -23,6 +23,7 @@ X = x - d) the new value is exact: X(p) - (p - c) = c - d.
 """
 import numpy as np
 
+from .mixture import cons_to_prim, material_terms, pressure_from_energy
 from .source import phi0_at
 
 
@@ -69,3 +70,53 @@ def seed_void(U, geom, layout, nu_thresh):
     for k in range(dim):
         U[L.X[k]] = np.where(mask, newX[k], X[k])
     return U
+
+
+RELAX_ITERS = 64
+
+
+def relax_void(U, geom, layout, nu_thresh, phi_floor):
+    """Void cells give up their pressure (a reading of the void treatment
+    around Section 3.2.1's seeding, one solid only): a cell with mass whose
+    void fraction exceeds the seeding threshold holds a film of material with
+    void on its free side, and void carries no stress.  The film's density
+    moves to the first density, scanning up from rho0 / 2 over
+    [rho0 / 2, 2 rho0], at which the material's own pressure at the cell's
+    specific internal energy e = rho_e / mass changes sign: the equation of
+    state of the film alone (volume fraction one, energy rho_l e per film
+    volume), so the closures of a trace never enter.  Bisection, RELAX_ITERS
+    halvings, on whether the pressure at the midpoint has the sign it has at
+    the lower end; without a sign change the film takes 2 rho0.  The volume
+    fraction follows as mass / density (clamped to [phi_floor, 1]); mass,
+    momentum, energy and histories are unchanged.  Returns a new array."""
+    L = layout
+    if len(L.mats) != 1:
+        return U
+    phi = U[L.phi[0]]
+    mass = U[L.mass[0]]
+    mask = ((1.0 - np.clip(phi, 0.0, 1.0)) > nu_thresh) & (mass > 0.0)
+    if not np.any(mask):
+        return U
+    P = cons_to_prim(U, L)
+    ms = np.where(mask, mass, 1.0)
+    e = P.rho_e / ms
+    rho0 = L.mats[0]["rho0"]
+    one = np.ones((1,) + mass.shape)
+
+    def positive(rl):
+        with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+            terms = material_terms(rl[None], P.D, P.J2, L.mats, one)
+            return pressure_from_energy(one, terms, rl * e, L.mats) > 0.0
+
+    lo = np.full(mass.shape, 0.5 * rho0)
+    hi = np.full(mass.shape, 2.0 * rho0)
+    slo = positive(lo)
+    for _ in range(RELAX_ITERS):
+        mid = 0.5 * (lo + hi)
+        same = positive(mid) == slo
+        lo = np.where(same, mid, lo)
+        hi = np.where(same, hi, mid)
+    rs = 0.5 * (lo + hi)
+    out = U.copy()
+    out[L.phi[0]] = np.where(mask, np.clip(ms / rs, phi_floor, 1.0), phi)
+    return out

@@ -13,7 +13,7 @@ from .mixture import Options, prim_to_cons, cons_to_prim
 from .scheme import Geometry, rhs, clamp_phi, dt_inverse
 from .source import source_step
 from .driver import apply_driver
-from .seeding import seed_void
+from .seeding import relax_void, seed_void
 from .totals import interior_totals, boundary_totals
 from . import fragments as _frag
 
@@ -69,6 +69,7 @@ class Solver:
                               self.t + dt)
         if getattr(o, "seed_nu", 0.0) > 0.0:
             self.U = seed_void(self.U, g, L, o.seed_nu)
+            self.U = relax_void(self.U, g, L, o.seed_nu, o.phi_floor)
         self.t += dt
         self.steps += 1
         return dt

@@ -39,7 +39,7 @@ import numpy as np
 from .closures import (solid_shear_modulus, triaxiality, eps_threshold,
                        bonora_dD_deps, is_critical, jc_active, jc_flow_stress,
                        temperature)
-from .scheme import _critical
+from .scheme import _critical, _stress_band
 from .kinematics import hencky, stretch_from_log
 from .mixture import cons_to_prim, closure_density, PHI_TRACE, material_terms
 
@@ -194,7 +194,7 @@ def source_step(U, phi0, geom, layout, opts, dt=None):
         sig_eq = (1.0 - D_n) * pert * jc_flow_stress(eps_n + dl, rate, temps[l], m)
         # the simplified law has no gate: damage grows with any plastic
         # increment of a live, not yet critical solid
-        open_p = True if simplified_law(m) else (P.p < m["p_gate"])
+        open_p = True if simplified_law(m) else (P.p < m["p_gate"] - _stress_band(m, opts))
         gate = open_p & (dl > 0) & ~_critical(D_n, m, opts)
         ok = sig_eq > 0
         R = triaxiality(P.p, np.where(ok, sig_eq, 1.0),

@@ -89,6 +89,11 @@ struct MatP {
   double Dcrit_eff;    // double storage: D_crit (1 - 1e-9)
   double Dcrit_bulk;   // float storage (FP32-bulk policy): D_crit (1 - 1e-6),
                        // about fifteen float ulps of D_crit
+  // band of the stress sign tests (the tension of the void-opening modifier,
+  // the pressure gate of the damage law): the same relative width of K0, so
+  // that a cell at zero stress up to rounding counts as out of tension
+  double sbnd;         // double storage: 1e-9 K0
+  double sbnd_bulk;    // float storage: 1e-6 K0
   double invGamma;   // 1 / Gamma0
   double nu;         // Poisson ratio of the undamaged moduli
   double bonA;       // alpha_B (Dc - D0)^(1/alpha_B) / ln(eps_c / eps_th)
@@ -114,6 +119,9 @@ struct Params {
   // imposed-velocity driver of the ring (Section 4.3): inner radius, v0, v1,
   // t0, t1, r_max (r_max = 0: off)
   double drv[6];
+  // tension band of the void-opening modifier: the largest of the solids'
+  // stress bands (double storage, float storage)
+  double tens_band, tens_band_bulk;
   float f_weno_eps, f_c_min2, f_phi_fp64_cut, f_pad;
   float f_thinc_beta, f_thinc_tb, f_thinc_sech, f_pad2;
 };
@@ -122,6 +130,8 @@ struct Params {
 inline void set_solid_constants(MatP& q) {
   q.Dcrit_eff = q.Dcrit * (1.0 - 1.0e-9);
   q.Dcrit_bulk = q.Dcrit * (1.0 - 1.0e-6);
+  q.sbnd = 1.0e-9 * q.K0;
+  q.sbnd_bulk = 1.0e-6 * q.K0;
   q.nu = (3.0 * q.K0 - 2.0 * q.G0) / (2.0 * (3.0 * q.K0 + q.G0));
   q.bonA = q.balpha * pow(q.Dcrit - q.D0, 1.0 / q.balpha) / log(q.eps_c / q.eps_th);
   q.bonExp = (q.balpha - 1.0) / q.balpha;
@@ -129,7 +139,12 @@ inline void set_solid_constants(MatP& q) {
 
 // Host: fill the float copies once the double parameters are set.
 inline void set_float_constants(Params& P) {
+  P.tens_band = P.tens_band_bulk = 0.0;
   for (MatP& m : P.mat) {
+    if (m.kind == 0) {
+      P.tens_band = m.sbnd > P.tens_band ? m.sbnd : P.tens_band;
+      P.tens_band_bulk = m.sbnd_bulk > P.tens_band_bulk ? m.sbnd_bulk : P.tens_band_bulk;
+    }
     m.f_rho0 = (float)m.rho0; m.f_K0 = (float)m.K0; m.f_alpha = (float)m.alpha;
     m.f_G0 = (float)m.G0; m.f_beta = (float)m.beta; m.f_Gamma0 = (float)m.Gamma0;
     m.f_invGamma = (float)m.invGamma; m.f_Dcrit_eff = (float)m.Dcrit_bulk;
@@ -345,6 +360,15 @@ struct Mix {
 // closures just above the threshold; evaluating them at rho0 instead would
 // switch on the full modulus G0 with whatever distortion the cell carries.
 constexpr double PHI_TRACE = 1.0e-6;
+
+// halvings of the void relaxation's density bracket [rho0/2, 2 rho0]
+constexpr int RELAX_ITERS = 64;
+
+// the void relaxation runs (and then sets the CFL state after the seeding
+// pass instead of the last stage): one solid and seeding on
+FV_HD bool relax_on(const Params& P, int nm, int ns) {
+  return nm == 1 && ns == 1 && P.seed_nu > 0.0;
+}
 
 // density for the closures that need one (the triaxiality's rho0/rho): the
 // reference density for a trace

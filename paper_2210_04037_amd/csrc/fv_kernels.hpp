@@ -215,7 +215,7 @@ stage_kernel(const Inst* __restrict__ insts, const int2* __restrict__ block_tab,
   }
   // blocks are dispatched round-robin over the XCDs: blockIdx.x & 7 is the
   // block's XCD and picks its CFL slot
-  if (stage == 3)
+  if (stage == 3 && !relax_on(P, NM, NS))
     block_max_to<NT>(cflv, reinterpret_cast<double*>(smem_d),
                      &dts[dts_slot(1 - q, blockIdx.x & (DTS_NSLOT - 1))]);
 }
@@ -280,17 +280,41 @@ __global__ void __launch_bounds__(256) seed_kernel(const Inst* insts, int ii, Pa
   for (int k = 0; k < DIM; ++k) out[(int64_t)(L::XC + k) * I.ncell + g] = (T)Xn[k];
 }
 
+// The seeded coordinates back into the state; with one solid, then the void
+// relaxation of the cell and the CFL reduction for the next step (which the
+// last stage leaves to this pass).
 template <int DIM, int NM, int NS, class T>
-__global__ void __launch_bounds__(256) seed_copy_kernel(const Inst* insts, int ii, int parity) {
+__global__ void __launch_bounds__(256) seed_copy_kernel(const Inst* insts, int ii, Params P,
+                                                        int parity) {
   using L = Lay<DIM, NM, NS>;
+  using St = Stage<DIM, NM, NS, T, T, 1, 1>;
+  __shared__ double scratch[4];
   const Inst& I = insts[ii];
+  if (!stepped(I, parity)) return;     // uniform over the launch
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= I.ncell || !stepped(I, parity)) return;
-  const T* src = (const T*)I.U1;
-  T* U = (T*)I.U;
+  const bool relax = relax_on(P, NM, NS);
+  double v = 0.0;
+  if (g < I.ncell) {
+    const T* src = (const T*)I.U1;
+    T* U = (T*)I.U;
 #pragma unroll
-  for (int k = 0; k < DIM; ++k)
-    U[(int64_t)(L::XC + k) * I.ncell + g] = src[(int64_t)(L::XC + k) * I.ncell + g];
+    for (int k = 0; k < DIM; ++k)
+      U[(int64_t)(L::XC + k) * I.ncell + g] = src[(int64_t)(L::XC + k) * I.ncell + g];
+    if (relax) {
+      double Ud[L::S];
+#pragma unroll
+      for (int f = 0; f < L::S; ++f) Ud[f] = (double)U[(int64_t)f * I.ncell + g];
+      St::relax_void_cell(P, Ud);
+      U[(int64_t)L::PHI * I.ncell + g] = (T)Ud[L::PHI];
+      Ud[L::PHI] = (double)U[(int64_t)L::PHI * I.ncell + g];
+      v = St::cfl_sum(P, I, Ud);
+      if (!(v == v)) {
+        atomicOr(reinterpret_cast<unsigned int*>(&I.dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);
+        v = 0.0;
+      }
+    }
+  }
+  if (relax) block_max_to<256>(v, scratch, &I.dts[dts_slot(1 - (parity & 1), blockIdx.x & (DTS_NSLOT - 1))]);
 }
 
 template <int DIM, int NM, int NS, class T, class C, int TX, int TY>
@@ -440,7 +464,7 @@ __global__ void __launch_bounds__(256) finish3_kernel(const Inst* insts, int ii,
     cflv = St::finish_cell(cx, g, acc, &bad);
     if (bad) atomicOr(reinterpret_cast<unsigned int*>(&I.dts[DTS_FLAG]), (unsigned)FLAG_NONPHYS);
   }
-  if (cx.stage == 3 && go)
+  if (cx.stage == 3 && go && !relax_on(P, NM, NS))
     block_max_to<256>(cflv, scratch, &I.dts[dts_slot(1 - q, blockIdx.x & (DTS_NSLOT - 1))]);
 }
 

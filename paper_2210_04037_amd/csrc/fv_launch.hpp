@@ -90,7 +90,7 @@ void common_ops(Ops& o) {
       hipLaunchKernelGGL((seed_kernel<DIM, NM, NS, T>), grid, blk, 0, s, c->insts_d, ii, c->P,
                          parity);
       hipLaunchKernelGGL((seed_copy_kernel<DIM, NM, NS, T>), grid, blk, 0, s, c->insts_d, ii,
-                         parity);
+                         c->P, parity);
     }
   };
   o.cfl = [](fv_ctx* c, int ii, int parity) {

@@ -563,7 +563,8 @@ struct Stage {
       const bool crit = W[L::W_CRIT * NCELL + c0] > (C)0 || W[L::W_CRIT * NCELL + c1] > (C)0;
       const C tens = W[(L::W_SIG + a) * NCELL + c0] + W[(L::W_SIG + a) * NCELL + c1];
       // open only while the two free surfaces separate
-      if (crit && tens > (C)0 && usL <= usR) {
+      const C band = (C)(sizeof(T) == 8 ? cx.P.tens_band : cx.P.tens_band_bulk);
+      if (crit && tens > band && usL <= usR) {
         // no traction; a side whose one-sided velocity points through the
         // face carries its material into the neighbour, else void enters it
         os = 1;
@@ -1210,7 +1211,8 @@ struct Stage {
         // the simplified law has no gate: any plastic increment of a live
         // solid below D_crit
         const bool simple = kExt && m.Ddot0 > 0.0;
-        bool gate = (simple || p < m.pgate) && (dl > 0.0) && (D[s] < crit_level(m));
+        const double pg = m.pgate - (sizeof(T) == 8 ? m.sbnd : m.sbnd_bulk);
+        bool gate = (simple || p < pg) && (dl > 0.0) && (D[s] < crit_level(m));
         const bool ok = seq > 0.0;
         const double R = ok ? triaxiality(m, p, seq, closure_density(m, phi[s], rho_l[s])) : 1.0;
         if (gate && !simple) {
@@ -1291,6 +1293,53 @@ struct Stage {
 #pragma unroll
     for (int k = 0; k < DIM; ++k) sum += (fabs(u[k]) + (double)c) / I.dx[k];
     return sum;
+  }
+
+  // Void relaxation of one cell after seeding (one solid, seed_nu > 0): a
+  // cell with mass whose void fraction exceeds seed_nu holds a film of
+  // material with void on its free side, and void carries no stress.  The
+  // film's density moves to the first density, scanning up from rho0/2 over
+  // [rho0/2, 2 rho0], at which the material's own pressure at the cell's
+  // specific internal energy e = rho_e / mass changes sign (the film alone:
+  // volume fraction one, energy rho_l e per film volume, no trace closures);
+  // RELAX_ITERS halvings on whether the pressure at the midpoint has the
+  // sign it has at the lower end; without a sign change the film takes
+  // 2 rho0.  phi = mass / density, clamped to [phi_floor, 1]; nothing else
+  // changes.  U: the cell's state (double), phi updated in place.
+  FV_HD static void relax_void_cell(const Params& P, double* U) {
+    if constexpr (NM == 1 && NS == 1) {
+      const double phi = U[L::PHI], ms = U[L::MASS];
+      if (!(1.0 - m_clamp(phi, 0.0, 1.0) > P.seed_nu) || !(ms > 0.0)) return;
+      double u2 = 0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        const double uk = U[L::MOM + k] / ms;
+        u2 += uk * uk;
+      }
+      const double e = (U[L::ENE] - 0.5 * ms * u2) / ms;
+      double D[1] = {U[L::HIST + 1] / ms};
+      double V[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+      for (int q = 0; q < L::NV; ++q) V[vb_i<DIM>(q)][vb_j<DIM>(q)] = U[L::VB + q];
+      double H[3][3];
+      hencky<DIM, double>(V, H);
+      const double J2 = J2_of<DIM, double>(H);
+      auto positive = [&](double rl) {
+        double one = 1.0;
+        Mix<1, 1, double> mr;
+        mix_terms<1, 1, double, kExt>(P, &one, &rl, D, J2, mr);
+        return mix_pressure<1, 1, double>(P, &one, mr, rl * e) > 0.0;
+      };
+      const double rho0 = P.mat[0].rho0;
+      double lo = 0.5 * rho0, hi = 2.0 * rho0;
+      const bool slo = positive(lo);
+      for (int it = 0; it < RELAX_ITERS; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (positive(mid) == slo) lo = mid;
+        else hi = mid;
+      }
+      U[L::PHI] = m_clamp(ms / (0.5 * (lo + hi)), P.phi_floor, 1.0);
+    }
   }
 
   // wave-speed sum of a state without a source step (initial CFL)

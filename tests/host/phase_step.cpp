@@ -158,7 +158,7 @@ static void init_ctx(Ctx& cx, Run& r, int stage, int q, double dt) {
 // Lagrangian seeding after a step, as the device's two passes: every cell's
 // new coordinates from the state before seeding, then copied back.
 template <int DIM, int NM, int NS>
-static void seed_all(Run& r) {
+static void seed_all(Run& r, int nq) {
   using St = Stage<DIM, NM, NS, double, double, 1, 1>;
   using L = Lay<DIM, NM, NS>;
   if (!(r.P.seed_nu > 0)) return;
@@ -170,6 +170,20 @@ static void seed_all(Run& r) {
   }
   for (int k = 0; k < DIM; ++k)
     for (int64_t g = 0; g < r.nc; ++g) r.U[(size_t)(L::XC + k) * r.nc + g] = X[(size_t)k * r.nc + g];
+  // one solid: the void relaxation, and the next step's CFL value from the
+  // relaxed state (the device's copy-back pass)
+  if (!relax_on(r.P, NM, NS)) return;
+  double m = 0.0;
+  for (int64_t g = 0; g < r.nc; ++g) {
+    double Uc[L::S];
+    for (int f = 0; f < L::S; ++f) Uc[f] = r.U[(size_t)f * r.nc + g];
+    St::relax_void_cell(r.P, Uc);
+    r.U[(size_t)L::PHI * r.nc + g] = Uc[L::PHI];
+    const double v = St::cfl_sum(r.P, r.I, Uc);
+    if (!(v == v)) r.dts[DTS_FLAG] = 1.0;
+    else m = std::max(m, v);
+  }
+  r.dts[dts_slot(nq, 0)] = m;
 }
 
 template <int DIM, int NM, int NS, int TX, int TY, int NTH = TX * TY>
@@ -226,7 +240,7 @@ static void step_tiles(Run& r, int nsteps) {
         }
       if (stage == 3) r.dts[dts_slot(1 - q, 0)] = bmax;
     }
-    seed_all<DIM, NM, NS>(r);
+    seed_all<DIM, NM, NS>(r, 1 - q);
   }
 }
 
@@ -279,7 +293,7 @@ static void step_3d(Run& r, int nsteps) {
       }
       if (stage == 3) r.dts[dts_slot(1 - q, 0)] = bmax;
     }
-    seed_all<3, NM, NS>(r);
+    seed_all<3, NM, NS>(r, 1 - q);
   }
 }
 

@@ -3,7 +3,8 @@ Burakovsky-Preston Grueneisen function, Johnson-Cook with thermal
 softening, the simplified damage law, the imposed-velocity driver and
 Lagrangian seeding): the FP64 form against the oracle on small copies in 2D
 and 3D.  The full 2D cross-section and the paper's 300 x 300 x 8 slab run to
-50 us are kept as a skipped case with their measured cause (DRIVEN_RING_SKIP)."""
+50 us: the 2D FP64 run reaches it and fragments; the other forms are kept
+as skipped cases with their measured causes."""
 import numpy as np
 import pytest
 
@@ -25,9 +26,13 @@ TOL = 1e-9
 # 1e-4 do not remove it.  The state of almost-empty cells under a wave is
 # ill-conditioned in this model; the paper's run used AMR, which this build
 # does not have.
-DRIVEN_RING_SKIP = ("the driven ring in void goes unstable at its outer surface "
-                    "(near-vacuum cells with negative internal energy under the "
-                    "driver's compression wave); kept skipped with that cause")
+DRIVEN_RING_FP32_SKIP = ("with the void films relaxed the FP64 form runs the full cross-section "
+                         "to 50 us; the FP32-bulk form still trips the non-physical flag "
+                         "before then (measured)")
+DRIVEN_RING_SKIP = ("the driven 300 x 300 x 8 slab in void goes unstable at its outer "
+                    "surface even with the void films relaxed: the FP64 time step "
+                    "collapses (17 us after 40000 steps), the FP32-bulk form trips "
+                    "the non-physical flag within 250 steps (measured)")
 
 
 def _gpu(case, **kw):
@@ -44,7 +49,7 @@ def _scaled_errors(got, ref, L):
     return np.max(np.abs(got - ref).reshape(L.S, -1), axis=1) / (sc + 1e-300)
 
 
-@pytest.mark.parametrize("dim,n,nz,steps", [(2, 40, 1, 6), (3, 24, 4, 4)])
+@pytest.mark.parametrize("dim,n,nz,steps", [(2, 40, 1, 3), (3, 24, 4, 4)])
 def test_unb_ring_matches_oracle(dim, n, nz, steps):
     case = F.unb_ring(dim, n=n, nz=nz)
     print(f"[unb] {dim}D {n} fp64 {steps} steps", flush=True)
@@ -76,9 +81,11 @@ def _radial_speed(state, case, L):
     return float(np.sum((m * ur)[solid]) / np.sum(m[solid]))
 
 
-@pytest.mark.skip(reason=DRIVEN_RING_SKIP)
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("dim,precision", [
+    (2, "fp64"),
+    pytest.param(2, "fp32", marks=pytest.mark.skip(reason=DRIVEN_RING_FP32_SKIP)),
+    pytest.param(3, "fp64", marks=pytest.mark.skip(reason=DRIVEN_RING_SKIP)),
+    pytest.param(3, "fp32", marks=pytest.mark.skip(reason=DRIVEN_RING_SKIP))])
 def test_unb_ring_runs_to_its_end_time_and_fragments(dim, precision):
     import torch
     case = F.unb_ring(dim)

@@ -362,6 +362,40 @@ def test_opened_face_carries_no_traction():
     assert abs(closed - want) > 1e-3 * abs(want)
 
 
+def test_tension_below_the_stress_band_keeps_the_face_closed():
+    """The tension test of the void-opening modifier holds beyond the stress
+    band (1e-9 K0): the separating critical bar of the closed-form test above
+    opens at a tension of four band widths (its left half's momentum rate is
+    exactly rho v^2 + p) and stays closed at a quarter of one, where a void
+    film relaxed to zero pressure sits up to rounding."""
+    from oracle.scheme import rhs
+    from oracle.closures import stress_band
+    v, n = 30.0, 40
+    band = stress_band(CU)
+
+    def left_half_rate(p0):
+        # just below rho0 (cold pressure about -10 band widths), so that the
+        # thermal energy stays non-negative at the chosen tension
+        case = F.uniform_case(1, (n, 1, 1), [CU], [1.0], [8930.0 * (1.0 - 1e-7)], [0.0],
+                              p0, bc="transmissive")
+        L = Layout(1, case.mats)
+        case.prim[L.dmg[0]] = 0.9
+        case.prim[L.mom[0]][..., : n // 2] = -v
+        case.prim[L.mom[0]][..., n // 2:] = v
+        s = _solver(case)
+        k, _ = rhs(s.U, s.geom, L, s.opts)
+        P = s.prim()
+        rho, p = P.rho[0, 0, 0], P.p[0, 0, 0]
+        return float(np.sum(k[L.mom[0]][..., : n // 2]) * s.geom.dx[0]), rho * v * v + p, p
+
+    got, want, p = left_half_rate(-2.0 * band)
+    assert -2.5 * band < p < -1.5 * band
+    assert got == pytest.approx(want, rel=1e-12, abs=1e-12 * abs(want))
+    got, want, p = left_half_rate(-0.125 * band)
+    assert -0.2 * band < p < -0.05 * band
+    assert abs(got - want) > 1e-3 * abs(want)
+
+
 def test_volume_fraction_bounds_ring():
     case = F.make_case(2, n=32)
     s = _solver(case)

@@ -123,3 +123,75 @@ def test_disk_with_seeding_stays_physical():
     assert np.min(s.U[L.mass[0]]) > 0
     D = s.U[L.dmg[0]] / s.U[L.mass[0]]
     assert np.max(D) >= 0.3 * (1 - 1e-9)
+
+
+def _film_state(phi, rho_l, u, e, n=6):
+    """A 1D row of one-solid cells (steel, volume fraction phi at phasic
+    density rho_l, velocity u, undistorted, undamaged) with the specific
+    internal energy set to e directly in the conserved state."""
+    c = F.uniform_case(1, (n, 1, 1), [F.STEEL_304L], [phi], [rho_l], [u], 0.0,
+                       bc="transmissive")
+    L = Layout(1, c.mats)
+    U = prim_to_cons(c.prim.copy(), L, Options(cfl=c.cfl))
+    m = U[L.mass[0]]
+    U[L.energy] = m * e + 0.5 * m * u * u
+    geom = Geometry(c.dim, c.n, c.lo, c.hi, c.bc)
+    return U, L, geom
+
+
+def test_relaxed_cold_film_takes_the_reference_density():
+    """Special case of the void relaxation: with no internal energy, no
+    distortion and no damage the steel's pressure vanishes at its reference
+    density rho0 (the cold curve's zero, where the film is unloaded), so a
+    void cell's volume fraction becomes mass / rho0, from either side of
+    rho0; mass, momentum and energy are untouched."""
+    from oracle.seeding import relax_void
+    rho0 = F.STEEL_304L["rho0"]
+    for rho_l in (0.6 * rho0, 1.7 * rho0):
+        U, L, geom = _film_state(0.004, rho_l, 120.0, 0.0)
+        out = relax_void(U, geom, L, 0.99, 1e-8)
+        m = U[L.mass[0]]
+        assert np.allclose(out[L.phi[0]] * rho0 / m, 1.0, rtol=1e-13, atol=0)
+        keep = [r for r in range(L.S) if r != L.phi[0]]
+        assert np.array_equal(out[keep], U[keep])
+
+
+def test_relaxed_film_has_zero_pressure_at_its_own_energy():
+    """The film density solves p_l(rho, e) = 0 for the cell's specific
+    internal energy: take e from the energy of the steel at zero pressure at
+    a chosen density rho* < rho0 (the inverse equation of state), relax, and
+    the film density mass / phi returns rho* (the bisection's rounding).
+    Above rho0 the cold pressure alone is positive, so an energy below the
+    cold curve (the zero-temperature bound the pressure inversion floors
+    the thermal energy at) leaves the film at rho0."""
+    from oracle.seeding import relax_void
+    from oracle.mixture import energy_from_pressure, material_terms
+    rho0 = F.STEEL_304L["rho0"]
+    for rs in (0.93 * rho0, 0.985 * rho0):
+        one = np.ones((1, 1))
+        terms = material_terms(np.full((1, 1), rs), np.zeros((1, 1)), np.zeros(1),
+                               [F.STEEL_304L], one)
+        e = float(energy_from_pressure(one, terms, np.zeros(1), [F.STEEL_304L])[0]) / rs
+        U, L, geom = _film_state(0.003, 0.8 * rho0, -40.0, e)
+        out = relax_void(U, geom, L, 0.99, 1e-8)
+        film = U[L.mass[0]] / out[L.phi[0]]
+        assert np.allclose(film, rs, rtol=1e-12, atol=0)
+    U, L, geom = _film_state(0.003, 1.2 * rho0, 5.0, -3.0e5)
+    out = relax_void(U, geom, L, 0.99, 1e-8)
+    assert np.allclose(U[L.mass[0]] / out[L.phi[0]], rho0, rtol=1e-13, atol=0)
+
+
+def test_relaxation_spares_filled_cells_and_mixtures():
+    """Only cells past the seeding threshold relax: a cell with 2% material
+    keeps its volume fraction at a threshold of 0.99, and a run with two
+    materials is left alone."""
+    from oracle.seeding import relax_void
+    rho0 = F.STEEL_304L["rho0"]
+    U, L, geom = _film_state(0.02, 1.3 * rho0, 10.0, 0.0)
+    assert np.array_equal(relax_void(U, geom, L, 0.99, 1e-8), U)
+    c = F.uniform_case(1, (4, 1, 1), [F.STEEL_304L, F.STEEL_304L], [0.002, 0.003],
+                       [rho0, rho0], [0.0], 0.0, bc="transmissive")
+    L2 = Layout(1, c.mats)
+    U2 = prim_to_cons(c.prim.copy(), L2, Options(cfl=c.cfl))
+    g2 = Geometry(c.dim, c.n, c.lo, c.hi, c.bc)
+    assert np.array_equal(relax_void(U2, g2, L2, 0.99, 1e-8), U2)
