@@ -1324,21 +1324,29 @@ struct Stage {
       double H[3][3];
       hencky<DIM, double>(V, H);
       const double J2 = J2_of<DIM, double>(H);
-      auto positive = [&](double rl) {
-        double one = 1.0;
-        Mix<1, 1, double> mr;
-        mix_terms<1, 1, double, kExt>(P, &one, &rl, D, J2, mr);
-        return mix_pressure<1, 1, double>(P, &one, mr, rl * e) > 0.0;
+      // the root in the closure precision C: float closures and 32 halvings
+      // (a bracket of 1.5 rho0 / 2^32, far below float storage) in the
+      // FP32-bulk form; in double the halvings stop once the midpoint is an
+      // end of the bracket, after which they could not move it
+      const C ec = (C)e, J2c = (C)J2;
+      C Dc[1] = {(C)D[0]};
+      auto positive = [&](C rl) {
+        C one = (C)1;
+        Mix<1, 1, C> mr;
+        mix_terms<1, 1, C, kExt>(P, &one, &rl, Dc, J2c, mr);
+        return mix_pressure<1, 1, C>(P, &one, mr, rl * ec) > (C)0;
       };
-      const double rho0 = P.mat[0].rho0;
-      double lo = 0.5 * rho0, hi = 2.0 * rho0;
+      const C rho0 = cst<C>(P.mat[0].rho0, P.mat[0].f_rho0);
+      C lo = (C)0.5 * rho0, hi = (C)2 * rho0;
       const bool slo = positive(lo);
-      for (int it = 0; it < RELAX_ITERS; ++it) {
-        const double mid = 0.5 * (lo + hi);
+      const int iters = sizeof(C) == 8 ? RELAX_ITERS : RELAX_ITERS / 2;
+      for (int it = 0; it < iters; ++it) {
+        const C mid = (C)0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
         if (positive(mid) == slo) lo = mid;
         else hi = mid;
       }
-      U[L::PHI] = m_clamp(ms / (0.5 * (lo + hi)), P.phi_floor, 1.0);
+      U[L::PHI] = m_clamp(ms / (double)((C)0.5 * (lo + hi)), P.phi_floor, 1.0);
     }
   }
 
