@@ -28,8 +28,9 @@ TOL = 1e-9
 # does not have.
 DRIVEN_RING_FP32_SKIP = ("with the void films relaxed the FP64 form runs the full cross-section "
                          "to 50 us; the FP32-bulk form trips the non-physical flag within "
-                         "its first 5 steps, also at rest without driver or seeding "
-                         "(measured; cause not found)")
+                         "its first 5 steps, also at rest without driver or seeding; "
+                         "measured to depend on U-Nb's reference density alone (steel's "
+                         "runs clean); cause not found")
 DRIVEN_RING_SKIP = ("the driven 300 x 300 x 8 slab in void goes unstable at its outer "
                     "surface even with the void films relaxed: the FP64 time step "
                     "collapses (17 us after 40000 steps), the FP32-bulk form trips "
